@@ -1,0 +1,170 @@
+/*
+ * qs_oracle.c -- plain FP64 CPU state-vector simulator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the correctness oracle for the GPU
+ * gate engine.  Only the test suite, the smoke check and the bench's CPU
+ * baseline may load it; the GPU product path never links or calls it, and it
+ * shares no code, headers or tables with that path (it parses the same circuit
+ * IR, which is plain data).
+ *
+ * What it computes: the state after applying the circuit's gate operators in
+ * order.  A gate on target set T with matrix U (2^|T| x 2^|T|) and control
+ * condition (i & cmask) == cvals is the operator that, for every index i with
+ * all target bits 0 that satisfies the control condition, replaces the 2^|T|
+ * amplitudes psi[i | bits(m)] (m = 0 .. 2^|T|-1, target T[j] holding bit j of
+ * m) by U times them, and leaves every other amplitude unchanged.  This is the
+ * paper's pair update (Alg. 1: indices i and i + 2^t, Section II-C) for a general
+ * 2x2 matrix, extended to several targets, with the control semantics of
+ * Fig. control6q2 (only amplitudes whose control bits are 1 are updated;
+ * Section III-A).
+ *
+ * Plainness rules: FP64 throughout, complex products written out as explicit
+ * real arithmetic, built with -ffp-contract=off and without fast-math, no gate
+ * fusion, no blocking.  Iterations of one gate touch disjoint amplitude groups,
+ * so the OpenMP loops give results bitwise equal to the serial loop.
+ *
+ * Layout: psi is 2^n complex numbers stored interleaved (re, im), the
+ * array-of-structures layout of Section II-A.  Qubit q is bit q of the index.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t nt;
+    int32_t t[6];
+    uint32_t flags;
+    uint64_t cmask;
+    uint64_t cvals;
+    uint64_t moff;
+    uint64_t rsv;
+} orc_op; /* 64-byte record of the circuit IR */
+
+int orc_op_size(void) { return (int)sizeof(orc_op); }
+
+void orc_init_basis(int n, double* psi, uint64_t x)
+{
+    uint64_t N = (uint64_t)1 << n;
+    memset(psi, 0, (size_t)(2 * N) * sizeof(double));
+    psi[2 * x] = 1.0;
+}
+
+/* One 1q gate.  U is 2x2 complex, row-major, interleaved (8 doubles).  Same
+ * walk as Alg. 1 (each index with the target bit 0 is the upper member of a
+ * pair whose lower member is 2^t above it), with the Hadamard's constants
+ * replaced by a general U and the control test of Fig. control6q2. */
+void orc_apply_1q(int n, double* psi, int t, const double* U, uint64_t cmask, uint64_t cvals)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int64_t half = (int64_t)1 << t;
+    const double u00r = U[0], u00i = U[1], u01r = U[2], u01i = U[3];
+    const double u10r = U[4], u10i = U[5], u11r = U[6], u11i = U[7];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        if (i & half) continue;
+        if (((uint64_t)i & cmask) != cvals) continue;
+        int64_t j = i + half;
+        double ar = psi[2 * i], ai = psi[2 * i + 1];
+        double br = psi[2 * j], bi = psi[2 * j + 1];
+        psi[2 * i]     = (u00r * ar - u00i * ai) + (u01r * br - u01i * bi);
+        psi[2 * i + 1] = (u00r * ai + u00i * ar) + (u01r * bi + u01i * br);
+        psi[2 * j]     = (u10r * ar - u10i * ai) + (u11r * br - u11i * bi);
+        psi[2 * j + 1] = (u10r * ai + u10i * ar) + (u11r * bi + u11i * br);
+    }
+}
+
+/* A gate on k = nt targets (1..6).  U is 2^k x 2^k complex, row-major. */
+void orc_apply_kq(int n, double* psi, int nt, const int32_t* t, const double* U,
+                  uint64_t cmask, uint64_t cvals)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int d = 1 << nt;
+    uint64_t tmask = 0;
+    for (int j = 0; j < nt; ++j) tmask |= (uint64_t)1 << t[j];
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        if ((uint64_t)i & tmask) continue;
+        if (((uint64_t)i & cmask) != cvals) continue;
+        int64_t idx[64];
+        double vr[64], vi[64];
+        for (int m = 0; m < d; ++m) {
+            uint64_t a = (uint64_t)i;
+            for (int j = 0; j < nt; ++j)
+                if ((m >> j) & 1) a |= (uint64_t)1 << t[j];
+            idx[m] = (int64_t)a;
+            vr[m] = psi[2 * a];
+            vi[m] = psi[2 * a + 1];
+        }
+        for (int r = 0; r < d; ++r) {
+            double sr = 0.0, si = 0.0;
+            for (int m = 0; m < d; ++m) {
+                double ur = U[2 * (r * d + m)], ui = U[2 * (r * d + m) + 1];
+                sr += ur * vr[m] - ui * vi[m];
+                si += ur * vi[m] + ui * vr[m];
+            }
+            psi[2 * idx[r]] = sr;
+            psi[2 * idx[r] + 1] = si;
+        }
+    }
+}
+
+void orc_apply_op(int n, double* psi, const orc_op* op, const double* mats)
+{
+    const double* U = mats + op->moff;
+    if (op->nt == 1)
+        orc_apply_1q(n, psi, op->t[0], U, op->cmask, op->cvals);
+    else
+        orc_apply_kq(n, psi, op->nt, op->t, U, op->cmask, op->cvals);
+}
+
+void orc_run(int n, double* psi, const orc_op* ops, int64_t nops, const double* mats)
+{
+    for (int64_t g = 0; g < nops; ++g) orc_apply_op(n, psi, &ops[g], mats);
+}
+
+/* Neumaier compensated sum step. */
+static inline void nsum(double* s, double* c, double x)
+{
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x))
+        *c += (*s - t) + x;
+    else
+        *c += (x - t) + *s;
+    *s = t;
+}
+
+/* Marginal probabilities: out[o] = sum of |psi_i|^2 over i whose bits at
+ * qubits[0..m) spell o (qubits[0] is bit 0 of o).  Serial, compensated. */
+void orc_probabilities(int n, const double* psi, const int32_t* qubits, int m, double* out)
+{
+    const int64_t N = (int64_t)1 << n;
+    const int64_t M = (int64_t)1 << m;
+    double* comp = (double*)calloc((size_t)M, sizeof(double));
+    for (int64_t o = 0; o < M; ++o) out[o] = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        int64_t o = 0;
+        for (int j = 0; j < m; ++j) o |= (((i >> qubits[j]) & 1) << j);
+        double p = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        nsum(&out[o], &comp[o], p);
+    }
+    for (int64_t o = 0; o < M; ++o) out[o] += comp[o];
+    free(comp);
+}
+
+double orc_norm2(int n, const double* psi)
+{
+    double out;
+    orc_probabilities(n, psi, NULL, 0, &out);
+    return out;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
