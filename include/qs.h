@@ -1,0 +1,216 @@
+/*
+ * qs.h -- C ABI of the gfx950 state-vector gate engine (libqs.so).
+ *
+ * The engine applies gate matrices to a 2^n-amplitude complex state held in
+ * device memory, the core operation of full state-vector simulation (the
+ * paper's Section I; its kernels are the pair update of Alg. 1 and Alg. 9).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - State layout: 2^n complex amplitudes, interleaved (re, im) -- the
+ *   array-of-structures layout of Section II-A.  QS_C128 stores two doubles
+ *   (16 B) per amplitude, QS_C64 two floats (8 B).  The base address must be
+ *   256-byte aligned.  This is exactly torch.complex128 / torch.complex64.
+ * - Qubit q is bit q of the amplitude index.  A 1q gate on target t pairs
+ *   index i (bit t clear) with i + 2^t (Alg. 1, Section II-C).
+ * - Matrices are always FP64 at the ABI: 2^k x 2^k complex, row-major,
+ *   interleaved (re, im).  For a gate on targets t[0..k), t[j] is bit j of the
+ *   matrix row/column index (t[0] is the least significant).  For QS_C64 states
+ *   the library rounds matrices (and any fused products, formed in FP64) to
+ *   FP32 once.
+ * - Controls are a bitmask ctrl_mask with required values ctrl_vals (a subset
+ *   of ctrl_mask; ctrl_vals == ctrl_mask means "control on 1").  A controlled
+ *   gate updates only the amplitudes whose control bits match and leaves all
+ *   others bitwise unchanged (Fig. control6q2, Section III-A).
+ * - Ownership: the caller keeps every pointer it passes; matrices and op
+ *   tables are copied before the call returns, so they may be freed at once.
+ * - Asynchrony: qs_apply_* / qs_run_circuit / qs_init_basis enqueue work on the
+ *   state's HIP stream and return.  qs_download, qs_probabilities, qs_norm and
+ *   qs_sync block until the result is on the host.
+ * - Errors: every call returns a qs_status; nothing aborts.  On QS_ERR_ARG the
+ *   state is untouched.  A failing HIP call marks the state failed and every
+ *   later call on it returns QS_ERR_DEVICE.  qs_last_error() gives a
+ *   thread-local message for the last failure on the calling thread.
+ * - Threads: one handle must not be used from two threads at once; distinct
+ *   handles are independent.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QS_OK = 0,
+    QS_ERR_ARG = 1,         /* invalid argument; nothing was changed */
+    QS_ERR_OOM = 2,         /* device memory (or the configured budget) exhausted */
+    QS_ERR_DEVICE = 3,      /* a HIP call failed; the handle is now failed */
+    QS_ERR_BUSY = 4,        /* resource in use (e.g. batch not finished) */
+    QS_ERR_UNSUPPORTED = 5, /* valid request this build does not handle */
+    QS_ERR_CANCELLED = 6,
+    QS_ERR_TIMEOUT = 7
+} qs_status;
+
+typedef enum { QS_C64 = 1, QS_C128 = 2 } qs_dtype;
+
+#define QS_MAX_QUBITS 34   /* 2^34 complex64 amplitudes = 128 GiB */
+#define QS_MAX_FUSED 6     /* largest k accepted by qs_apply_fused */
+
+typedef struct qs_state_s* qs_state;
+
+/* One gate of a circuit (64 bytes).  nt targets in t[0..nt) (t[0] is the least
+ * significant bit of the matrix index), unused t[] entries are -1; controls as
+ * described above; moff = offset, in doubles, of the gate's 2^nt x 2^nt complex
+ * matrix inside the circuit's matrix pool. */
+typedef struct {
+    int32_t nt;
+    int32_t t[6];
+    uint32_t flags; /* must be 0 */
+    uint64_t cmask;
+    uint64_t cvals;
+    uint64_t moff;
+    uint64_t rsv; /* must be 0 */
+} qs_op;
+
+/* ------------------------------------------------------------------ basics */
+
+/* Library version, (major << 16) | minor. */
+int qs_version(void);
+
+/* Message for the last failing call on this thread ("" if none).  The pointer
+ * stays valid until the next qs_* call on the same thread. */
+const char* qs_last_error(void);
+
+/* Number of HIP devices visible (0 if none); never fails. */
+int qs_device_count(void);
+
+/* ------------------------------------------------------------------ states */
+
+/* Allocate a state of n qubits (1 <= n <= QS_MAX_QUBITS) on the current HIP
+ * device, initialised to |0..0>, with a library-created stream.  The library
+ * owns the memory; qs_destroy frees it.  QS_ERR_OOM if it does not fit. */
+qs_status qs_create(int n, qs_dtype dt, qs_state* out);
+
+/* Wrap caller-owned device memory (e.g. a torch tensor's data_ptr) of `bytes`
+ * bytes (>= 2^n * amplitude size, 256-byte aligned) as a state.  Contents are
+ * used as they are.  `stream` is a hipStream_t (NULL = the null stream) on
+ * which all of the state's work is enqueued.  qs_destroy does not free it. */
+qs_status qs_create_external(int n, qs_dtype dt, void* dev_ptr, uint64_t bytes,
+                             void* stream, qs_state* out);
+
+/* Release the handle (waits for its pending work first).  NULL is accepted. */
+qs_status qs_destroy(qs_state s);
+
+/* Change the stream later work is enqueued on.  Work already enqueued on the
+ * previous stream is ordered before new work (the library waits on it). */
+qs_status qs_set_stream(qs_state s, void* stream);
+
+/* Report n, dtype and the device pointer of the amplitudes. */
+qs_status qs_get_info(qs_state s, int* n, int* dtype, void** dev_ptr);
+
+/* Set the state to the basis state |x> (x < 2^n). */
+qs_status qs_init_basis(qs_state s, uint64_t x);
+
+/* Copy `count` amplitudes between host memory and amplitudes
+ * [first, first + count) of the state.  The host buffer uses the state's own
+ * element type (complex64 or complex128).  qs_upload is stream-ordered and
+ * returns once the host buffer may be reused; qs_download blocks until the
+ * data is on the host. */
+qs_status qs_upload(qs_state s, const void* host, uint64_t first, uint64_t count);
+qs_status qs_download(qs_state s, void* host, uint64_t first, uint64_t count);
+
+/* ------------------------------------------------------------------ gates */
+
+/* 1q gate: U is 2x2 complex (8 doubles).  Target and control qubits must be
+ * distinct and < n; ctrl_vals must be a subset of ctrl_mask.  Pair update of
+ * Alg. 1 with a general matrix, restricted to matching controls. */
+qs_status qs_apply_1q(qs_state s, int target, const double* U,
+                      uint64_t ctrl_mask, uint64_t ctrl_vals);
+
+/* 2q gate on (t0, t1), t0 the least significant bit of the 4x4 matrix index:
+ * for every index i with both target bits clear (and matching controls) the
+ * quad psi[i + b0*2^t0 + b1*2^t1] (m = b0 + 2 b1) is replaced by U times it.
+ * U is 4x4 complex (32 doubles). */
+qs_status qs_apply_2q(qs_state s, int t0, int t1, const double* U,
+                      uint64_t ctrl_mask, uint64_t ctrl_vals);
+
+/* Dense gate on k distinct targets (1 <= k <= QS_MAX_FUSED), U 2^k x 2^k
+ * complex: the same update for groups of 2^k amplitudes.  Typically U is the
+ * product of several gates formed by the caller or by the planner (gate fusion,
+ * Section I). */
+qs_status qs_apply_fused(qs_state s, const int* targets, int k, const double* U,
+                         uint64_t ctrl_mask, uint64_t ctrl_vals);
+
+/* Execution options for qs_run_circuit.  Zero-initialised means defaults. */
+typedef struct {
+    int32_t mode;        /* 0 = auto (fused tile passes), 1 = one launch per gate */
+    int32_t fuse_k;      /* max qubits of a fused dense block; 0 = default */
+    int32_t tile_qubits; /* qubits held in LDS per tile; 0 = default */
+    int32_t rsv[5];
+} qs_run_opts;
+
+/* Apply a whole circuit (ops[0..n_ops), matrices in mats[0..n_mats)) in
+ * order.  The result equals applying the gates one by one up to rounding; the
+ * library may group gates into LDS tile passes and fused dense blocks.  The op
+ * table and matrices are validated and copied before any work is enqueued. */
+qs_status qs_run_circuit(qs_state s, const qs_op* ops, int64_t n_ops,
+                         const double* mats, int64_t n_mats, const qs_run_opts* opts);
+
+/* Plan a circuit for an n-qubit state of type dt without executing it (host
+ * only; needs no GPU).  *n_passes receives the number of LDS tile passes
+ * (state read+write sweeps) qs_run_circuit would launch in mode 0, and
+ * *n_ops_out the total operations inside them.  Same validation as
+ * qs_run_circuit. */
+qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                          int64_t n_mats, const qs_run_opts* opts, int64_t* n_passes, int64_t* n_ops_out);
+
+/* ------------------------------------------------------------------ reductions */
+
+/* Marginal probabilities over m distinct qubits (0 <= m <= 24): out[o] (2^m
+ * doubles, host memory) = sum of |psi_i|^2 over indices i whose bits at
+ * qubits[0..m) spell o (qubits[0] is bit 0 of o).  Accumulated in FP64 in a
+ * fixed order, so repeated calls give bitwise equal results.  Blocking. */
+qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out);
+
+/* Squared norm sum |psi_i|^2 in FP64 (the m = 0 case).  Blocking. */
+qs_status qs_norm(qs_state s, double* out);
+
+/* Wait for all work enqueued on the state. */
+qs_status qs_sync(qs_state s);
+
+/* ------------------------------------------------------------------ tracing */
+
+/* One traced kernel launch. */
+typedef struct {
+    int32_t kind;       /* QS_K_* below */
+    int32_t n;
+    int32_t t0, t1;     /* first two targets (-1 if unused) */
+    int32_t nctrl;
+    int32_t dtype;
+    uint64_t bytes;     /* algorithmic HBM bytes: 2 * S * amplitudes touched */
+    uint64_t updates;   /* amplitude updates credited to the launch */
+    float ms;           /* duration between HIP events around the launch */
+    int32_t rsv;
+} qs_trace_rec;
+
+enum {
+    QS_K_INIT = 0, QS_K_1Q_HI = 1, QS_K_1Q_LO = 2, QS_K_2Q = 3, QS_K_KQ = 4,
+    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7
+};
+
+/* Start (on != 0) or stop recording HIP events around every launch on the
+ * state's stream.  Starting clears earlier records. */
+qs_status qs_trace_enable(qs_state s, int on);
+
+/* Wait for traced work and copy up to `max` records; *count = records copied. */
+qs_status qs_trace_read(qs_state s, qs_trace_rec* out, int max, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

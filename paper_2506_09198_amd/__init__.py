@@ -1,0 +1,329 @@
+"""Python binding of libqs.so, the gfx950 state-vector gate engine.
+
+Argument marshalling only: every step runs in the library's HIP kernels.  The
+functions carry the C ABI's names (``include/qs.h``) and raise ``QSError`` on
+any status other than QS_OK.  Importing this package fails loudly if
+``libqs.so`` has not been built (``python -m paper_2506_09198_amd._build``).
+
+PyTorch is optional plumbing: ``State.from_torch`` wraps a torch complex tensor's
+device memory and current stream so kernels run on torch's stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqs.so")
+
+QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_DEVICE, QS_ERR_BUSY, QS_ERR_UNSUPPORTED, QS_ERR_CANCELLED, \
+    QS_ERR_TIMEOUT = range(8)
+QS_C64, QS_C128 = 1, 2
+QS_MAX_QUBITS = 34
+QS_MAX_FUSED = 6
+KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce"}
+
+TRACE_DTYPE = np.dtype([("kind", "<i4"), ("n", "<i4"), ("t0", "<i4"), ("t1", "<i4"), ("nctrl", "<i4"),
+                        ("dtype", "<i4"), ("bytes", "<u8"), ("updates", "<u8"), ("ms", "<f4"),
+                        ("rsv", "<i4")])
+assert TRACE_DTYPE.itemsize == 48
+
+
+class QSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qs status {status}: {msg}")
+        self.status = status
+
+
+class _RunOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
+                ("rsv", ctypes.c_int32 * 5)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_09198_amd._build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32, dp = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "qs_version": ([], ctypes.c_int),
+        "qs_last_error": ([], ctypes.c_char_p),
+        "qs_device_count": ([], ctypes.c_int),
+        "qs_create": ([i32, i32, ctypes.POINTER(vp)], i32),
+        "qs_create_external": ([i32, i32, vp, u64, vp, ctypes.POINTER(vp)], i32),
+        "qs_destroy": ([vp], i32),
+        "qs_set_stream": ([vp, vp], i32),
+        "qs_get_info": ([vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(vp)], i32),
+        "qs_init_basis": ([vp, u64], i32),
+        "qs_upload": ([vp, vp, u64, u64], i32),
+        "qs_download": ([vp, vp, u64, u64], i32),
+        "qs_apply_1q": ([vp, i32, dp, u64, u64], i32),
+        "qs_apply_2q": ([vp, i32, i32, dp, u64, u64], i32),
+        "qs_apply_fused": ([vp, ctypes.POINTER(i32), i32, dp, u64, u64], i32),
+        "qs_run_circuit": ([vp, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts)], i32),
+        "qs_plan_circuit": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
+                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
+        "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
+        "qs_norm": ([vp, dp], i32),
+        "qs_sync": ([vp], i32),
+        "qs_trace_enable": ([vp, i32], i32),
+        "qs_trace_read": ([vp, vp, i32, ctypes.POINTER(i32)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != QS_OK:
+        raise QSError(st, lib.qs_last_error().decode(errors="replace"))
+
+
+def _mask(c) -> int:
+    if c is None:
+        return 0
+    if isinstance(c, (int, np.integer)):
+        return int(c)
+    m = 0
+    for q in c:
+        m |= 1 << int(q)
+    return m
+
+
+def _mat(U, k: int):
+    a = np.ascontiguousarray(U, dtype=np.complex128)
+    if a.shape != (1 << k, 1 << k):
+        raise ValueError(f"matrix shape {a.shape} != {(1 << k, 1 << k)}")
+    f = a.view(np.float64).ravel()
+    return f, f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _np_dtype(dt: int):
+    return np.complex128 if dt == QS_C128 else np.complex64
+
+
+# ------------------------------------------------------------------ ABI calls
+
+def qs_version() -> int:
+    return lib.qs_version()
+
+
+def qs_last_error() -> str:
+    return lib.qs_last_error().decode(errors="replace")
+
+
+def qs_device_count() -> int:
+    return lib.qs_device_count()
+
+
+def qs_create(n: int, dtype: int = QS_C128) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.qs_create(n, dtype, ctypes.byref(h)))
+    return h.value
+
+
+def qs_create_external(n: int, dtype: int, dev_ptr: int, nbytes: int, stream: int | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.qs_create_external(n, dtype, ctypes.c_void_p(dev_ptr), nbytes, ctypes.c_void_p(stream or 0),
+                                  ctypes.byref(h)))
+    return h.value
+
+
+def qs_destroy(s: int):
+    _check(lib.qs_destroy(ctypes.c_void_p(s)))
+
+
+def qs_set_stream(s: int, stream: int | None):
+    _check(lib.qs_set_stream(ctypes.c_void_p(s), ctypes.c_void_p(stream or 0)))
+
+
+def qs_get_info(s: int):
+    n, dt, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_void_p()
+    _check(lib.qs_get_info(ctypes.c_void_p(s), ctypes.byref(n), ctypes.byref(dt), ctypes.byref(p)))
+    return n.value, dt.value, p.value
+
+
+def qs_init_basis(s: int, x: int):
+    _check(lib.qs_init_basis(ctypes.c_void_p(s), int(x)))
+
+
+def qs_upload(s: int, host: np.ndarray, first: int = 0):
+    n, dt, _ = qs_get_info(s)
+    a = np.ascontiguousarray(host, dtype=_np_dtype(dt))
+    _check(lib.qs_upload(ctypes.c_void_p(s), ctypes.c_void_p(a.ctypes.data), first, a.size))
+
+
+def qs_download(s: int, first: int = 0, count: int | None = None) -> np.ndarray:
+    n, dt, _ = qs_get_info(s)
+    if count is None:
+        count = (1 << n) - first
+    out = np.empty(count, dtype=_np_dtype(dt))
+    _check(lib.qs_download(ctypes.c_void_p(s), ctypes.c_void_p(out.ctypes.data), first, count))
+    return out
+
+
+def qs_apply_1q(s: int, target: int, U, ctrl_mask=0, ctrl_vals=None):
+    cm = _mask(ctrl_mask)
+    cv = cm if ctrl_vals is None else _mask(ctrl_vals)
+    f, p = _mat(U, 1)
+    _check(lib.qs_apply_1q(ctypes.c_void_p(s), int(target), p, cm, cv))
+
+
+def qs_apply_2q(s: int, t0: int, t1: int, U, ctrl_mask=0, ctrl_vals=None):
+    cm = _mask(ctrl_mask)
+    cv = cm if ctrl_vals is None else _mask(ctrl_vals)
+    f, p = _mat(U, 2)
+    _check(lib.qs_apply_2q(ctypes.c_void_p(s), int(t0), int(t1), p, cm, cv))
+
+
+def qs_apply_fused(s: int, targets, U, ctrl_mask=0, ctrl_vals=None):
+    t = np.ascontiguousarray(list(targets), dtype=np.int32)
+    cm = _mask(ctrl_mask)
+    cv = cm if ctrl_vals is None else _mask(ctrl_vals)
+    f, p = _mat(U, len(t))
+    _check(lib.qs_apply_fused(ctypes.c_void_p(s), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(t), p,
+                              cm, cv))
+
+
+def qs_run_circuit(s: int, ops: np.ndarray, mats: np.ndarray, mode: int = 0, fuse_k: int = 0,
+                   tile_qubits: int = 0):
+    ops = np.ascontiguousarray(ops)
+    if ops.dtype.itemsize != 64:
+        raise ValueError("ops must be 64-byte records (workloads.OP_DTYPE)")
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    o = _RunOpts(mode, fuse_k, tile_qubits)
+    _check(lib.qs_run_circuit(ctypes.c_void_p(s), ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
+                              mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o)))
+
+
+def qs_plan_circuit(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, mode: int = 0, fuse_k: int = 0,
+                    tile_qubits: int = 0):
+    """Host-only planning: returns (passes, ops inside passes)."""
+    ops = np.ascontiguousarray(ops)
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    o = _RunOpts(mode, fuse_k, tile_qubits)
+    npass, nops = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.qs_plan_circuit(n, dtype, ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
+                               mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o),
+                               ctypes.byref(npass), ctypes.byref(nops)))
+    return npass.value, nops.value
+
+
+def qs_probabilities(s: int, qubits) -> np.ndarray:
+    q = np.ascontiguousarray(list(qubits), dtype=np.int32)
+    out = np.empty(1 << len(q), dtype=np.float64)
+    _check(lib.qs_probabilities(ctypes.c_void_p(s), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(q),
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def qs_norm(s: int) -> float:
+    v = ctypes.c_double()
+    _check(lib.qs_norm(ctypes.c_void_p(s), ctypes.byref(v)))
+    return v.value
+
+
+def qs_sync(s: int):
+    _check(lib.qs_sync(ctypes.c_void_p(s)))
+
+
+def qs_trace_enable(s: int, on: bool = True):
+    _check(lib.qs_trace_enable(ctypes.c_void_p(s), 1 if on else 0))
+
+
+def qs_trace_read(s: int, max_records: int = 1 << 16) -> np.ndarray:
+    out = np.zeros(max_records, dtype=TRACE_DTYPE)
+    c = ctypes.c_int()
+    _check(lib.qs_trace_read(ctypes.c_void_p(s), ctypes.c_void_p(out.ctypes.data), max_records, ctypes.byref(c)))
+    return out[: c.value]
+
+
+# ------------------------------------------------------------------ convenience
+
+class State:
+    """Owning wrapper around a qs_state handle."""
+
+    def __init__(self, handle: int, tensor=None):
+        self.h = handle
+        self.tensor = tensor  # keeps torch-owned memory alive
+        self.n, self.dtype, self.ptr = qs_get_info(handle)
+
+    @classmethod
+    def create(cls, n: int, dtype: int = QS_C128) -> "State":
+        return cls(qs_create(n, dtype))
+
+    @classmethod
+    def from_torch(cls, tensor, stream=None) -> "State":
+        import torch
+
+        if tensor.dtype == torch.complex128:
+            dt = QS_C128
+        elif tensor.dtype == torch.complex64:
+            dt = QS_C64
+        else:
+            raise TypeError("state tensor must be complex64 or complex128")
+        n = int(tensor.numel()).bit_length() - 1
+        if tensor.numel() != 1 << n or not tensor.is_contiguous() or not tensor.is_cuda:
+            raise ValueError("need a contiguous CUDA tensor with 2^n elements")
+        if stream is None:
+            stream = torch.cuda.current_stream(tensor.device).cuda_stream
+        nbytes = tensor.numel() * tensor.element_size()
+        return cls(qs_create_external(n, dt, tensor.data_ptr(), nbytes, stream), tensor)
+
+    def close(self):
+        if self.h:
+            qs_destroy(self.h)
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def apply_1q(self, t, U, controls=0, cvals=None):
+        qs_apply_1q(self.h, t, U, controls, cvals)
+
+    def apply_2q(self, t0, t1, U, controls=0, cvals=None):
+        qs_apply_2q(self.h, t0, t1, U, controls, cvals)
+
+    def apply_fused(self, targets, U, controls=0, cvals=None):
+        qs_apply_fused(self.h, targets, U, controls, cvals)
+
+    def run(self, ops, mats, **kw):
+        qs_run_circuit(self.h, ops, mats, **kw)
+
+    def run_circuit(self, circ, **kw):
+        ops, mats = circ.arrays()
+        qs_run_circuit(self.h, ops, mats, **kw)
+
+    def init_basis(self, x=0):
+        qs_init_basis(self.h, x)
+
+    def upload(self, host, first=0):
+        qs_upload(self.h, host, first)
+
+    def download(self, first=0, count=None):
+        return qs_download(self.h, first, count)
+
+    def probabilities(self, qubits):
+        return qs_probabilities(self.h, qubits)
+
+    def norm(self):
+        return qs_norm(self.h)
+
+    def sync(self):
+        qs_sync(self.h)

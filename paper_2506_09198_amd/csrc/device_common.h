@@ -1,0 +1,48 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+
+#include "qs_internal.h"
+
+namespace qs {
+
+template <typename R> struct CT;
+template <> struct CT<double> { using V = double2; };
+template <> struct CT<float> { using V = float2; };
+
+// Insert a zero bit at every position listed in `p` (ascending), turning a
+// compact counter into an amplitude index.
+__device__ __forceinline__ uint64_t ins_bits(uint64_t k, const InsertPlan& p)
+{
+    for (int j = 0; j < p.n; ++j) {
+        const uint64_t lo = p.low[j];
+        k = (k & lo) | ((k & ~lo) << 1);
+    }
+    return k;
+}
+
+__device__ __forceinline__ uint32_t ins0_32(uint32_t k, int p)
+{
+    const uint32_t lo = (1u << p) - 1;
+    return (k & lo) | ((k & ~lo) << 1);
+}
+
+// a*x + b*y for complex scalars a=(ar,ai), b=(br,bi) and complex vectors x, y.
+template <typename V, typename R>
+__device__ __forceinline__ V cmad2(R ar, R ai, V x, R br, R bi, V y)
+{
+    V r;
+    r.x = ar * x.x - ai * x.y + br * y.x - bi * y.y;
+    r.y = ar * x.y + ai * x.x + br * y.y + bi * y.x;
+    return r;
+}
+
+template <typename V, typename R>
+__device__ __forceinline__ V cmul(R ar, R ai, V x)
+{
+    V r;
+    r.x = ar * x.x - ai * x.y;
+    r.y = ar * x.y + ai * x.x;
+    return r;
+}
+
+} // namespace qs

@@ -1,0 +1,55 @@
+// Internal declarations shared by the runtime (qs_api.cpp, planner.cpp) and
+// the kernel translation units (*.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qs.h"
+
+namespace qs {
+
+// Zero bits inserted into a compact counter to form an amplitude index.  For
+// sorted positions p_0 < p_1 < ..., inserting in ascending order turns the
+// counter k (over the remaining bits) into the index with 0 at every p_j; the
+// same walk as Alg. 1's block/offset split, for any number of fixed bits.
+constexpr int kMaxIns = 36;
+struct InsertPlan {
+    int32_t n = 0;
+    int32_t pad = 0;
+    uint64_t low[kMaxIns]; // (1 << p_j) - 1, ascending
+};
+
+InsertPlan make_insert_plan(uint64_t positions_mask);
+
+// Tile pass description (LDS-resident tiles of 2^m amplitudes).  Defined in
+// tile.hip, built by the planner.
+struct TileGate;
+struct TilePass;
+
+// Kernel launchers.  All return hipSuccess or the launch error; `kind`
+// receives the QS_K_* class actually used (for tracing).
+hipError_t launch_init_basis(void* psi, int dt, int n, uint64_t x, hipStream_t st);
+hipError_t launch_apply_1q(void* psi, int dt, int n, int t, const double* U, uint64_t cm,
+                           uint64_t cv, hipStream_t st, int* kind);
+hipError_t launch_apply_2q(void* psi, int dt, int n, int t0, int t1, const double* U,
+                           uint64_t cm, uint64_t cv, hipStream_t st, int* kind);
+// Dense k-qubit gate; Ud is a device copy of U in the state's element type.
+hipError_t launch_apply_kq_dev(void* psi, int dt, int n, const int* targets, int k, const void* Ud,
+                               uint64_t cm, uint64_t cv, hipStream_t st, int* kind);
+
+// Reductions.  `part` is device scratch of at least reduce_scratch_doubles()
+// doubles.  Results land in `dev_out` (device, 2^m doubles).
+uint64_t reduce_scratch_doubles(int n, int m);
+hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m,
+                                double* part, double* dev_out, hipStream_t st);
+
+// Environment-tunable launch knobs (read once).
+int env_int(const char* name, int dflt);
+
+inline size_t amp_bytes(int dt) { return dt == QS_C128 ? 16 : 8; }
+
+} // namespace qs

@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+the header declares, rejects bad arguments before touching the device, and the
+host-side planner groups gates as designed."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def qs():
+    lib = os.path.join(ROOT, "paper_2506_09198_amd", "libqs.so")
+    if not os.path.exists(lib):
+        from paper_2506_09198_amd import _build
+
+        _build.build()
+    import paper_2506_09198_amd as qs
+
+    return qs
+
+
+def _declared_functions():
+    hdr = open(os.path.join(ROOT, "include", "qs.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(qs_[a-z0-9_]+)\s*\(", hdr)))
+
+
+def test_exports_every_declared_symbol(qs):
+    names = _declared_functions()
+    assert len(names) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", qs.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (qs_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(qs, n), n  # the binding carries the same names
+
+
+def test_version_and_errors(qs):
+    assert qs.qs_version() >= 1
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_create(0, qs.QS_C128)
+    assert e.value.status == qs.QS_ERR_ARG and "outside" in qs.qs_last_error()
+    for bad in (-1, 35, 64):
+        with pytest.raises(qs.QSError) as e:
+            qs.qs_create(bad, qs.QS_C64)
+        assert e.value.status == qs.QS_ERR_ARG
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_create(4, 7)
+    assert e.value.status == qs.QS_ERR_ARG
+
+
+def test_null_handle_rejected(qs):
+    for call in (lambda: qs.qs_apply_1q(0, 0, np.eye(2)), lambda: qs.qs_norm(0), lambda: qs.qs_sync(0),
+                 lambda: qs.qs_init_basis(0, 0)):
+        with pytest.raises(qs.QSError) as e:
+            call()
+        assert e.value.status == qs.QS_ERR_ARG
+    qs.qs_destroy(0)  # NULL is accepted
+
+
+def test_create_without_device_reports_device_error(qs):
+    if qs.qs_device_count() > 0:
+        pytest.skip("a GPU is visible")
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_create(4, qs.QS_C128)
+    assert e.value.status == qs.QS_ERR_DEVICE
+
+
+def test_plan_validation(qs):
+    c = W.Circuit(4).g1(0, W.H).g2(1, 2, W.SWAP)
+    ops, mats = c.arrays()
+    bad = ops.copy()
+    bad[0]["t"][0] = 4
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(4, qs.QS_C128, bad, mats)
+    bad = ops.copy()
+    bad[1]["t"][1] = 1  # duplicate target
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(4, qs.QS_C128, bad, mats)
+    bad = ops.copy()
+    bad[0]["cmask"] = 1  # control equals target
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(4, qs.QS_C128, bad, mats)
+    bad = ops.copy()
+    bad[0]["cmask"] = 2
+    bad[0]["cvals"] = 4  # value outside mask
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(4, qs.QS_C128, bad, mats)
+    bad = ops.copy()
+    bad[1]["moff"] = mats.size  # matrix out of the pool
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(4, qs.QS_C128, bad, mats)
+
+
+def test_planner_groups_gates(qs):
+    # every gate inside the tile: one pass
+    c = W.random_u3_cnot(10, 200, seed=2)
+    ops, mats = c.arrays()
+    assert qs.qs_plan_circuit(10, qs.QS_C128, ops, mats, tile_qubits=10) == (1, len(ops))
+    # diagonal gates never force a new pass
+    q = W.qft(24)
+    ops, mats = q.arrays()
+    npass, nops = qs.qs_plan_circuit(24, qs.QS_C128, ops, mats, tile_qubits=11)
+    assert nops == len(ops)
+    n_dense = 24 + 12  # Hadamards and swaps
+    assert npass < n_dense // 2
+    # per-gate mode is not planned into tiles but validates the same way
+    r = W.rqc_chain(32, 20, 5)
+    ops, mats = r.arrays()
+    npass, nops = qs.qs_plan_circuit(32, qs.QS_C64, ops, mats, tile_qubits=12)
+    assert nops == len(ops) and npass <= 20 * 6
