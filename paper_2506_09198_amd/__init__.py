@@ -43,6 +43,14 @@ class _RunOpts(ctypes.Structure):
 
 
 def _load():
+    # PyTorch-ROCm ships its own HIP runtime under the same soname
+    # (libamdhip64.so.7).  The first one loaded serves the whole process, so
+    # when torch is installed it is imported first: libqs then binds to the
+    # runtime torch uses and both share one device context.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2506_09198_amd._build`")
     L = ctypes.CDLL(LIB_PATH)

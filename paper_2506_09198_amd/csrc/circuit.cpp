@@ -33,10 +33,10 @@ qs_status run_per_gate(qs_state s, const qs_op* ops, int64_t n_ops, const double
     bool need_pool = false;
     for (int64_t g = 0; g < n_ops; ++g) need_pool |= ops[g].nt > 2;
     if (need_pool) {
-        qs_status st = stage_matrices(s, mats, (uint64_t)n_mats, &dpool);
+        qs_status st = stage_bytes(s, mats, (uint64_t)n_mats * sizeof(double), &dpool);
         if (st != QS_OK) return st;
     }
-    const size_t es = s->dt == QS_C128 ? sizeof(double) : sizeof(float);
+    const size_t es = sizeof(double);
     for (int64_t g = 0; g < n_ops; ++g) {
         const qs_op& o = ops[g];
         const double* U = mats + o.moff;

@@ -45,4 +45,14 @@ __device__ __forceinline__ V cmul(R ar, R ai, V x)
     return r;
 }
 
+// Amplitudes are stored as R (float or double) but every gate is computed in
+// FP64 with FP64 matrices: a complex64 state is rounded once per stored
+// result, and gate matrices are never rounded to FP32 (rounding 1/sqrt2 to FP32
+// would shrink the norm by the same factor at every Hadamard).
+__device__ __forceinline__ double2 ld2(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 ld2(double2 v) { return v; }
+template <typename V> __device__ __forceinline__ V st2(double2 v);
+template <> __device__ __forceinline__ float2 st2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ __forceinline__ double2 st2<double2>(double2 v) { return v; }
+
 } // namespace qs

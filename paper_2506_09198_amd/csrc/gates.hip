@@ -19,8 +19,8 @@
 
 namespace qs {
 
-template <typename R> struct M2 { R m[8]; };
-template <typename R> struct M4 { R m[32]; };
+struct M2 { double m[8]; };
+struct M4 { double m[32]; };
 
 InsertPlan make_insert_plan(uint64_t mask)
 {
@@ -75,7 +75,7 @@ hipError_t launch_init_basis(void* psi, int dt, int n, uint64_t x, hipStream_t s
 template <typename R, int PPL>
 __global__ void __launch_bounds__(256)
 k_1q_pairs(typename CT<R>::V* __restrict__ psi, uint64_t npairs, uint64_t half, uint64_t cvals,
-           InsertPlan ip, M2<R> u)
+           InsertPlan ip, M2 u)
 {
     using V = typename CT<R>::V;
     const uint64_t stride = (uint64_t)gridDim.x * (256 * PPL);
@@ -95,8 +95,9 @@ k_1q_pairs(typename CT<R>::V* __restrict__ psi, uint64_t npairs, uint64_t half, 
         for (int p = 0; p < PPL; ++p) {
             const uint64_t k = k0 + (uint64_t)p * 256;
             if (k < npairs) {
-                psi[ia[p]] = cmad2<V, R>(u.m[0], u.m[1], a[p], u.m[2], u.m[3], b[p]);
-                psi[ia[p] + half] = cmad2<V, R>(u.m[4], u.m[5], a[p], u.m[6], u.m[7], b[p]);
+                const double2 x = ld2(a[p]), y = ld2(b[p]);
+                psi[ia[p]] = st2<V>(cmad2<double2, double>(u.m[0], u.m[1], x, u.m[2], u.m[3], y));
+                psi[ia[p] + half] = st2<V>(cmad2<double2, double>(u.m[4], u.m[5], x, u.m[6], u.m[7], y));
             }
         }
     }
@@ -113,11 +114,24 @@ __device__ __forceinline__ V shfl_xor_v(V v, int d)
     return r;
 }
 
+template <int A, int D>
+__device__ __forceinline__ void inlane_pairs(const double2 (&x)[A], double2 (&y)[A], const M2& u)
+{
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+        if (j & D) continue;
+        if (j + D >= A) continue;
+        const double2 a = x[j], b = x[j + D];
+        y[j] = cmad2<double2, double>(u.m[0], u.m[1], a, u.m[2], u.m[3], b);
+        y[j + D] = cmad2<double2, double>(u.m[4], u.m[5], a, u.m[6], u.m[7], b);
+    }
+}
+
 // A amplitudes per lane (LA = log2 A); a wave covers W = 6 + LA index bits.
 template <typename R, int LA>
 __global__ void __launch_bounds__(256)
 k_1q_wave(typename CT<R>::V* __restrict__ psi, uint64_t nchunks, uint64_t namps, int t,
-          uint64_t cm_lo, uint64_t cv_lo, uint64_t cv_hi, InsertPlan ip_hi, M2<R> u)
+          uint64_t cm_lo, uint64_t cv_lo, uint64_t cv_hi, InsertPlan ip_hi, M2 u)
 {
     using V = typename CT<R>::V;
     constexpr int A = 1 << LA;
@@ -126,41 +140,39 @@ k_1q_wave(typename CT<R>::V* __restrict__ psi, uint64_t nchunks, uint64_t namps,
     const uint64_t nw = (uint64_t)gridDim.x * 4;
     for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nchunks; c += nw) {
         const uint64_t i0 = ((ins_bits(c, ip_hi) << W) | cv_hi) + (uint64_t)lane * A;
-        V x[A], y[A];
+        double2 x[A], y[A];
 #pragma unroll
         for (int j = 0; j < A; ++j) {
             if (i0 + j < namps) {
-                x[j] = psi[i0 + j];
+                x[j] = ld2(psi[i0 + j]);
             } else {
                 x[j].x = 0;
                 x[j].y = 0;
             }
         }
         if (t < LA) {
-            const int d = 1 << t;
-#pragma unroll
-            for (int j = 0; j < A; ++j) {
-                if (j & d) continue;
-                const V a = x[j], b = x[j + d];
-                y[j] = cmad2<V, R>(u.m[0], u.m[1], a, u.m[2], u.m[3], b);
-                y[j + d] = cmad2<V, R>(u.m[4], u.m[5], a, u.m[6], u.m[7], b);
-            }
+            // partner in the lane's own registers; t is 0 or 1, unrolled
+            // separately so every register index is a constant
+            if (t == 0)
+                inlane_pairs<A, 1>(x, y, u);
+            else
+                inlane_pairs<A, 2>(x, y, u);
         } else {
             const int d = 1 << (t - LA);
             const bool upper = (lane & d) == 0;
             // upper lane (bit clear): u00*x + u01*partner; lower: u10*partner + u11*x
-            const R ar = upper ? u.m[0] : u.m[6], ai = upper ? u.m[1] : u.m[7];
-            const R br = upper ? u.m[2] : u.m[4], bi = upper ? u.m[3] : u.m[5];
+            const double ar = upper ? u.m[0] : u.m[6], ai = upper ? u.m[1] : u.m[7];
+            const double br = upper ? u.m[2] : u.m[4], bi = upper ? u.m[3] : u.m[5];
 #pragma unroll
             for (int j = 0; j < A; ++j) {
-                const V p = shfl_xor_v(x[j], d);
-                y[j] = cmad2<V, R>(ar, ai, x[j], br, bi, p);
+                const double2 p = shfl_xor_v(x[j], d);
+                y[j] = cmad2<double2, double>(ar, ai, x[j], br, bi, p);
             }
         }
 #pragma unroll
         for (int j = 0; j < A; ++j) {
             const uint64_t i = i0 + j;
-            if (i < namps && ((i & cm_lo) == cv_lo)) psi[i] = y[j];
+            if (i < namps && ((i & cm_lo) == cv_lo)) psi[i] = st2<V>(y[j]);
         }
     }
 }
@@ -171,8 +183,8 @@ static hipError_t apply_1q_t(void* psiv, int n, int t, const double* U, uint64_t
 {
     using V = typename CT<R>::V;
     V* psi = (V*)psiv;
-    M2<R> u;
-    for (int i = 0; i < 8; ++i) u.m[i] = (R)U[i];
+    M2 u;
+    for (int i = 0; i < 8; ++i) u.m[i] = U[i];
     constexpr int LA = sizeof(R) == 8 ? 1 : 2; // 32 bytes of amplitudes per lane
     constexpr int W = 6 + LA;
     if (t < W) {
@@ -211,7 +223,7 @@ hipError_t launch_apply_1q(void* psi, int dt, int n, int t, const double* U, uin
 template <typename R, int PPL>
 __global__ void __launch_bounds__(256)
 k_2q_quads(typename CT<R>::V* __restrict__ psi, uint64_t nquads, uint64_t b0, uint64_t b1, uint64_t cvals,
-           InsertPlan ip, M4<R> u)
+           InsertPlan ip, M4 u)
 {
     using V = typename CT<R>::V;
     const uint64_t stride = (uint64_t)gridDim.x * (256 * PPL);
@@ -233,19 +245,20 @@ k_2q_quads(typename CT<R>::V* __restrict__ psi, uint64_t nquads, uint64_t b0, ui
         for (int p = 0; p < PPL; ++p) {
             const uint64_t k = k0 + (uint64_t)p * 256;
             if (k < nquads) {
-                V o[4];
+                double2 o[4];
+                const double2 w0 = ld2(v[p][0]), w1 = ld2(v[p][1]), w2 = ld2(v[p][2]), w3 = ld2(v[p][3]);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const R* ur = &u.m[8 * r];
-                    V s = cmad2<V, R>(ur[0], ur[1], v[p][0], ur[2], ur[3], v[p][1]);
-                    V s2 = cmad2<V, R>(ur[4], ur[5], v[p][2], ur[6], ur[7], v[p][3]);
+                    const double* ur = &u.m[8 * r];
+                    const double2 s = cmad2<double2, double>(ur[0], ur[1], w0, ur[2], ur[3], w1);
+                    const double2 s2 = cmad2<double2, double>(ur[4], ur[5], w2, ur[6], ur[7], w3);
                     o[r].x = s.x + s2.x;
                     o[r].y = s.y + s2.y;
                 }
-                psi[ia[p]] = o[0];
-                psi[ia[p] | b0] = o[1];
-                psi[ia[p] | b1] = o[2];
-                psi[ia[p] | b0 | b1] = o[3];
+                psi[ia[p]] = st2<V>(o[0]);
+                psi[ia[p] | b0] = st2<V>(o[1]);
+                psi[ia[p] | b1] = st2<V>(o[2]);
+                psi[ia[p] | b0 | b1] = st2<V>(o[3]);
             }
         }
     }
@@ -256,8 +269,8 @@ static hipError_t apply_2q_t(void* psiv, int n, int t0, int t1, const double* U,
                              hipStream_t st, int* kind)
 {
     using V = typename CT<R>::V;
-    M4<R> u;
-    for (int i = 0; i < 32; ++i) u.m[i] = (R)U[i];
+    M4 u;
+    for (int i = 0; i < 32; ++i) u.m[i] = U[i];
     const int nc = __builtin_popcountll(cm);
     const uint64_t nq = 1ull << (n - 2 - nc);
     InsertPlan ip = make_insert_plan(cm | (1ull << t0) | (1ull << t1));
@@ -284,15 +297,15 @@ hipError_t launch_apply_2q(void* psi, int dt, int n, int t0, int t1, const doubl
 template <typename R, int K>
 __global__ void __launch_bounds__(256)
 k_kq_lds(typename CT<R>::V* __restrict__ psi, uint64_t ngroups, uint64_t cvals, InsertPlan ip,
-         const typename CT<R>::V* __restrict__ Ud, uint64_t tbits_packed_lo, uint64_t tbits_packed_hi)
+         const double2* __restrict__ Ud, uint64_t tbits_packed_lo, uint64_t tbits_packed_hi)
 {
     using V = typename CT<R>::V;
     constexpr int D = 1 << K;
     constexpr int G = 256 / D;
     // U goes to LDS when it fits in 32 KiB; the c128 6-qubit matrix (64 KiB) is
     // read through the caches instead.
-    constexpr bool kUL = D * D * sizeof(V) <= 32768;
-    __shared__ V su[kUL ? D * D : 1];
+    constexpr bool kUL = D * D * sizeof(double2) <= 32768;
+    __shared__ double2 su[kUL ? D * D : 1];
     __shared__ V sx[256];
     __shared__ uint64_t soff[D];
     if (kUL)
@@ -318,18 +331,15 @@ k_kq_lds(typename CT<R>::V* __restrict__ psi, uint64_t ngroups, uint64_t cvals, 
         __syncthreads();
         const uint64_t gi = g0 + cg;
         if (gi < ngroups) {
-            R sr = 0, si = 0;
+            double sr = 0, si = 0;
 #pragma unroll 4
             for (int m = 0; m < D; ++m) {
-                const V a = kUL ? su[cr * D + m] : Ud[cr * D + m];
-                const V x = sx[cg * D + m];
+                const double2 a = kUL ? su[cr * D + m] : Ud[cr * D + m];
+                const double2 x = ld2(sx[cg * D + m]);
                 sr += a.x * x.x - a.y * x.y;
                 si += a.x * x.y + a.y * x.x;
             }
-            V o;
-            o.x = sr;
-            o.y = si;
-            psi[(ins_bits(gi, ip) | cvals) | soff[cr]] = o;
+            psi[(ins_bits(gi, ip) | cvals) | soff[cr]] = st2<V>(make_double2(sr, si));
         }
         __syncthreads();
     }
@@ -346,10 +356,11 @@ static void launch_kq_k(void* psi, int n, uint64_t tmask, uint64_t cm, uint64_t 
     const uint64_t ng = 1ull << (n - K - nc);
     InsertPlan ip = make_insert_plan(cm | tmask);
     const unsigned g = blocks_for(ng, G * 4);
-    hipLaunchKernelGGL((k_kq_lds<R, K>), dim3(g), dim3(256), 0, st, (V*)psi, ng, cv, ip, (const V*)Ud, plo, phi);
+    hipLaunchKernelGGL((k_kq_lds<R, K>), dim3(g), dim3(256), 0, st, (V*)psi, ng, cv, ip, (const double2*)Ud, plo,
+                       phi);
 }
 
-// Ud: device matrix already converted to the state's element type.
+// Ud: device copy of the FP64 matrix.
 hipError_t launch_apply_kq_dev(void* psi, int dt, int n, const int* targets, int k, const void* Ud,
                                uint64_t cm, uint64_t cv, hipStream_t st, int* kind)
 {

@@ -154,24 +154,17 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
     std::vector<double> pool;
     plan_circuit(s->n, ops, n_ops, mats, po, passes, pool);
 
-    // One staging copy: every pass's op table, then the matrix pool in the
-    // state's real type.
+    // One staging copy: every pass's op table, then the FP64 matrix pool.
     size_t nops_total = 0;
     for (auto& p : passes) nops_total += p.ops.size();
-    const size_t es = s->dt == QS_C128 ? sizeof(double) : sizeof(float);
     const size_t ops_bytes = ((nops_total * sizeof(TileOp)) + 255) & ~size_t(255);
-    std::vector<char> host(ops_bytes + pool.size() * es);
+    std::vector<char> host(ops_bytes + pool.size() * sizeof(double));
     size_t off = 0;
     for (auto& p : passes) {
         std::memcpy(host.data() + off, p.ops.data(), p.ops.size() * sizeof(TileOp));
         off += p.ops.size() * sizeof(TileOp);
     }
-    if (s->dt == QS_C128) {
-        std::memcpy(host.data() + ops_bytes, pool.data(), pool.size() * sizeof(double));
-    } else {
-        float* f = (float*)(host.data() + ops_bytes);
-        for (size_t i = 0; i < pool.size(); ++i) f[i] = (float)pool[i];
-    }
+    std::memcpy(host.data() + ops_bytes, pool.data(), pool.size() * sizeof(double));
     const void* dev = nullptr;
     qs_status st = stage_bytes(s, host.data(), host.size(), &dev);
     if (st != QS_OK) return st;

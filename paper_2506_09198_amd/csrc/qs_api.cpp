@@ -473,7 +473,7 @@ qs_status qs_apply_fused(qs_state s, const int* targets, int k, const double* U,
     if (!U || !targets) return set_err(QS_ERR_ARG, "null matrix or target list");
     if ((st = validate_gate(s->n, targets, k, cm, cv)) != QS_OK) return st;
     const void* Ud = nullptr;
-    if ((st = stage_matrices(s, U, 2ull << (2 * k), &Ud)) != QS_OK) return st;
+    if ((st = stage_bytes(s, U, (2ull << (2 * k)) * sizeof(double), &Ud)) != QS_OK) return st;
     return apply_kq_dev_internal(s, targets, k, Ud, cm, cv);
 }
 

@@ -27,7 +27,7 @@ struct QList {
 template <typename R, int M>
 __global__ void __launch_bounds__(256)
 k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
-       const TileOp* __restrict__ ops, int nops, const R* __restrict__ mats)
+       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
@@ -76,20 +76,21 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
             const TileOp& d = ops[o];
             const int kind = d.kind;
             if ((base & d.gcm) != d.gcv) continue; // whole tile fails the outside controls
-            const R* u = mats + d.moff;
+            const double* u = mats + d.moff;
             const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
             if (kind == TK_DENSE1) {
                 const int p = d.p[0];
-                const R u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3], u4 = u[4], u5 = u[5], u6 = u[6], u7 = u[7];
+                const double u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3], u4 = u[4], u5 = u[5], u6 = u[6],
+                             u7 = u[7];
 #pragma unroll
                 for (int s = 0; s < (PER + 1) / 2; ++s) {
                     const uint32_t k = tid + 256 * s;
                     if (k < E / 2) {
                         const uint32_t e0 = ins0_32(k, p), e1 = e0 | (1u << p);
                         if ((e0 & lcm) == lcv) {
-                            const V a = tile[e0], b = tile[e1];
-                            tile[e0] = cmad2<V, R>(u0, u1, a, u2, u3, b);
-                            tile[e1] = cmad2<V, R>(u4, u5, a, u6, u7, b);
+                            const double2 a = ld2(tile[e0]), b = ld2(tile[e1]);
+                            tile[e0] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
+                            tile[e1] = st2<V>(cmad2<double2, double>(u4, u5, a, u6, u7, b));
                         }
                     }
                 }
@@ -103,20 +104,21 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                     if (k < E / 4) {
                         const uint32_t e = ins0_32(ins0_32(k, lo), hi);
                         if ((e & lcm) == lcv) {
-                            const V v0 = tile[e], v1 = tile[e | b0], v2 = tile[e | b1], v3 = tile[e | b0 | b1];
-                            V out[4];
+                            const double2 v0 = ld2(tile[e]), v1 = ld2(tile[e | b0]), v2 = ld2(tile[e | b1]),
+                                          v3 = ld2(tile[e | b0 | b1]);
+                            double2 out[4];
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
-                                const R* ur = u + 8 * r;
-                                const V s1 = cmad2<V, R>(ur[0], ur[1], v0, ur[2], ur[3], v1);
-                                const V s2 = cmad2<V, R>(ur[4], ur[5], v2, ur[6], ur[7], v3);
+                                const double* ur = u + 8 * r;
+                                const double2 s1 = cmad2<double2, double>(ur[0], ur[1], v0, ur[2], ur[3], v1);
+                                const double2 s2 = cmad2<double2, double>(ur[4], ur[5], v2, ur[6], ur[7], v3);
                                 out[r].x = s1.x + s2.x;
                                 out[r].y = s1.y + s2.y;
                             }
-                            tile[e] = out[0];
-                            tile[e | b0] = out[1];
-                            tile[e | b1] = out[2];
-                            tile[e | b0 | b1] = out[3];
+                            tile[e] = st2<V>(out[0]);
+                            tile[e | b0] = st2<V>(out[1]);
+                            tile[e | b1] = st2<V>(out[2]);
+                            tile[e | b0 | b1] = st2<V>(out[3]);
                         }
                     }
                 }
@@ -132,7 +134,7 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                     const uint32_t slot = r0 + tid;
                     bool act = false;
                     uint32_t eo = 0;
-                    V res;
+                    double2 res;
                     if (slot < E) {
                         const uint32_t g = slot >> k, r = slot & (D - 1);
                         uint32_t gb = g; // insert zeros at the target positions (ascending)
@@ -140,14 +142,14 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                             if ((tm >> b) & 1) gb = ins0_32(gb, b);
                         if ((gb & lcm) == lcv) {
                             act = true;
-                            R sr = 0, si = 0;
+                            double sr = 0, si = 0;
 #pragma unroll 4
                             for (uint32_t mm = 0; mm < D; ++mm) {
                                 uint32_t ei = gb;
                                 for (int j = 0; j < k; ++j)
                                     if ((mm >> j) & 1) ei |= 1u << d.p[j];
-                                const V x = tile[ei];
-                                const R ar = u[2 * (r * D + mm)], ai = u[2 * (r * D + mm) + 1];
+                                const double2 x = ld2(tile[ei]);
+                                const double ar = u[2 * (r * D + mm)], ai = u[2 * (r * D + mm) + 1];
                                 sr += ar * x.x - ai * x.y;
                                 si += ar * x.y + ai * x.x;
                             }
@@ -159,7 +161,7 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                         }
                     }
                     __syncthreads();
-                    if (act) tile[eo] = res;
+                    if (act) tile[eo] = st2<V>(res);
                     __syncthreads();
                 }
             } else if (kind == TK_DIAG) {
@@ -171,7 +173,7 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                         const uint64_t g = base | (e & lowm) | ((uint64_t)hoff[e >> L] << L);
                         uint32_t idx = 0;
                         for (int j = 0; j < k; ++j) idx |= (uint32_t)((g >> d.p[j]) & 1) << j;
-                        tile[e] = cmul<V, R>(u[2 * idx], u[2 * idx + 1], tile[e]);
+                        tile[e] = st2<V>(cmul<double2, double>(u[2 * idx], u[2 * idx + 1], ld2(tile[e])));
                     }
                 }
             }
@@ -219,7 +221,7 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     static int cap = env_int("QS_TILE_GRID_CAP", 256 * 8);
     const unsigned g = (unsigned)(ntiles < (uint64_t)cap ? ntiles : (uint64_t)cap);
     hipLaunchKernelGGL((k_tile<R, M>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                       (int)pass.ops.size(), (const R*)dmats);
+                       (int)pass.ops.size(), (const double*)dmats);
     return hipGetLastError();
 }
 
