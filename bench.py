@@ -39,6 +39,8 @@ def _args():
     p.add_argument("--mode", choices=["pergate", "planned"], default="pergate")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-n", type=int, default=26, help="qubits of the oracle sample")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run 3 torch copies of 4 GiB (reference for HBM byte counters) and exit")
     return p.parse_args()
 
 
@@ -58,6 +60,29 @@ def cpu_baseline(n_cpu: int) -> dict:
             "sample": f"gate sweep at n={n_cpu} complex128 ({len(ops)} gates, one pass, {dt:.1f} s)"}
 
 
+def measured_traffic(kernel_class: str, tag: str):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary, or None when the summary is missing or the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"{tag}_hbm_bytes.txt")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC_JSON "):
+            rec = json.loads(line[len("TRAFFIC_JSON "):])
+    if rec is None:
+        return None
+    srcs = ["paper_2506_09198_amd/csrc/gates.hip", "paper_2506_09198_amd/csrc/device_common.h"]
+    sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in srcs)).hexdigest()[:16]
+    if sha != rec.get("src_sha"):
+        return None
+    c = rec["classes"].get(kernel_class)
+    return None if c is None else c["traffic_bytes_per_launch"]
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -65,6 +90,15 @@ def main():
               "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_copy": src.numel() * 16, "copies": 3}))
+        return
 
     import paper_2506_09198_amd as qs
     import workloads as W
@@ -155,7 +189,10 @@ def main():
         "hbm_gbs_algorithmic": bytes_step * a.steps / elapsed / 1e9,
         "hbm_frac_algorithmic": bytes_step * a.steps / elapsed / 1e9 / PEAK_HBM_GBS,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": (measured_traffic(dom, f"gate_sweep_n{n}_{a.dtype}") if a.mode == "pergate" else None),
+                     "traffic_unit": "HBM bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": D["avg_bytes"]},
         "kernels": {k: {"launches": d["launches"], "avg_ms": round(d["avg_ms"], 4), "gbs": round(d["gbs"], 1)}
                     for k, d in kinds.items()},
         "event_coverage": kern_ms / (elapsed * 1e3),

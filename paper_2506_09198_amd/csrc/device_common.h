@@ -55,4 +55,43 @@ template <typename V> __device__ __forceinline__ V st2(double2 v);
 template <> __device__ __forceinline__ float2 st2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 template <> __device__ __forceinline__ double2 st2<double2>(double2 v) { return v; }
 
+// Global loads/stores, optionally non-temporal (streamed past the caches:
+// a gate pass touches every amplitude once, so nothing is reused).
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+template <bool NT> __device__ __forceinline__ double2 gld(const double2* p)
+{
+    if (NT) {
+        const d2v_t v = __builtin_nontemporal_load((const d2v_t*)p);
+        return make_double2(v.x, v.y);
+    }
+    return *p;
+}
+template <bool NT> __device__ __forceinline__ float2 gld(const float2* p)
+{
+    if (NT) {
+        const f2v_t v = __builtin_nontemporal_load((const f2v_t*)p);
+        return make_float2(v.x, v.y);
+    }
+    return *p;
+}
+template <bool NT> __device__ __forceinline__ void gst(double2* p, double2 v)
+{
+    if (NT) {
+        d2v_t w = {v.x, v.y};
+        __builtin_nontemporal_store(w, (d2v_t*)p);
+    } else {
+        *p = v;
+    }
+}
+template <bool NT> __device__ __forceinline__ void gst(float2* p, float2 v)
+{
+    if (NT) {
+        f2v_t w = {v.x, v.y};
+        __builtin_nontemporal_store(w, (f2v_t*)p);
+    } else {
+        *p = v;
+    }
+}
+
 } // namespace qs

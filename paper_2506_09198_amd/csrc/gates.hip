@@ -1,26 +1,21 @@
 // Per-gate kernels for gfx950 (wave64).
 //
 //   k_init_basis   zero the state and set one amplitude to 1.
-//   k_1q_pairs     1q gate, pair walk over a compact counter with the target
-//                  and control bits inserted (the pair update of Alg. 1 for a
-//                  general 2x2 matrix; controls as fixed inserted bits, so no
-//                  branch skips work as in Fig. control6q2).  Consecutive lanes
-//                  take consecutive pairs, so for targets >= 7 (c128) / 8 (c64)
-//                  every load and store instruction covers whole 128-byte lines.
-//   k_1q_wave      1q gate on a low target: each wave loads one contiguous
-//                  chunk (64 lanes x A amplitudes); the partner amplitude is in
-//                  the lane's own registers (t < log2 A) or in lane
-//                  (lane ^ 2^(t - log2 A)) of the same wave, fetched with a
-//                  cross-lane shuffle.  All HBM traffic stays fully coalesced.
-//   k_2q_quads     2q gate on any (t0, t1): 4x4 complex matvec per quad.
+//   k_gate         1q and 2q gates: the pair update of Alg. 1 for a general
+//                  matrix (and its 4x4 analogue), controls as in
+//                  Fig. control6q2.  Targets at bit 6 and above are reached by
+//                  bit-inserted indexing (each lane holds the group members in
+//                  registers); targets below bit 6 by cross-lane shuffles, so
+//                  every memory instruction of a wave covers 64 consecutive
+//                  amplitudes whatever the targets.
 //   k_kq_lds       dense gate on k <= 6 targets: groups of 2^k amplitudes are
 //                  staged through LDS with the matrix, one output per lane.
+#include <cstring>
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace qs {
-
-struct M2 { double m[8]; };
-struct M4 { double m[32]; };
 
 InsertPlan make_insert_plan(uint64_t mask)
 {
@@ -70,143 +65,255 @@ hipError_t launch_init_basis(void* psi, int dt, int n, uint64_t x, hipStream_t s
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- K1 pairs
+// ---------------------------------------------------------------- K1-K3
 
-template <typename R, int PPL>
-__global__ void __launch_bounds__(256)
-k_1q_pairs(typename CT<R>::V* __restrict__ psi, uint64_t npairs, uint64_t half, uint64_t cvals,
-           InsertPlan ip, M2 u)
+// One kernel family for 1q and 2q gates.  Let K be the number of targets and
+// NH of them lie at bit 6 or above ("high"); the other NL = K - NH are "low"
+// (inside a 64-amplitude run).  A compact counter k enumerates the amplitudes
+// whose high-target bits are 0 and whose high control bits match; its low 6
+// bits are the lane, so every load and store instruction of a wave covers 64
+// consecutive amplitudes.  A lane holds, per slot, the 2^NH amplitudes that
+// differ in the high-target bits (registers); the partners along low targets
+// sit in other lanes of the same wave and arrive by cross-lane shuffles.  Each
+// lane then forms its own outputs from the 2^K group members.  Controls below
+// bit 6 are tested per amplitude (the whole wave still takes part in the
+// shuffles); controls at bit 6 or above are inserted into the counter.
+//
+// Memory schedule (measured on MI355X for in-place read-modify-write): one
+// counter chunk per block (no grid-stride loop), a lane's PPL slots spread S
+// = 2^11 counter steps apart, non-temporal loads and stores when every store
+// instruction writes whole lines.
+struct GateArgs {
+    uint64_t C;          // counter range
+    uint64_t cv_hi;      // control values at positions >= 6
+    uint64_t nblocks;    // counter chunks (blocks loop when the grid is capped)
+    uint32_t cm_lo, cv_lo;
+    uint32_t lowmask;    // lane bits of the low targets
+    int32_t slog;        // log2 of the slot spread S
+    uint64_t roff[4];    // register r -> index offset (high-target bits of r)
+    int32_t srcl[4];     // member m -> lane bits of its low targets
+    int32_t hreg[4];     // member m -> register holding it
+    int32_t tlow[2];     // target j is low?
+    int32_t tbit[2];     // target j: lane bit (low) or register bit (high)
+    double U[32];        // 2^K x 2^K complex, row-major
+    InsertPlan ip;       // high targets and high controls, inserted into k
+};
+
+// Register r of a lane's slot, chosen with selects (r is a runtime value).
+template <int NR>
+__device__ __forceinline__ double2 pick(const double2 (&x)[NR], int r)
+{
+    double2 v = x[0];
+#pragma unroll
+    for (int i = 1; i < NR; ++i)
+        if (r == i) v = x[i];
+    return v;
+}
+
+template <typename R, int K, int NH, int PPL, bool NT>
+__global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ psi, GateArgs ga)
 {
     using V = typename CT<R>::V;
-    const uint64_t stride = (uint64_t)gridDim.x * (256 * PPL);
-    for (uint64_t k0 = (uint64_t)blockIdx.x * (256 * PPL) + threadIdx.x; k0 < npairs; k0 += stride) {
-        V a[PPL], b[PPL];
-        uint64_t ia[PPL];
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            const uint64_t k = k0 + (uint64_t)p * 256;
-            ia[p] = ins_bits(k, ip) | cvals;
-            if (k < npairs) {
-                a[p] = psi[ia[p]];
-                b[p] = psi[ia[p] + half];
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            const uint64_t k = k0 + (uint64_t)p * 256;
-            if (k < npairs) {
-                const double2 x = ld2(a[p]), y = ld2(b[p]);
-                psi[ia[p]] = st2<V>(cmad2<double2, double>(u.m[0], u.m[1], x, u.m[2], u.m[3], y));
-                psi[ia[p] + half] = st2<V>(cmad2<double2, double>(u.m[4], u.m[5], x, u.m[6], u.m[7], y));
-            }
-        }
-    }
-}
+    constexpr int D = 1 << K;
+    constexpr int NR = 1 << NH;
+    __shared__ double su[2 * D * D];
+    if (threadIdx.x < 2 * D * D) su[threadIdx.x] = ga.U[threadIdx.x];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t S = 1ull << ga.slog;
+    const uint64_t spb = S >> 8;
+    for (uint64_t b = blockIdx.x; b < ga.nblocks; b += gridDim.x) {
+    const uint64_t base = (b / spb) * (S * PPL) + (b % spb) * 256 + threadIdx.x;
 
-// ---------------------------------------------------------------- K2 wave
-
-template <typename V>
-__device__ __forceinline__ V shfl_xor_v(V v, int d)
-{
-    V r;
-    r.x = __shfl_xor(v.x, d, 64);
-    r.y = __shfl_xor(v.y, d, 64);
-    return r;
-}
-
-template <int A, int D>
-__device__ __forceinline__ void inlane_pairs(const double2 (&x)[A], double2 (&y)[A], const M2& u)
-{
+    double2 x[PPL][NR];
+    uint64_t idx[PPL];
+    bool live[PPL];
 #pragma unroll
-    for (int j = 0; j < A; ++j) {
-        if (j & D) continue;
-        if (j + D >= A) continue;
-        const double2 a = x[j], b = x[j + D];
-        y[j] = cmad2<double2, double>(u.m[0], u.m[1], a, u.m[2], u.m[3], b);
-        y[j + D] = cmad2<double2, double>(u.m[4], u.m[5], a, u.m[6], u.m[7], b);
-    }
-}
-
-// A amplitudes per lane (LA = log2 A); a wave covers W = 6 + LA index bits.
-template <typename R, int LA>
-__global__ void __launch_bounds__(256)
-k_1q_wave(typename CT<R>::V* __restrict__ psi, uint64_t nchunks, uint64_t namps, int t,
-          uint64_t cm_lo, uint64_t cv_lo, uint64_t cv_hi, InsertPlan ip_hi, M2 u)
-{
-    using V = typename CT<R>::V;
-    constexpr int A = 1 << LA;
-    constexpr int W = 6 + LA;
-    const int lane = threadIdx.x & 63;
-    const uint64_t nw = (uint64_t)gridDim.x * 4;
-    for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < nchunks; c += nw) {
-        const uint64_t i0 = ((ins_bits(c, ip_hi) << W) | cv_hi) + (uint64_t)lane * A;
-        double2 x[A], y[A];
+    for (int p = 0; p < PPL; ++p) {
+        const uint64_t k = base + (uint64_t)p * S;
+        live[p] = k < ga.C;
+        idx[p] = ins_bits(k, ga.ip) | ga.cv_hi;
 #pragma unroll
-        for (int j = 0; j < A; ++j) {
-            if (i0 + j < namps) {
-                x[j] = ld2(psi[i0 + j]);
-            } else {
-                x[j].x = 0;
-                x[j].y = 0;
-            }
-        }
-        if (t < LA) {
-            // partner in the lane's own registers; t is 0 or 1, unrolled
-            // separately so every register index is a constant
-            if (t == 0)
-                inlane_pairs<A, 1>(x, y, u);
+        for (int r = 0; r < NR; ++r) {
+            if (live[p])
+                x[p][r] = ld2(gld<NT>(psi + (idx[p] | ga.roff[r])));
             else
-                inlane_pairs<A, 2>(x, y, u);
-        } else {
-            const int d = 1 << (t - LA);
-            const bool upper = (lane & d) == 0;
-            // upper lane (bit clear): u00*x + u01*partner; lower: u10*partner + u11*x
-            const double ar = upper ? u.m[0] : u.m[6], ai = upper ? u.m[1] : u.m[7];
-            const double br = upper ? u.m[2] : u.m[4], bi = upper ? u.m[3] : u.m[5];
-#pragma unroll
-            for (int j = 0; j < A; ++j) {
-                const double2 p = shfl_xor_v(x[j], d);
-                y[j] = cmad2<double2, double>(ar, ai, x[j], br, bi, p);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < A; ++j) {
-            const uint64_t i = i0 + j;
-            if (i < namps && ((i & cm_lo) == cv_lo)) psi[i] = st2<V>(y[j]);
+                x[p][r] = make_double2(0.0, 0.0);
         }
     }
+    // row of the matrix each register of this lane computes
+    int rr[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        int v = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int bit = ga.tlow[j] ? (int)((lane >> ga.tbit[j]) & 1) : ((r >> ga.tbit[j]) & 1);
+            v |= bit << j;
+        }
+        rr[r] = v;
+    }
+    const uint32_t myctl = lane & ga.cm_lo;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        double2 mem[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            // all-high gates keep member m in register m (targets in order)
+            const double2 v = (NH == K) ? x[p][m & (NR - 1)] : pick<NR>(x[p], ga.hreg[m]);
+            if (NH == K) {
+                mem[m] = v; // no low targets: every member is in this lane
+            } else {
+                const int src = (int)((lane & ~ga.lowmask) | (uint32_t)ga.srcl[m]);
+                mem[m].x = __shfl(v.x, src, 64);
+                mem[m].y = __shfl(v.y, src, 64);
+            }
+        }
+        if (live[p] && myctl == ga.cv_lo) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    const double ur = su[2 * (rr[r] * D + m)], ui = su[2 * (rr[r] * D + m) + 1];
+                    sr += ur * mem[m].x - ui * mem[m].y;
+                    si += ur * mem[m].y + ui * mem[m].x;
+                }
+                gst<NT>(psi + (idx[p] | ga.roff[r]), st2<V>(make_double2(sr, si)));
+            }
+        }
+    }
+    }
+}
+
+static int env_nt()
+{
+    static int v = env_int("QS_NT", 1);
+    return v;
+}
+
+template <typename R, int K, int NH, int PPL>
+static void launch_gate_p(void* psi, const GateArgs& ga, bool nt, hipStream_t st)
+{
+    using V = typename CT<R>::V;
+    // One block per counter chunk; beyond 2^22 blocks (2^32 threads would
+    // overflow the dispatch size) the blocks loop over the remaining chunks.
+    const unsigned g = (unsigned)(ga.nblocks < (1ull << 22) ? ga.nblocks : (1ull << 22));
+    if (nt)
+        hipLaunchKernelGGL((k_gate<R, K, NH, PPL, true>), dim3(g), dim3(256), 0, st, (V*)psi, ga);
+    else
+        hipLaunchKernelGGL((k_gate<R, K, NH, PPL, false>), dim3(g), dim3(256), 0, st, (V*)psi, ga);
+}
+
+static int env_slog()
+{
+    static int v = env_int("QS_SLOG", 11);
+    return v;
+}
+
+// Slots per lane by register count (about 4 amplitudes in flight per lane by
+// default; QS_PPL_H<NH> overrides for tuning).
+template <typename R, int K, int NH>
+static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
+{
+    static int ppl_env = env_int(NH == 0 ? "QS_PPL_H0" : (NH == 1 ? "QS_PPL_H1" : "QS_PPL_H2"), 0);
+    // Measured on MI355X (n=30 c128): 4 / 2 / 1 slots for NH = 0 / 1 / 2,
+    // except two high targets both at bit 18 or above, where 2 slots recover
+    // 10-15% (their four streams are megabytes apart).
+    int ppl = NH == 0 ? 4 : (NH == 1 ? 2 : (ga.roff[1] >= (1ull << 18) && ga.roff[2] >= (1ull << 18) ? 2 : 1));
+    if (ppl_env > 0) ppl = ppl_env;
+    auto go = [&](auto pplc) {
+        constexpr int P = decltype(pplc)::value;
+        const int sl = env_slog();
+        ga.slog = (ga.C >= ((1ull << sl) * P)) ? sl : 8;
+        ga.nblocks = (ga.C + 256 * P - 1) / (256 * P);
+        launch_gate_p<R, K, NH, P>(psi, ga, nt, st);
+    };
+    if (ppl == 1)
+        go(std::integral_constant<int, 1>());
+    else if (ppl == 4)
+        go(std::integral_constant<int, 4>());
+    else
+        go(std::integral_constant<int, 2>());
 }
 
 template <typename R>
-static hipError_t apply_1q_t(void* psiv, int n, int t, const double* U, uint64_t cm, uint64_t cv,
-                             hipStream_t st, int* kind)
+static hipError_t apply_gate_t(void* psi, int n, int K, const int* t, const double* U, uint64_t cm, uint64_t cv,
+                               hipStream_t st)
 {
-    using V = typename CT<R>::V;
-    V* psi = (V*)psiv;
-    M2 u;
-    for (int i = 0; i < 8; ++i) u.m[i] = U[i];
-    constexpr int LA = sizeof(R) == 8 ? 1 : 2; // 32 bytes of amplitudes per lane
-    constexpr int W = 6 + LA;
-    if (t < W) {
-        const uint64_t lo_mask = (W >= 64) ? ~0ull : ((1ull << W) - 1);
-        const uint64_t cm_lo = cm & lo_mask, cv_lo = cv & lo_mask;
-        const uint64_t cm_hi = cm & ~lo_mask, cv_hi = cv & ~lo_mask;
-        const int nhi = __builtin_popcountll(cm_hi);
-        const uint64_t nchunks = (n > W) ? (1ull << (n - W - nhi)) : 1;
-        InsertPlan ip = make_insert_plan(cm_hi >> W);
-        const unsigned g = blocks_for(nchunks, 4);
-        hipLaunchKernelGGL((k_1q_wave<R, LA>), dim3(g), dim3(256), 0, st, psi, nchunks, 1ull << n, t,
-                           cm_lo, cv_lo, cv_hi, ip, u);
-        if (kind) *kind = QS_K_1Q_LO;
+    // Amplitudes per 128-byte line: controls at or above this bit select whole
+    // lines and are inserted into the counter (only needed lines are read);
+    // controls below it are tested per amplitude.
+    constexpr int LINE_BITS = sizeof(R) == 8 ? 3 : 4;
+    GateArgs ga;
+    std::memset(&ga, 0, sizeof ga);
+    const int D = 1 << K;
+    for (int i = 0; i < 2 * D * D; ++i) ga.U[i] = U[i];
+    const uint64_t linemask = (1ull << LINE_BITS) - 1;
+    const uint64_t cm_ins = cm & ~linemask;
+    // lane bits: the lowest 6 positions not taken by inserted controls
+    int lanepos[6];
+    int nl = 0;
+    for (int q = 0; q < 64 && nl < 6; ++q)
+        if (!((cm_ins >> q) & 1)) lanepos[nl++] = q;
+    uint64_t himask = 0;
+    int nh = 0;
+    uint32_t lowmask = 0;
+    for (int j = 0; j < K; ++j) {
+        int lb = -1;
+        for (int l = 0; l < 6; ++l)
+            if (lanepos[l] == t[j]) lb = l;
+        if (lb < 0) {
+            ga.tlow[j] = 0;
+            ga.tbit[j] = nh++;
+            himask |= 1ull << t[j];
+        } else {
+            ga.tlow[j] = 1;
+            ga.tbit[j] = lb;
+            lowmask |= 1u << lb;
+        }
+    }
+    ga.lowmask = lowmask;
+    for (int r = 0; r < (1 << nh); ++r) {
+        uint64_t off = 0;
+        for (int j = 0; j < K; ++j)
+            if (!ga.tlow[j] && ((r >> ga.tbit[j]) & 1)) off |= 1ull << t[j];
+        ga.roff[r] = off;
+    }
+    for (int m = 0; m < D; ++m) {
+        int sl = 0, hr = 0;
+        for (int j = 0; j < K; ++j)
+            if ((m >> j) & 1) {
+                if (ga.tlow[j])
+                    sl |= 1 << ga.tbit[j];
+                else
+                    hr |= 1 << ga.tbit[j];
+            }
+        ga.srcl[m] = sl;
+        ga.hreg[m] = hr;
+    }
+    // controls below LINE_BITS are lane bits l == q (no insertion below them)
+    ga.cm_lo = (uint32_t)(cm & linemask);
+    ga.cv_lo = (uint32_t)(cv & linemask);
+    ga.cv_hi = cv & ~linemask;
+    ga.ip = make_insert_plan(himask | cm_ins);
+    const int nins = nh + __builtin_popcountll(cm_ins);
+    ga.C = 1ull << (n - nins);
+    // Non-temporal stores only when each store instruction writes whole lines:
+    // no lane skips its store (no per-amplitude controls) and full waves.
+    const bool nt = env_nt() && ga.cm_lo == 0 && ga.C >= 64;
+    if (K == 1) {
+        if (nh == 0)
+            launch_gate_k<R, 1, 0>(psi, ga, nt, st);
+        else
+            launch_gate_k<R, 1, 1>(psi, ga, nt, st);
     } else {
-        const int nc = __builtin_popcountll(cm);
-        const uint64_t npairs = 1ull << (n - 1 - nc);
-        InsertPlan ip = make_insert_plan(cm | (1ull << t));
-        constexpr int PPL = 2;
-        const unsigned g = blocks_for(npairs, 256 * PPL);
-        hipLaunchKernelGGL((k_1q_pairs<R, PPL>), dim3(g), dim3(256), 0, st, psi, npairs, 1ull << t, cv, ip,
-                           u);
-        if (kind) *kind = QS_K_1Q_HI;
+        if (nh == 0)
+            launch_gate_k<R, 2, 0>(psi, ga, nt, st);
+        else if (nh == 1)
+            launch_gate_k<R, 2, 1>(psi, ga, nt, st);
+        else
+            launch_gate_k<R, 2, 2>(psi, ga, nt, st);
     }
     return hipGetLastError();
 }
@@ -214,79 +321,18 @@ static hipError_t apply_1q_t(void* psiv, int n, int t, const double* U, uint64_t
 hipError_t launch_apply_1q(void* psi, int dt, int n, int t, const double* U, uint64_t cm, uint64_t cv,
                            hipStream_t st, int* kind)
 {
-    return dt == QS_C128 ? apply_1q_t<double>(psi, n, t, U, cm, cv, st, kind)
-                         : apply_1q_t<float>(psi, n, t, U, cm, cv, st, kind);
-}
-
-// ---------------------------------------------------------------- K3 quads
-
-template <typename R, int PPL>
-__global__ void __launch_bounds__(256)
-k_2q_quads(typename CT<R>::V* __restrict__ psi, uint64_t nquads, uint64_t b0, uint64_t b1, uint64_t cvals,
-           InsertPlan ip, M4 u)
-{
-    using V = typename CT<R>::V;
-    const uint64_t stride = (uint64_t)gridDim.x * (256 * PPL);
-    for (uint64_t k0 = (uint64_t)blockIdx.x * (256 * PPL) + threadIdx.x; k0 < nquads; k0 += stride) {
-        V v[PPL][4];
-        uint64_t ia[PPL];
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            const uint64_t k = k0 + (uint64_t)p * 256;
-            ia[p] = ins_bits(k, ip) | cvals;
-            if (k < nquads) {
-                v[p][0] = psi[ia[p]];
-                v[p][1] = psi[ia[p] | b0];
-                v[p][2] = psi[ia[p] | b1];
-                v[p][3] = psi[ia[p] | b0 | b1];
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < PPL; ++p) {
-            const uint64_t k = k0 + (uint64_t)p * 256;
-            if (k < nquads) {
-                double2 o[4];
-                const double2 w0 = ld2(v[p][0]), w1 = ld2(v[p][1]), w2 = ld2(v[p][2]), w3 = ld2(v[p][3]);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double* ur = &u.m[8 * r];
-                    const double2 s = cmad2<double2, double>(ur[0], ur[1], w0, ur[2], ur[3], w1);
-                    const double2 s2 = cmad2<double2, double>(ur[4], ur[5], w2, ur[6], ur[7], w3);
-                    o[r].x = s.x + s2.x;
-                    o[r].y = s.y + s2.y;
-                }
-                psi[ia[p]] = st2<V>(o[0]);
-                psi[ia[p] | b0] = st2<V>(o[1]);
-                psi[ia[p] | b1] = st2<V>(o[2]);
-                psi[ia[p] | b0 | b1] = st2<V>(o[3]);
-            }
-        }
-    }
-}
-
-template <typename R>
-static hipError_t apply_2q_t(void* psiv, int n, int t0, int t1, const double* U, uint64_t cm, uint64_t cv,
-                             hipStream_t st, int* kind)
-{
-    using V = typename CT<R>::V;
-    M4 u;
-    for (int i = 0; i < 32; ++i) u.m[i] = U[i];
-    const int nc = __builtin_popcountll(cm);
-    const uint64_t nq = 1ull << (n - 2 - nc);
-    InsertPlan ip = make_insert_plan(cm | (1ull << t0) | (1ull << t1));
-    constexpr int PPL = 2;
-    const unsigned g = blocks_for(nq, 256 * PPL);
-    hipLaunchKernelGGL((k_2q_quads<R, PPL>), dim3(g), dim3(256), 0, st, (V*)psiv, nq, 1ull << t0, 1ull << t1,
-                       cv, ip, u);
-    if (kind) *kind = QS_K_2Q;
-    return hipGetLastError();
+    if (kind) *kind = t >= 6 ? QS_K_1Q_HI : QS_K_1Q_LO; // class by target only (tracing)
+    return dt == QS_C128 ? apply_gate_t<double>(psi, n, 1, &t, U, cm, cv, st)
+                         : apply_gate_t<float>(psi, n, 1, &t, U, cm, cv, st);
 }
 
 hipError_t launch_apply_2q(void* psi, int dt, int n, int t0, int t1, const double* U, uint64_t cm,
                            uint64_t cv, hipStream_t st, int* kind)
 {
-    return dt == QS_C128 ? apply_2q_t<double>(psi, n, t0, t1, U, cm, cv, st, kind)
-                         : apply_2q_t<float>(psi, n, t0, t1, U, cm, cv, st, kind);
+    if (kind) *kind = QS_K_2Q;
+    const int t[2] = {t0, t1};
+    return dt == QS_C128 ? apply_gate_t<double>(psi, n, 2, t, U, cm, cv, st)
+                         : apply_gate_t<float>(psi, n, 2, t, U, cm, cv, st);
 }
 
 // ---------------------------------------------------------------- generic k
