@@ -11,9 +11,167 @@
 #include "planner.h"
 
 #include <algorithm>
+#include <complex>
 #include <cstring>
 
 namespace qs {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- fusion
+//
+// Inside one pass, consecutive operations whose qubits (targets and local
+// controls, all inside the tile, no per-tile controls) fit in K qubits are
+// multiplied into one 2^K x 2^K matrix in FP64 and applied as a single dense
+// block on matrix cores.  The product is split into FP32 hi and lo parts
+// (hi + lo carries ~48 bits) and stored in the A-fragment order of
+// v_mfma_f32_16x16x4f32 for the real embedding [[Ur, -Ui], [Ui, Ur]].
+
+static bool op_local_bits(const TileOp& t, uint32_t* bits)
+{
+    if (t.gcm != 0) return false;
+    uint32_t b = (uint32_t)t.lcm;
+    if (t.kind == TK_DIAG) {
+        for (int j = 0; j < t.k; ++j) {
+            if (t.lp[j] < 0) return false;
+            b |= 1u << t.lp[j];
+        }
+    } else if (t.kind == TK_DENSE1 || t.kind == TK_DENSE2 || t.kind == TK_DENSEK) {
+        for (int j = 0; j < t.k; ++j) b |= 1u << t.p[j];
+    } else {
+        return false;
+    }
+    *bits = b;
+    return true;
+}
+
+// Full 2^K x 2^K matrix (column-major product order: G = op * G) of one op in
+// the block whose qubits are the local positions bq[0..K).
+static void embed_op(const TileOp& t, const std::vector<double>& pool, const int* bq, int K, std::vector<cd>& G)
+{
+    const int D = 1 << K;
+    int bidx[32];
+    for (int i = 0; i < 32; ++i) bidx[i] = -1;
+    for (int j = 0; j < K; ++j) bidx[bq[j]] = j;
+    uint32_t cbm = 0, cbv = 0;
+    for (int q = 0; q < 32; ++q)
+        if ((t.lcm >> q) & 1) {
+            cbm |= 1u << bidx[q];
+            if ((t.lcv >> q) & 1) cbv |= 1u << bidx[q];
+        }
+    int tb[6];
+    const bool diag = t.kind == TK_DIAG;
+    for (int j = 0; j < t.k; ++j) tb[j] = bidx[diag ? t.lp[j] : t.p[j]];
+    const int dk = 1 << t.k;
+    const double* U = pool.data() + t.moff;
+    std::vector<cd> H((size_t)D * D, cd(0, 0));
+    for (int c = 0; c < D; ++c) {
+        if (((uint32_t)c & cbm) != cbv) {
+            H[(size_t)c * D + c] = 1.0;
+            continue;
+        }
+        int mi = 0, base = c;
+        for (int j = 0; j < t.k; ++j) {
+            mi |= ((c >> tb[j]) & 1) << j;
+            base &= ~(1 << tb[j]);
+        }
+        if (diag) {
+            H[(size_t)c * D + c] = cd(U[2 * mi], U[2 * mi + 1]);
+            continue;
+        }
+        for (int r = 0; r < dk; ++r) {
+            int row = base;
+            for (int j = 0; j < t.k; ++j)
+                if ((r >> j) & 1) row |= 1 << tb[j];
+            H[(size_t)row * D + c] = cd(U[2 * (r * dk + mi)], U[2 * (r * dk + mi) + 1]);
+        }
+    }
+    std::vector<cd> out((size_t)D * D, cd(0, 0));
+    for (int r = 0; r < D; ++r)
+        for (int k2 = 0; k2 < D; ++k2) {
+            const cd h = H[(size_t)r * D + k2];
+            if (h == cd(0, 0)) continue;
+            for (int c = 0; c < D; ++c) out[(size_t)r * D + c] += h * G[(size_t)k2 * D + c];
+        }
+    G.swap(out);
+}
+
+static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_dense)
+{
+    std::vector<TileOp> out;
+    std::vector<size_t> blk;
+    uint32_t bbits = 0;
+    int bdense = 0;
+    auto emit = [&]() {
+        if (blk.empty()) return;
+        if (bdense < min_dense) {
+            for (size_t i : blk) out.push_back(P.ops[i]);
+        } else {
+            uint32_t bits = bbits;
+            for (int q = 0; __builtin_popcount(bits) < K && q < P.m; ++q) bits |= 1u << q;
+            int bq[8], nb = 0;
+            for (int q = 0; q < 32; ++q)
+                if ((bits >> q) & 1) bq[nb++] = q;
+            const int D = 1 << K;
+            std::vector<cd> G((size_t)D * D, cd(0, 0));
+            for (int i = 0; i < D; ++i) G[(size_t)i * D + i] = 1.0;
+            for (size_t i : blk) embed_op(P.ops[i], pool, bq, K, G);
+            const int DR = 2 * D, RB = DR / 16, KS = DR / 4, NF = RB * KS;
+            std::vector<float> fr((size_t)2 * NF * 64); // hi fragments, then lo
+            for (int lane = 0; lane < 64; ++lane)
+                for (int rb = 0; rb < RB; ++rb)
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int row = 16 * rb + (lane % 16), col = 4 * ks + lane / 16;
+                        const cd u = G[(size_t)(row / 2) * D + col / 2];
+                        double v;
+                        if ((row & 1) == 0)
+                            v = (col & 1) == 0 ? u.real() : -u.imag();
+                        else
+                            v = (col & 1) == 0 ? u.imag() : u.real();
+                        const int f = rb * KS + ks;
+                        const float hi = (float)v;
+                        const float lo = (float)(v - (double)hi);
+                        fr[((size_t)(f / 4) * 64 + lane) * 4 + (f % 4)] = hi;
+                        fr[((size_t)(NF / 4 + f / 4) * 64 + lane) * 4 + (f % 4)] = lo;
+                    }
+            TileOp t;
+            std::memset(&t, 0, sizeof t);
+            t.kind = TK_MFMA;
+            t.k = K;
+            for (int j = 0; j < K; ++j) t.p[j] = bq[j];
+            size_t off = pool.size();
+            pool.resize(off + fr.size() / 2 + 2);
+            // fragments start on a 16-byte boundary inside the pool
+            if (off & 1) ++off;
+            std::memcpy(pool.data() + off, fr.data(), fr.size() * sizeof(float));
+            t.moff = off;
+            out.push_back(t);
+        }
+        blk.clear();
+        bbits = 0;
+        bdense = 0;
+    };
+    for (size_t i = 0; i < P.ops.size(); ++i) {
+        uint32_t bits = 0;
+        const bool ok = op_local_bits(P.ops[i], &bits);
+        if (ok && __builtin_popcount(bbits | bits) <= K) {
+            blk.push_back(i);
+            bbits |= bits;
+            bdense += P.ops[i].kind != TK_DIAG;
+            continue;
+        }
+        emit();
+        if (ok) {
+            blk.push_back(i);
+            bbits = bits;
+            bdense = P.ops[i].kind != TK_DIAG;
+        } else {
+            out.push_back(P.ops[i]);
+        }
+    }
+    emit();
+    P.ops.swap(out);
+}
 
 static bool is_diagonal(const double* U, int nt)
 {
@@ -75,7 +233,28 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
             t.moff = pool.size();
             if (it.diag) {
                 t.kind = TK_DIAG;
-                for (int j = 0; j < o.nt; ++j) t.p[j] = o.t[j];
+                int nlt = 0;
+                for (int j = 0; j < 6; ++j) t.lp[j] = -1;
+                for (int j = 0; j < o.nt; ++j) {
+                    t.p[j] = o.t[j];
+                    if ((qmask >> o.t[j]) & 1) {
+                        t.lp[j] = (int8_t)pos[o.t[j]];
+                        ++nlt;
+                        t.dj = j;
+                        t.dbit = (int8_t)pos[o.t[j]];
+                    }
+                }
+                const int nlc = __builtin_popcountll(t.lcm);
+                if (nlt == 0 && nlc == 0) {
+                    t.dclass = DG_UNIFORM;
+                } else if (nlt == 1 && nlc == 0) {
+                    t.dclass = DG_LTARGET;
+                } else if (nlt == 0 && nlc == 1) {
+                    t.dclass = DG_LCONTROL;
+                    t.dbit = (int8_t)__builtin_ctzll(t.lcm);
+                } else {
+                    t.dclass = DG_GENERAL;
+                }
                 for (int r = 0; r < d; ++r) {
                     pool.push_back(U[2 * (r * d + r)]);
                     pool.push_back(U[2 * (r * d + r) + 1]);
@@ -89,6 +268,8 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
             P.gates += 1;
             P.updates += 1ull << (n - __builtin_popcountll(o.cmask));
         }
+        if ((po.fuse_k == 4 || po.fuse_k == 5) && po.dt == QS_C64 && m >= po.fuse_k + 4)
+            fuse_pass(P, pool, po.fuse_k, po.fuse_min);
         passes.push_back(std::move(P));
         items.clear();
         qmask = 0;
@@ -138,7 +319,11 @@ static qs_status plan_opts(int dt, const qs_op* ops, int64_t n_ops, const qs_run
     for (int64_t g = 0; g < n_ops; ++g) maxk = std::max(maxk, (int)ops[g].nt);
     po.m = std::max(po.m, maxk);
     po.L = default_low_qubits(dt);
-    po.fuse_k = o.fuse_k;
+    po.fuse_k = o.fuse_k > 0 ? o.fuse_k : env_int("QS_FUSE_K", 0);
+    po.fuse_min = env_int("QS_FUSE_MIN", 3);
+    po.dt = dt;
+    if (po.fuse_k != 0 && po.fuse_k != 4 && po.fuse_k != 5)
+        return set_err(QS_ERR_ARG, "fuse_k=%d: fused blocks have 4 or 5 qubits", po.fuse_k);
     return QS_OK;
 }
 

@@ -26,9 +26,18 @@ struct TileOp {
     uint64_t lcm, lcv;
     uint64_t gcm, gcv;
     uint64_t moff; // offset, in reals, into the pass matrix pool
-    uint64_t rsv;
+    // TK_DIAG only: tile-local position of each target (-1 outside the tile),
+    // and the shape class the kernel folds per tile: DG_UNIFORM (no local bit:
+    // one factor for the whole tile), DG_LTARGET (one local target, no local
+    // control), DG_LCONTROL (no local target, one local control), DG_GENERAL.
+    int8_t lp[6];
+    int8_t dclass;
+    int8_t dbit; // the local bit of DG_LTARGET / DG_LCONTROL
+    int32_t dj;  // DG_LTARGET: which target is local
+    int32_t rsv;
 };
-static_assert(sizeof(TileOp) == 80, "TileOp layout");
+static_assert(sizeof(TileOp) == 88, "TileOp layout");
+enum { DG_UNIFORM = 0, DG_LTARGET = 1, DG_LCONTROL = 2, DG_GENERAL = 3 };
 
 struct PlanPass {
     int m = 0;                 // tile qubits
@@ -40,9 +49,11 @@ struct PlanPass {
 };
 
 struct PlanOpts {
-    int m = 12;     // tile qubits
-    int L = 5;      // forced low qubits
-    int fuse_k = 0; // 0: no dense fusion
+    int m = 12;       // tile qubits
+    int L = 5;        // forced low qubits
+    int fuse_k = 0;   // 0: no dense fusion; 4 or 5: matrix-core blocks (complex64)
+    int fuse_min = 3; // dense gates a block must absorb to be worth a fused block
+    int dt = QS_C128;
 };
 
 // Plan in FP64.  `mats_out` receives the pool the passes' moff index (FP64,

@@ -24,10 +24,92 @@ struct QList {
     int32_t q[QS_MAX_QUBITS];
 };
 
+// Fused dense block on K = 4 or 5 tile-local qubits with FP32 matrix cores
+// (complex64 tiles).  The complex 2^K x 2^K matrix acts as its real embedding
+// [[Ur, -Ui], [Ui, Ur]] (interleaved rows/columns, 2^(K+1) square) on the
+// tile's 2^(M-K) groups ("columns"), with v_mfma_f32_16x16x4f32: lane l holds
+// A[l%16][l/16], B[l/16][l%16] and D[4(l/16)+v][l%16].  The A fragments come
+// pre-arranged by the planner ([q][lane][4] floats, q*4+j = rb*KS + ks), so a
+// wave loads them with 16-byte coalesced loads.  Each wave owns whole column
+// blocks of 16 groups, so its in-place writes never race another wave.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <int K, int M>
+__device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const double* mats, int tid)
+{
+    constexpr int DR = 2 << K;     // real dimension
+    constexpr int RB = DR / 16;    // 16-row blocks
+    constexpr int KS = DR / 4;     // k steps of 4
+    constexpr int NF = RB * KS;    // A fragments per lane
+    constexpr int C = 1 << (M - K);
+    constexpr int CB = C / 16;
+    static_assert(CB >= 1, "tile too small for a fused block");
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // hi fragments, then lo fragments: the FP64 product U = U_hi + U_lo with
+    // both parts FP32, so the matrix is not rounded (a rounded H^n block would
+    // shrink the norm by the same factor at every pass).
+    const f4_t* frag = (const f4_t*)(mats + d.moff);
+    float a[NF], al[NF];
+#pragma unroll
+    for (int q = 0; q < NF / 4; ++q) {
+        const f4_t v = frag[q * 64 + lane];
+        const f4_t w = frag[(NF / 4 + q) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            a[4 * q + j] = v[j];
+            al[4 * q + j] = w[j];
+        }
+    }
+    uint32_t tm = 0;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        pos[j] = d.p[j];
+        tm |= 1u << pos[j];
+    }
+    for (int cb = wave; cb < CB; cb += 4) {
+        const uint32_t col = cb * 16 + li;
+        uint32_t gb = col; // insert zeros at the block qubits (ascending)
+        for (int b = 0; b < M; ++b)
+            if ((tm >> b) & 1) gb = ins0_32(gb, b);
+        f4_t acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int mm = 2 * ks + (lk >> 1); // group member of real row 4ks + lk
+            uint32_t e = gb;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((mm >> j) & 1) e |= 1u << pos[j];
+            const float2 x = tile[e];
+            const float bv = (lk & 1) ? x.y : x.x;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[rb * KS + ks], bv, acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb * KS + ks], bv, acc[rb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int mm = 8 * rb + 2 * lk + h; // rows 16rb + 4lk + 2h (+1) = (re, im) of member mm
+                uint32_t e = gb;
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if ((mm >> j) & 1) e |= 1u << pos[j];
+                tile[e] = make_float2(acc[rb][2 * h], acc[rb][2 * h + 1]);
+            }
+        }
+    }
+}
+
 template <typename R, int M>
 __global__ void __launch_bounds__(256)
 k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
-       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats)
+       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
@@ -55,7 +137,8 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
             for (int s = 0; s < PER; ++s) {
                 const uint32_t e = tid + 256 * s;
                 if (E >= 256 || e < E) {
-                    const V v = psi[base | (e & lowm) | ((uint64_t)hoff[e >> L] << L)];
+                    const V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
+                    const V v = nt ? gld<true>(a) : gld<false>(a);
                     rx[s] = v.x;
                     ry[s] = v.y;
                 }
@@ -75,7 +158,7 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
         for (int o = 0; o < nops; ++o) {
             const TileOp& d = ops[o];
             const int kind = d.kind;
-            if ((base & d.gcm) != d.gcv) continue; // whole tile fails the outside controls
+            if (kind != TK_DIAG && (base & d.gcm) != d.gcv) continue; // tile fails the outside controls
             const double* u = mats + d.moff;
             const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
             if (kind == TK_DENSE1) {
@@ -164,18 +247,102 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                     if (act) tile[eo] = st2<V>(res);
                     __syncthreads();
                 }
+            } else if (kind == TK_MFMA) {
+                if constexpr (sizeof(R) == 4 && M >= 8) {
+                    if (d.k == 5) {
+                        if constexpr (M >= 9) mfma_block<5, M>((float2*)tile, d, mats, tid);
+                    } else {
+                        mfma_block<4, M>((float2*)tile, d, mats, tid);
+                    }
+                }
             } else if (kind == TK_DIAG) {
-                const int k = d.k;
+                // A run of diagonal gates [o, o2) is applied in one sweep with
+                // the lane's elements in registers.  Per tile the gates' bits
+                // outside the tile are fixed, so most gates reduce to a factor
+                // on one local bit (or to one factor for the whole tile); such
+                // factors are multiplied together in uniform (scalar) code and
+                // reach each element as one complex multiply per local bit.
+                int o2 = o + 1;
+                while (o2 < nops && ops[o2].kind == TK_DIAG) ++o2;
+                double2 v[PER];
 #pragma unroll
                 for (int s = 0; s < PER; ++s) {
                     const uint32_t e = tid + 256 * s;
-                    if (e < E && (e & lcm) == lcv) {
-                        const uint64_t g = base | (e & lowm) | ((uint64_t)hoff[e >> L] << L);
-                        uint32_t idx = 0;
-                        for (int j = 0; j < k; ++j) idx |= (uint32_t)((g >> d.p[j]) & 1) << j;
-                        tile[e] = st2<V>(cmul<double2, double>(u[2 * idx], u[2 * idx + 1], ld2(tile[e])));
+                    v[s] = (E >= 256 || e < E) ? ld2(tile[e]) : make_double2(0.0, 0.0);
+                }
+                double cr = 1.0, ci = 0.0;              // whole-tile factor
+                int abit = -1;                          // pending one-bit factor
+                double a0r = 1.0, a0i = 0.0, a1r = 1.0, a1i = 0.0;
+                auto flush = [&]() {
+                    if (abit < 0) return;
+#pragma unroll
+                    for (int s = 0; s < PER; ++s) {
+                        const uint32_t e = tid + 256 * s;
+                        const bool one = (e >> abit) & 1;
+                        v[s] = cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, v[s]);
+                    }
+                    abit = -1;
+                };
+                auto merge = [&](int bit, double f0r, double f0i, double f1r, double f1i) {
+                    if (bit != abit) {
+                        flush();
+                        abit = bit;
+                        a0r = f0r; a0i = f0i; a1r = f1r; a1i = f1i;
+                    } else {
+                        const double t0r = a0r * f0r - a0i * f0i, t0i = a0r * f0i + a0i * f0r;
+                        const double t1r = a1r * f1r - a1i * f1i, t1i = a1r * f1i + a1i * f1r;
+                        a0r = t0r; a0i = t0i; a1r = t1r; a1i = t1i;
+                    }
+                };
+                for (int q = o; q < o2; ++q) {
+                    const TileOp& g = ops[q];
+                    if ((base & g.gcm) != g.gcv) continue;
+                    const double* dd = mats + g.moff;
+                    uint32_t gidx = 0; // index bits contributed by targets outside the tile
+                    for (int j = 0; j < g.k; ++j)
+                        if (g.lp[j] < 0) gidx |= (uint32_t)((base >> g.p[j]) & 1) << j;
+                    const int cls = g.dclass;
+                    if (cls == DG_UNIFORM) {
+                        const double fr = dd[2 * gidx], fi = dd[2 * gidx + 1];
+                        const double tr = cr * fr - ci * fi, ti = cr * fi + ci * fr;
+                        cr = tr; ci = ti;
+                    } else if (cls == DG_LTARGET) {
+                        const uint32_t i1 = gidx | (1u << g.dj);
+                        merge(g.dbit, dd[2 * gidx], dd[2 * gidx + 1], dd[2 * i1], dd[2 * i1 + 1]);
+                    } else if (cls == DG_LCONTROL) {
+                        const double fr = dd[2 * gidx], fi = dd[2 * gidx + 1];
+                        if (g.lcv) merge(g.dbit, 1.0, 0.0, fr, fi);
+                        else merge(g.dbit, fr, fi, 1.0, 0.0);
+                    } else {
+                        flush();
+                        const uint32_t lc = (uint32_t)g.lcm, lv = (uint32_t)g.lcv;
+#pragma unroll
+                        for (int s = 0; s < PER; ++s) {
+                            const uint32_t e = tid + 256 * s;
+                            if ((e & lc) == lv) {
+                                uint32_t idx = gidx;
+                                for (int j = 0; j < g.k; ++j)
+                                    if (g.lp[j] >= 0) idx |= ((e >> g.lp[j]) & 1) << j;
+                                v[s] = cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], v[s]);
+                            }
+                        }
                     }
                 }
+                if (abit >= 0) {
+                    const double t0r = a0r * cr - a0i * ci, t0i = a0r * ci + a0i * cr;
+                    const double t1r = a1r * cr - a1i * ci, t1i = a1r * ci + a1i * cr;
+                    a0r = t0r; a0i = t0i; a1r = t1r; a1i = t1i;
+                    flush();
+                } else if (cr != 1.0 || ci != 0.0) {
+#pragma unroll
+                    for (int s = 0; s < PER; ++s) v[s] = cmul<double2, double>(cr, ci, v[s]);
+                }
+#pragma unroll
+                for (int s = 0; s < PER; ++s) {
+                    const uint32_t e = tid + 256 * s;
+                    if (E >= 256 || e < E) tile[e] = st2<V>(v[s]);
+                }
+                o = o2 - 1;
             }
             __syncthreads();
         }
@@ -183,7 +350,13 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
 #pragma unroll
             for (int s = 0; s < PER; ++s) {
                 const uint32_t e = tid + 256 * s;
-                if (e < E) psi[base | (e & lowm) | ((uint64_t)hoff[e >> L] << L)] = tile[e];
+                if (e < E) {
+                    V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
+                    if (nt)
+                        gst<true>(a, tile[e]);
+                    else
+                        gst<false>(a, tile[e]);
+                }
             }
         }
         __syncthreads();
@@ -220,8 +393,12 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     if (lds > 163840) return hipErrorInvalidValue;
     static int cap = env_int("QS_TILE_GRID_CAP", 256 * 8);
     const unsigned g = (unsigned)(ntiles < (uint64_t)cap ? ntiles : (uint64_t)cap);
+    // non-temporal when each contiguous run covers whole 128-byte lines
+    const int line_bits = sizeof(R) == 8 ? 3 : 4;
+    static int nt_env = env_int("QS_NT", 1);
+    const int nt = (nt_env && pass.L >= line_bits) ? 1 : 0;
     hipLaunchKernelGGL((k_tile<R, M>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                       (int)pass.ops.size(), (const double*)dmats);
+                       (int)pass.ops.size(), (const double*)dmats, nt);
     return hipGetLastError();
 }
 

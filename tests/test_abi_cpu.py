@@ -115,3 +115,17 @@ def test_planner_groups_gates(qs):
     ops, mats = r.arrays()
     npass, nops = qs.qs_plan_circuit(32, qs.QS_C64, ops, mats, tile_qubits=12)
     assert nops == len(ops) and npass <= 20 * 6
+
+
+def test_planner_fuses_blocks_for_c64(qs, monkeypatch):
+    monkeypatch.setenv("QS_FUSE_MIN", "2")
+    r = W.rqc_chain(20, 10, 1)
+    ops, mats = r.arrays()
+    plain = qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, tile_qubits=12)
+    fused = qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, tile_qubits=12, fuse_k=5)
+    assert fused[0] == plain[0] and fused[1] < 0.6 * plain[1]
+    # complex128 states never get FP32 matrix-core blocks
+    assert qs.qs_plan_circuit(20, qs.QS_C128, ops, mats, tile_qubits=12, fuse_k=5) == \
+        qs.qs_plan_circuit(20, qs.QS_C128, ops, mats, tile_qubits=12)
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, fuse_k=3)

@@ -285,3 +285,18 @@ def test_error_leaves_state_untouched(qs):
     with pytest.raises(qs.QSError):
         s.apply_1q(1, W.H, 1 << 1)
     assert np.array_equal(s.download(), psi0)
+
+
+@pytest.mark.parametrize("name", list(CIRCS))
+@pytest.mark.parametrize("fk,tq,fmin", [(4, 0, 1), (5, 0, 1), (5, 9, 1), (4, 8, 2), (5, 13, 3)])
+def test_fused_mfma_blocks_c64(qs, name, fk, tq, fmin, monkeypatch):
+    monkeypatch.setenv("QS_FUSE_MIN", str(fmin))
+    c = CIRCS[name]()
+    n = c.n
+    ops, mats = c.arrays()
+    npass, nops = qs.qs_plan_circuit(n, qs.QS_C64, ops, mats, fuse_k=fk, tile_qubits=tq)
+    psi0 = _rand(n, 11) if name in ("rqc14", "bench16") else None
+    want = oracle.run(n, ops, mats, psi0, c.init_basis)
+    s = _state(qs, n, 1, psi0, c.init_basis)
+    s.run(ops, mats, mode=0, fuse_k=fk, tile_qubits=tq)
+    _check(s.download(), want, 1, f"{name} fuse_k={fk} tq={tq} ({nops} ops in {npass} passes)")
