@@ -182,6 +182,67 @@ qs_status qs_norm(qs_state s, double* out);
 /* Wait for all work enqueued on the state. */
 qs_status qs_sync(qs_state s);
 
+/* ------------------------------------------------------------------ batches */
+
+typedef struct qs_batch_s* qs_batch;
+
+/* One circuit of a batch: n qubits, initial basis state, op table and matrix
+ * pool exactly as for qs_run_circuit. */
+typedef struct {
+    int32_t n;
+    int32_t rsv0;
+    uint64_t init_basis;
+    const qs_op* ops;
+    int64_t n_ops;
+    const double* mats;
+    int64_t n_mats;
+} qs_circuit;
+
+typedef struct {
+    int32_t dtype;       /* QS_C64 or QS_C128 (0 = QS_C128) for every state of the batch */
+    int32_t mode;        /* 0 = fused (LDS-resident / persistent / tile passes), 1 = one launch per gate */
+    int32_t streams;     /* HIP streams the batch spreads over (0 = 8) */
+    int32_t fuse_k;      /* as in qs_run_opts */
+    int32_t tile_qubits; /* as in qs_run_opts */
+    int32_t rsv[3];
+} qs_batch_opts;
+
+typedef struct {
+    uint64_t launches;   /* kernel launches enqueued */
+    uint64_t passes;     /* tile passes planned (fused mode) */
+    double device_ms;    /* first event to last completion, after qs_batch_wait */
+    double class_ms[3];  /* fused mode: completion of the LDS-resident, persistent and
+                            pass-major classes, from the same first event (0 if empty) */
+    uint32_t class_circuits[3];
+    uint32_t rsv;
+} qs_batch_stats;
+
+/* Run `count` independent circuits (batching survey item; the paper times one
+ * circuit at a time, Section III).  All circuits are validated first (nothing
+ * is enqueued if one is invalid), then one device arena is allocated for all
+ * final states and the work is enqueued on the batch's own streams; the call
+ * returns without waiting.  Each circuit's result equals running it alone with
+ * qs_run_circuit (mode 0) or gate by gate (mode 1); it does not depend on the
+ * other circuits of the batch.  The caller's tables may be freed on return. */
+qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_opts* opts, qs_batch* out);
+
+/* Wait until the batch is done (timeout_ms < 0: no limit).  QS_ERR_TIMEOUT if
+ * it is still running after timeout_ms; the batch stays valid. */
+qs_status qs_batch_wait(qs_batch b, int timeout_ms);
+
+/* Device pointer and qubit count of circuit i's final state (owned by the
+ * batch; valid until qs_batch_release; complete after qs_batch_wait). */
+qs_status qs_batch_state(qs_batch b, int i, void** dev_ptr, int* n);
+
+/* Copy circuit i's final state to host memory (2^n elements of the batch
+ * dtype); waits for the batch first. */
+qs_status qs_batch_download(qs_batch b, int i, void* host);
+
+qs_status qs_batch_get_stats(qs_batch b, qs_batch_stats* out);
+
+/* Wait for outstanding work and free the batch (NULL accepted). */
+qs_status qs_batch_release(qs_batch b);
+
 /* ------------------------------------------------------------------ tracing */
 
 /* One traced kernel launch. */

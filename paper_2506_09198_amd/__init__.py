@@ -37,6 +37,22 @@ class QSError(RuntimeError):
         self.status = status
 
 
+class _Circuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("rsv0", ctypes.c_int32), ("init_basis", ctypes.c_uint64),
+                ("ops", ctypes.c_void_p), ("n_ops", ctypes.c_int64), ("mats", ctypes.c_void_p),
+                ("n_mats", ctypes.c_int64)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("mode", ctypes.c_int32), ("streams", ctypes.c_int32),
+                ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32), ("rsv", ctypes.c_int32 * 3)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("device_ms", ctypes.c_double),
+                ("class_ms", ctypes.c_double * 3), ("class_circuits", ctypes.c_uint32 * 3), ("rsv", ctypes.c_uint32)]
+
+
 class _RunOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
                 ("rsv", ctypes.c_int32 * 5)]
@@ -76,6 +92,12 @@ def _load():
         "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
         "qs_norm": ([vp, dp], i32),
         "qs_sync": ([vp], i32),
+        "qs_batch_submit": ([ctypes.POINTER(_Circuit), i32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(vp)], i32),
+        "qs_batch_wait": ([vp, i32], i32),
+        "qs_batch_state": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i32)], i32),
+        "qs_batch_download": ([vp, i32, vp], i32),
+        "qs_batch_get_stats": ([vp, ctypes.POINTER(_BatchStats)], i32),
+        "qs_batch_release": ([vp], i32),
         "qs_trace_enable": ([vp, i32], i32),
         "qs_trace_read": ([vp, vp, i32, ctypes.POINTER(i32)], i32),
     }
@@ -240,6 +262,54 @@ def qs_norm(s: int) -> float:
 
 def qs_sync(s: int):
     _check(lib.qs_sync(ctypes.c_void_p(s)))
+
+
+def qs_batch_submit(circuits, dtype: int = QS_C128, mode: int = 0, streams: int = 0, fuse_k: int = 0,
+                    tile_qubits: int = 0) -> int:
+    """circuits: iterable of (n, ops, mats, init_basis) or objects with .n/.arrays()/.init_basis."""
+    keep, arr = [], (_Circuit * max(1, len(circuits)))()
+    for i, c in enumerate(circuits):
+        if hasattr(c, "arrays"):
+            n, (ops, mats), basis = c.n, c.arrays(), c.init_basis
+        else:
+            n, ops, mats, basis = c
+        ops = np.ascontiguousarray(ops)
+        mats = np.ascontiguousarray(mats, dtype=np.float64)
+        keep.append((ops, mats))
+        arr[i] = _Circuit(n, 0, int(basis), ops.ctypes.data if len(ops) else 0, len(ops),
+                          mats.ctypes.data if mats.size else 0, mats.size)
+    o = _BatchOpts(dtype, mode, streams, fuse_k, tile_qubits)
+    h = ctypes.c_void_p()
+    _check(lib.qs_batch_submit(arr, len(circuits), ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def qs_batch_wait(b: int, timeout_ms: int = -1):
+    _check(lib.qs_batch_wait(ctypes.c_void_p(b), timeout_ms))
+
+
+def qs_batch_state(b: int, i: int):
+    p, n = ctypes.c_void_p(), ctypes.c_int()
+    _check(lib.qs_batch_state(ctypes.c_void_p(b), i, ctypes.byref(p), ctypes.byref(n)))
+    return p.value, n.value
+
+
+def qs_batch_download(b: int, i: int, dtype: int = QS_C128) -> np.ndarray:
+    _, n = qs_batch_state(b, i)
+    out = np.empty(1 << n, dtype=_np_dtype(dtype))
+    _check(lib.qs_batch_download(ctypes.c_void_p(b), i, ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+def qs_batch_get_stats(b: int) -> dict:
+    st = _BatchStats()
+    _check(lib.qs_batch_get_stats(ctypes.c_void_p(b), ctypes.byref(st)))
+    return {"launches": st.launches, "passes": st.passes, "device_ms": st.device_ms,
+            "class_ms": list(st.class_ms), "class_circuits": list(st.class_circuits)}
+
+
+def qs_batch_release(b: int):
+    _check(lib.qs_batch_release(ctypes.c_void_p(b)))
 
 
 def qs_trace_enable(s: int, on: bool = True):

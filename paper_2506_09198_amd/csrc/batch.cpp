@@ -1,0 +1,454 @@
+// Batched execution of many independent circuits (qs_batch_*).
+//
+// All final states live in one device arena.  Mode 0 (fused) sorts circuits by
+// size:
+//   - "whole": n at most the largest LDS tile -- each circuit runs entirely in
+//     one workgroup's LDS; one launch per distinct n covers all of them, and
+//     their states touch HBM once, when written;
+//   - "persistent": medium n -- one workgroup per circuit walks the circuit's
+//     tile passes over its state (block barriers only, no grid-wide sync);
+//     one launch per tile size covers all of them;
+//   - "streamed": large n -- pass-major rounds: launch r processes pass r of
+//     every large circuit that has one (each block one tile), so the launch
+//     count is the longest pass list, not the sum of all of them.
+// Mode 1 launches every gate separately (the per-gate kernels), circuits spread
+// over the streams: the unfused reference the fused mode is compared against.
+#include <chrono>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "planner.h"
+#include "runtime.h"
+
+using namespace qs;
+
+struct qs_batch_s {
+    int dt = QS_C128;
+    int mode = 0;
+    int count = 0;
+    char* arena = nullptr;
+    uint64_t arena_bytes = 0;
+    char* dbuf = nullptr; // descriptors, passes, ops, matrices
+    uint64_t dbuf_bytes = 0;
+    char* hbuf = nullptr; // pinned staging for dbuf
+    std::vector<uint64_t> off;
+    std::vector<int> n;
+    std::vector<hipStream_t> st;
+    std::vector<hipEvent_t> done;
+    hipEvent_t t0 = nullptr;
+    hipEvent_t cls_done[3] = {nullptr, nullptr, nullptr};
+    bool failed = false;
+    qs_batch_stats stats;
+};
+
+namespace {
+
+qs_status bfail(qs_batch b, hipError_t e, const char* what)
+{
+    b->failed = true;
+    (void)hipGetLastError();
+    return set_err(QS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void release(qs_batch b)
+{
+    if (!b) return;
+    for (hipStream_t s : b->st) (void)hipStreamSynchronize(s);
+    for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+    if (b->t0) (void)hipEventDestroy(b->t0);
+    for (hipEvent_t e : b->cls_done)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->st) (void)hipStreamDestroy(s);
+    if (b->arena) dev_free(b->arena, b->arena_bytes);
+    if (b->dbuf) dev_free(b->dbuf, b->dbuf_bytes);
+    if (b->hbuf) (void)hipHostFree(b->hbuf);
+    (void)hipGetLastError();
+    delete b;
+}
+
+int whole_max(int dt)
+{
+    const int e = env_int("QS_BATCH_WHOLE_MAX", 0);
+    if (e > 0) return e;
+    return dt == QS_C128 ? 12 : 13; // 64 KiB of LDS
+}
+
+int persist_max(int dt)
+{
+    const int e = env_int("QS_BATCH_PERSIST_MAX", 0);
+    if (e > 0) return e;
+    return dt == QS_C128 ? 15 : 16;
+}
+
+} // namespace
+
+extern "C" {
+
+qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_opts* opts, qs_batch* out)
+{
+    if (!out) return set_err(QS_ERR_ARG, "null output pointer");
+    *out = nullptr;
+    if (count < 0 || (count > 0 && !circuits)) return set_err(QS_ERR_ARG, "bad circuit list");
+    qs_batch_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    if (o.dtype == 0) o.dtype = QS_C128;
+    if (o.dtype != QS_C64 && o.dtype != QS_C128) return set_err(QS_ERR_ARG, "unknown dtype %d", o.dtype);
+    if (o.mode != 0 && o.mode != 1) return set_err(QS_ERR_ARG, "unknown batch mode %d", o.mode);
+    if (o.streams <= 0) o.streams = 8;
+    if (o.streams > 64) return set_err(QS_ERR_ARG, "streams=%d > 64", o.streams);
+    for (int i = 0; i < count; ++i) {
+        const qs_circuit& c = circuits[i];
+        if (c.n < 1 || c.n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "circuit %d: n=%d outside [1, %d]", i, c.n, QS_MAX_QUBITS);
+        if (c.init_basis >= (1ull << c.n)) return set_err(QS_ERR_ARG, "circuit %d: basis state out of range", i);
+        qs_status st = validate_circuit(c.n, c.ops, c.n_ops, c.mats, c.n_mats);
+        if (st != QS_OK) return set_err(st, "circuit %d: %s", i, qs_last_error());
+    }
+    if (qs_device_count() < 1) return set_err(QS_ERR_DEVICE, "no HIP device available");
+
+    qs_batch b = new qs_batch_s();
+    std::memset(&b->stats, 0, sizeof b->stats);
+    b->dt = o.dtype;
+    b->mode = o.mode;
+    b->count = count;
+    const uint64_t S = amp_bytes(b->dt);
+    // arena layout
+    uint64_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        b->off.push_back(total);
+        b->n.push_back(circuits[i].n);
+        total += ((S << circuits[i].n) + 255) & ~255ull;
+    }
+    b->arena_bytes = total ? total : 256;
+    qs_status st = dev_alloc((void**)&b->arena, b->arena_bytes, "batch arena");
+    if (st != QS_OK) {
+        release(b);
+        return st;
+    }
+    for (int i = 0; i < o.streams; ++i) {
+        hipStream_t s;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            qs_status r = bfail(b, e, "hipStreamCreate");
+            release(b);
+            return r;
+        }
+        b->st.push_back(s);
+        hipEvent_t ev;
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            qs_status r = bfail(b, e, "hipEventCreate");
+            release(b);
+            return r;
+        }
+        b->done.push_back(ev);
+    }
+    hipError_t e = hipEventCreate(&b->t0);
+    if (e == hipSuccess) e = hipEventRecord(b->t0, b->st[0]);
+    if (e != hipSuccess) {
+        qs_status r = bfail(b, e, "hipEventRecord");
+        release(b);
+        return r;
+    }
+    for (size_t i = 1; i < b->st.size(); ++i) (void)hipStreamWaitEvent(b->st[i], b->t0, 0);
+
+    // ------------------------------------------------------------ plan
+    enum { C_WHOLE = 0, C_PERSIST = 1, C_STREAM = 2 };
+    std::vector<int> cls(count, C_STREAM);
+    std::vector<BatchCirc> bc(count);
+    std::vector<BatchPass> bpass;
+    std::vector<TileOp> bops;
+    std::vector<double> bmats;
+    int persist_m = 0, stream_m = 0;
+    for (int i = 0; i < count; ++i) {
+        const qs_circuit& c = circuits[i];
+        std::memset(&bc[i], 0, sizeof(BatchCirc));
+        bc[i].psi_off = b->off[i];
+        bc[i].basis = c.init_basis;
+        bc[i].n = c.n;
+        if (b->mode == 1) continue;
+        PlanOpts po;
+        st = plan_opts_for(b->dt, c.ops, c.n_ops, o.fuse_k, o.tile_qubits, po);
+        if (st != QS_OK) {
+            release(b);
+            return st;
+        }
+        if (c.n <= whole_max(b->dt)) {
+            cls[i] = C_WHOLE;
+            po.m = c.n;
+        } else if (c.n <= persist_max(b->dt)) {
+            cls[i] = C_PERSIST;
+            if (persist_m == 0) persist_m = std::min(po.m, 13);
+            po.m = persist_m;
+        } else {
+            if (stream_m == 0) stream_m = std::min(po.m, 13);
+            po.m = stream_m;
+        }
+        std::vector<PlanPass> passes;
+        std::vector<double> pool;
+        if (c.n_ops > 0) plan_circuit(c.n, c.ops, c.n_ops, c.mats, po, passes, pool);
+        const size_t pool_base = bmats.size() + (bmats.size() & 1); // keep 16-byte alignment
+        bmats.resize(pool_base);
+        bmats.insert(bmats.end(), pool.begin(), pool.end());
+        bc[i].pass0 = (int)bpass.size();
+        bc[i].npass = (int)passes.size();
+        for (auto& p : passes) {
+            BatchPass d;
+            std::memset(&d, 0, sizeof d);
+            d.m = p.m;
+            d.L = p.L;
+            uint64_t qm = 0;
+            for (int j = 0; j < p.m; ++j) {
+                d.q[j] = p.Q[j];
+                qm |= 1ull << p.Q[j];
+            }
+            d.ip = make_insert_plan(qm);
+            d.op0 = (int)bops.size();
+            d.nops = (int)p.ops.size();
+            for (TileOp t : p.ops) {
+                t.moff += pool_base;
+                bops.push_back(t);
+            }
+            bpass.push_back(d);
+            b->stats.passes += 1;
+        }
+    }
+    // per-gate mode: stage every circuit's matrices (dense k > 2 gates read them)
+    std::vector<size_t> gate_pool_base(count, 0);
+    if (b->mode == 1) {
+        for (int i = 0; i < count; ++i) {
+            gate_pool_base[i] = bmats.size();
+            bmats.insert(bmats.end(), circuits[i].mats, circuits[i].mats + circuits[i].n_mats);
+        }
+    }
+    // pass-major rounds over the streamed circuits: round r = pass r of each
+    std::vector<RoundEntry> rents;
+    std::vector<std::pair<size_t, std::pair<int, uint32_t>>> rounds; // (entry offset, (count, blocks))
+    if (b->mode == 0) {
+        int maxp = 0;
+        for (int i = 0; i < count; ++i)
+            if (cls[i] == C_STREAM) maxp = std::max(maxp, bc[i].npass);
+        for (int r = 0; r < maxp; ++r) {
+            const size_t e0 = rents.size();
+            uint32_t blocks = 0;
+            for (int i = 0; i < count; ++i) {
+                if (cls[i] != C_STREAM || bc[i].npass <= r) continue;
+                RoundEntry en;
+                en.circ = i;
+                en.pass = bc[i].pass0 + r;
+                en.first_block = blocks;
+                en.rsv = 0;
+                rents.push_back(en);
+                blocks += (uint32_t)(1u << (bc[i].n - stream_m));
+            }
+            rounds.push_back({e0, {(int)(rents.size() - e0), blocks}});
+        }
+    }
+    std::vector<int32_t> lists;
+    std::vector<std::pair<int, std::pair<size_t, int>>> whole_groups; // (n, (list offset, count))
+    for (int nn = 1; nn <= 13; ++nn) {
+        const size_t l0 = lists.size();
+        for (int i = 0; i < count; ++i)
+            if (cls[i] == C_WHOLE && bc[i].n == nn && b->mode == 0) lists.push_back(i);
+        if (lists.size() > l0) whole_groups.push_back({nn, {l0, (int)(lists.size() - l0)}});
+    }
+    const size_t persist_l0 = lists.size();
+    for (int i = 0; i < count; ++i)
+        if (cls[i] == C_PERSIST && b->mode == 0) lists.push_back(i);
+    const int persist_count = (int)(lists.size() - persist_l0);
+    const size_t stream_l0 = lists.size();
+    for (int i = 0; i < count; ++i)
+        if (cls[i] == C_STREAM && b->mode == 0) lists.push_back(i);
+    const int stream_count = (int)(lists.size() - stream_l0);
+
+    // ------------------------------------------------------------ upload
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t o_circ = 0;
+    const uint64_t o_pass = al(o_circ + bc.size() * sizeof(BatchCirc));
+    const uint64_t o_ops = al(o_pass + bpass.size() * sizeof(BatchPass));
+    const uint64_t o_list = al(o_ops + bops.size() * sizeof(TileOp));
+    const uint64_t o_ents = al(o_list + lists.size() * sizeof(int32_t));
+    const uint64_t o_mats = al(o_ents + rents.size() * sizeof(RoundEntry));
+    b->dbuf_bytes = al(o_mats + bmats.size() * sizeof(double)) + 256;
+    if ((st = dev_alloc((void**)&b->dbuf, b->dbuf_bytes, "batch descriptors")) != QS_OK) {
+        release(b);
+        return st;
+    }
+    e = hipHostMalloc((void**)&b->hbuf, b->dbuf_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        release(b);
+        (void)hipGetLastError();
+        return set_err(QS_ERR_OOM, "hipHostMalloc(%llu) failed", (unsigned long long)b->dbuf_bytes);
+    }
+    std::memcpy(b->hbuf + o_circ, bc.data(), bc.size() * sizeof(BatchCirc));
+    std::memcpy(b->hbuf + o_pass, bpass.data(), bpass.size() * sizeof(BatchPass));
+    std::memcpy(b->hbuf + o_ops, bops.data(), bops.size() * sizeof(TileOp));
+    std::memcpy(b->hbuf + o_list, lists.data(), lists.size() * sizeof(int32_t));
+    std::memcpy(b->hbuf + o_ents, rents.data(), rents.size() * sizeof(RoundEntry));
+    std::memcpy(b->hbuf + o_mats, bmats.data(), bmats.size() * sizeof(double));
+    hipStream_t s0 = b->st[0];
+    e = hipMemcpyAsync(b->dbuf, b->hbuf, b->dbuf_bytes, hipMemcpyHostToDevice, s0);
+    if (e != hipSuccess) {
+        qs_status r = bfail(b, e, "batch upload");
+        release(b);
+        return r;
+    }
+    const BatchCirc* dcirc = (const BatchCirc*)(b->dbuf + o_circ);
+    const BatchPass* dpass = (const BatchPass*)(b->dbuf + o_pass);
+    const TileOp* dops = (const TileOp*)(b->dbuf + o_ops);
+    const int32_t* dlist = (const int32_t*)(b->dbuf + o_list);
+    const RoundEntry* dents = (const RoundEntry*)(b->dbuf + o_ents);
+    const double* dmats = (const double*)(b->dbuf + o_mats);
+    if (b->mode == 0 && stream_count > 0) {
+        // zero the arena and set the streamed circuits' basis amplitudes before
+        // any other stream writes a state into it
+        e = launch_batch_init(b->dt, b->arena, b->arena_bytes, dcirc, dlist + stream_l0, stream_count, s0);
+        b->stats.launches += 2;
+        if (e != hipSuccess) {
+            qs_status r = bfail(b, e, "batch init launch");
+            release(b);
+            return r;
+        }
+    }
+    hipEvent_t up;
+    (void)hipEventCreate(&up);
+    (void)hipEventRecord(up, s0);
+    for (size_t i = 1; i < b->st.size(); ++i) (void)hipStreamWaitEvent(b->st[i], up, 0);
+    (void)hipEventDestroy(up);
+
+    // ------------------------------------------------------------ launch
+    auto launched = [&](hipError_t err, const char* what) -> qs_status {
+        b->stats.launches += 1;
+        if (err != hipSuccess) return bfail(b, err, what);
+        return QS_OK;
+    };
+    const int NS = (int)b->st.size();
+    bool any_mfma = false;
+    for (const TileOp& t : bops) any_mfma |= t.kind == TK_MFMA;
+    if (b->mode == 0) {
+        // whole circuits on stream 0, persistent ones on stream 1 (if any), the
+        // rest round-robin over the remaining streams
+        auto mark = [&](int k, hipStream_t s) {
+            if (hipEventCreate(&b->cls_done[k]) == hipSuccess) (void)hipEventRecord(b->cls_done[k], s);
+        };
+        for (int i = 0; i < count; ++i) b->stats.class_circuits[cls[i]] += 1;
+        for (auto& g : whole_groups) {
+            st = launched(launch_batch_whole(b->dt, g.first, b->arena, dcirc, dlist + g.second.first,
+                                             g.second.second, dpass, dops, dmats, any_mfma, s0),
+                          "batch whole launch");
+            if (st != QS_OK) break;
+        }
+        if (!whole_groups.empty()) mark(0, s0);
+        if (st == QS_OK && persist_count > 0) {
+            st = launched(launch_batch_persist(b->dt, persist_m, b->arena, dcirc, dlist + persist_l0, persist_count,
+                                               dpass, dops, dmats, any_mfma, b->st[NS > 1 ? 1 : 0]),
+                          "batch persistent launch");
+            mark(1, b->st[NS > 1 ? 1 : 0]);
+        }
+        hipStream_t sr = b->st[NS > 2 ? 2 : 0];
+        for (size_t r = 0; r < rounds.size() && st == QS_OK; ++r)
+            st = launched(launch_batch_round(b->dt, stream_m, b->arena, dcirc, dpass, dops, dmats,
+                                             dents + rounds[r].first, rounds[r].second.first,
+                                             rounds[r].second.second, any_mfma, sr),
+                          "batch round launch");
+        if (!rounds.empty()) mark(2, sr);
+    } else {
+        for (int i = 0; i < count && st == QS_OK; ++i) {
+            const qs_circuit& c = circuits[i];
+            hipStream_t s = b->st[i % NS];
+            void* psi = b->arena + b->off[i];
+            st = launched(launch_init_basis(psi, b->dt, c.n, c.init_basis, s), "batch init launch");
+            for (int64_t g = 0; g < c.n_ops && st == QS_OK; ++g) {
+                const qs_op& op = c.ops[g];
+                const double* U = c.mats + op.moff;
+                int kind;
+                hipError_t err;
+                if (op.nt == 1)
+                    err = launch_apply_1q(psi, b->dt, c.n, op.t[0], U, op.cmask, op.cvals, s, &kind);
+                else if (op.nt == 2)
+                    err = launch_apply_2q(psi, b->dt, c.n, op.t[0], op.t[1], U, op.cmask, op.cvals, s, &kind);
+                else
+                    err = launch_apply_kq_dev(psi, b->dt, c.n, op.t, op.nt, dmats + gate_pool_base[i] + op.moff,
+                                              op.cmask, op.cvals, s, &kind);
+                st = launched(err, "batch gate launch");
+            }
+        }
+    }
+    for (int i = 0; i < NS; ++i) {
+        e = hipEventRecord(b->done[i], b->st[i]);
+        if (e != hipSuccess && st == QS_OK) st = bfail(b, e, "hipEventRecord");
+    }
+    if (st != QS_OK) {
+        release(b);
+        return st;
+    }
+    *out = b;
+    return QS_OK;
+}
+
+qs_status qs_batch_wait(qs_batch b, int timeout_ms)
+{
+    if (!b) return set_err(QS_ERR_ARG, "null batch handle");
+    if (b->failed) return set_err(QS_ERR_DEVICE, "batch is in the failed state");
+    const auto t_end = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms);
+    for (;;) {
+        bool all = true;
+        for (hipEvent_t ev : b->done) {
+            hipError_t e = hipEventQuery(ev);
+            if (e == hipErrorNotReady) {
+                all = false;
+                (void)hipGetLastError();
+            } else if (e != hipSuccess) {
+                return bfail(b, e, "batch execution");
+            }
+        }
+        if (all) break;
+        if (timeout_ms >= 0 && std::chrono::steady_clock::now() >= t_end)
+            return set_err(QS_ERR_TIMEOUT, "batch not finished after %d ms", timeout_ms);
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    float ms = 0.f, best = 0.f;
+    for (hipEvent_t ev : b->done)
+        if (hipEventElapsedTime(&ms, b->t0, ev) == hipSuccess && ms > best) best = ms;
+    b->stats.device_ms = best;
+    for (int k = 0; k < 3; ++k)
+        if (b->cls_done[k] && hipEventElapsedTime(&ms, b->t0, b->cls_done[k]) == hipSuccess) b->stats.class_ms[k] = ms;
+    return QS_OK;
+}
+
+qs_status qs_batch_state(qs_batch b, int i, void** dev_ptr, int* n)
+{
+    if (!b) return set_err(QS_ERR_ARG, "null batch handle");
+    if (i < 0 || i >= b->count) return set_err(QS_ERR_ARG, "circuit index %d outside [0, %d)", i, b->count);
+    if (dev_ptr) *dev_ptr = b->arena + b->off[i];
+    if (n) *n = b->n[i];
+    return QS_OK;
+}
+
+qs_status qs_batch_download(qs_batch b, int i, void* host)
+{
+    if (!b) return set_err(QS_ERR_ARG, "null batch handle");
+    if (i < 0 || i >= b->count) return set_err(QS_ERR_ARG, "circuit index %d outside [0, %d)", i, b->count);
+    if (!host) return set_err(QS_ERR_ARG, "null host buffer");
+    qs_status st = qs_batch_wait(b, -1);
+    if (st != QS_OK) return st;
+    hipError_t e = hipMemcpy(host, b->arena + b->off[i], amp_bytes(b->dt) << b->n[i], hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bfail(b, e, "batch download");
+    return QS_OK;
+}
+
+qs_status qs_batch_get_stats(qs_batch b, qs_batch_stats* out)
+{
+    if (!b || !out) return set_err(QS_ERR_ARG, "null argument");
+    *out = b->stats;
+    return QS_OK;
+}
+
+qs_status qs_batch_release(qs_batch b)
+{
+    release(b);
+    return QS_OK;
+}
+
+} // extern "C"

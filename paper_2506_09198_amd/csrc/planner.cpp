@@ -252,6 +252,8 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
                 } else if (nlt == 0 && nlc == 1) {
                     t.dclass = DG_LCONTROL;
                     t.dbit = (int8_t)__builtin_ctzll(t.lcm);
+                } else if (nlt == 1 && nlc == 1) {
+                    t.dclass = DG_CT;
                 } else {
                     t.dclass = DG_GENERAL;
                 }
@@ -313,13 +315,18 @@ static int default_low_qubits(int dt)
 
 static qs_status plan_opts(int dt, const qs_op* ops, int64_t n_ops, const qs_run_opts& o, PlanOpts& po)
 {
-    po.m = o.tile_qubits > 0 ? o.tile_qubits : default_tile_qubits(dt);
+    return plan_opts_for(dt, ops, n_ops, o.fuse_k, o.tile_qubits, po);
+}
+
+qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int tile_qubits, PlanOpts& po)
+{
+    po.m = tile_qubits > 0 ? tile_qubits : default_tile_qubits(dt);
     if (po.m > 13) return set_err(QS_ERR_ARG, "tile_qubits=%d > 13", po.m);
     int maxk = 1;
     for (int64_t g = 0; g < n_ops; ++g) maxk = std::max(maxk, (int)ops[g].nt);
     po.m = std::max(po.m, maxk);
     po.L = default_low_qubits(dt);
-    po.fuse_k = o.fuse_k > 0 ? o.fuse_k : env_int("QS_FUSE_K", 0);
+    po.fuse_k = fuse_k > 0 ? fuse_k : env_int("QS_FUSE_K", 0);
     po.fuse_min = env_int("QS_FUSE_MIN", 3);
     po.dt = dt;
     if (po.fuse_k != 0 && po.fuse_k != 4 && po.fuse_k != 5)
@@ -378,8 +385,6 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
     }
     return QS_OK;
 }
-
-qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats);
 
 } // namespace qs
 

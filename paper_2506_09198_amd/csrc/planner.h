@@ -29,7 +29,8 @@ struct TileOp {
     // TK_DIAG only: tile-local position of each target (-1 outside the tile),
     // and the shape class the kernel folds per tile: DG_UNIFORM (no local bit:
     // one factor for the whole tile), DG_LTARGET (one local target, no local
-    // control), DG_LCONTROL (no local target, one local control), DG_GENERAL.
+    // control), DG_LCONTROL (no local target, one local control), DG_CT (one
+    // local target and one local control), DG_GENERAL.
     int8_t lp[6];
     int8_t dclass;
     int8_t dbit; // the local bit of DG_LTARGET / DG_LCONTROL
@@ -37,7 +38,7 @@ struct TileOp {
     int32_t rsv;
 };
 static_assert(sizeof(TileOp) == 88, "TileOp layout");
-enum { DG_UNIFORM = 0, DG_LTARGET = 1, DG_LCONTROL = 2, DG_GENERAL = 3 };
+enum { DG_UNIFORM = 0, DG_LTARGET = 1, DG_LCONTROL = 2, DG_GENERAL = 3, DG_CT = 4 };
 
 struct PlanPass {
     int m = 0;                 // tile qubits
@@ -60,6 +61,57 @@ struct PlanOpts {
 // interleaved complex); the executor converts it to the state's real type.
 void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po,
                   std::vector<PlanPass>& passes, std::vector<double>& mats_out);
+
+// ---------------------------------------------------------------- batches
+
+// Pass descriptor in device memory (persistent batch kernels read it there).
+struct BatchPass {
+    int32_t m, L;
+    int32_t q[QS_MAX_QUBITS];
+    InsertPlan ip; // tile qubits, inserted into the tile counter
+    int32_t op0, nops;
+};
+
+// Circuit descriptor in device memory.
+struct BatchCirc {
+    uint64_t psi_off; // byte offset of the state inside the batch arena
+    uint64_t basis;   // initial basis state
+    int32_t n;
+    int32_t pass0, npass;
+    int32_t rsv;
+};
+
+// One launch for `count` circuits listed in `list`: every circuit of n = M
+// qubits runs whole in one block's LDS (initial basis state built in LDS; the
+// final state written once).
+hipError_t launch_batch_whole(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
+                              const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                              hipStream_t st);
+// One launch for `count` circuits whose passes all use tile size M: one block
+// per circuit initialises its state and loops over its passes and tiles.
+hipError_t launch_batch_persist(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list,
+                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                                hipStream_t st);
+
+// One entry of a pass-major round: blocks [first_block, first_block + 2^(n-m))
+// of the round's launch process the tiles of pass `pass` of circuit `circ`.
+struct RoundEntry {
+    int32_t circ;
+    int32_t pass;
+    uint32_t first_block;
+    uint32_t rsv;
+};
+
+// One launch covering the same pass index of many circuits (all with tile size M).
+hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
+                              const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
+                              uint32_t nblocks, bool mf, hipStream_t st);
+// Zero `bytes` bytes of the arena and set each listed circuit's basis amplitude.
+hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCirc* circs, const int32_t* list,
+                             int count, hipStream_t st);
+
+qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats);
+qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int tile_qubits, PlanOpts& po);
 
 qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats,
                       const qs_run_opts& o);

@@ -106,70 +106,46 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
     }
 }
 
-template <typename R, int M>
-__global__ void __launch_bounds__(256)
-k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
-       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
+// Apply a pass's operation list to the tile held in LDS (all lanes of the
+// block call this; it ends with the tile complete in LDS).  `base` is the
+// global index of tile element 0 (tile bits zero).
+template <typename R, int M, bool MF>
+__device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base, const TileOp* __restrict__ ops,
+                                         int nops, const double* __restrict__ mats)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
     constexpr int PER = (E + 255) / 256; // tile elements per lane
-    extern __shared__ __align__(16) unsigned char smem[];
-    V* tile = (V*)smem;
-    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E); // dep_Q of the upper tile bits, >> L
-    const int L = ql.L;
-    const uint32_t H = 1u << (M - L);
-    for (uint32_t h = threadIdx.x; h < H; h += 256) {
-        uint64_t off = 0;
-        for (int j = L; j < M; ++j)
-            if ((h >> (j - L)) & 1) off |= 1ull << ql.q[j];
-        hoff[h] = (uint32_t)(off >> L);
-    }
-    __syncthreads();
-    const uint32_t lowm = (1u << L) - 1;
     const int tid = threadIdx.x;
-    for (uint64_t tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
-        const uint64_t base = ins_bits(tau, ipQ);
-        {
-            // all loads of the tile are issued before the first LDS write
-            R rx[PER], ry[PER];
-#pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const uint32_t e = tid + 256 * s;
-                if (E >= 256 || e < E) {
-                    const V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
-                    const V v = nt ? gld<true>(a) : gld<false>(a);
-                    rx[s] = v.x;
-                    ry[s] = v.y;
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const uint32_t e = tid + 256 * s;
-                if (E >= 256 || e < E) {
-                    V v;
-                    v.x = rx[s];
-                    v.y = ry[s];
-                    tile[e] = v;
-                }
-            }
-        }
-        __syncthreads();
-        for (int o = 0; o < nops; ++o) {
-            const TileOp& d = ops[o];
-            const int kind = d.kind;
-            if (kind != TK_DIAG && (base & d.gcm) != d.gcv) continue; // tile fails the outside controls
-            const double* u = mats + d.moff;
-            const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
-            if (kind == TK_DENSE1) {
-                const int p = d.p[0];
-                const double u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3], u4 = u[4], u5 = u[5], u6 = u[6],
-                             u7 = u[7];
-#pragma unroll
+    for (int o = 0; o < nops; ++o) {
+        const TileOp& d = ops[o];
+        const int kind = d.kind;
+        if (kind != TK_DIAG && (base & d.gcm) != d.gcv) continue; // tile fails the outside controls
+        const double* u = mats + d.moff;
+        const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
+        if (kind == TK_DENSE1) {
+            const int p = d.p[0];
+            const uint32_t hm = ~((1u << p) - 1); // pair k -> e0 = k + (k & hm) (zero inserted at p)
+            const uint32_t pb = 1u << p;
+            const double u0 = u[0], u1 = u[1], u2 = u[2], u3 = u[3], u4 = u[4], u5 = u[5], u6 = u[6],
+                         u7 = u[7];
+            if (lcm == 0) {
+#pragma unroll 4
                 for (int s = 0; s < (PER + 1) / 2; ++s) {
                     const uint32_t k = tid + 256 * s;
-                    if (k < E / 2) {
-                        const uint32_t e0 = ins0_32(k, p), e1 = e0 | (1u << p);
+                    if (E >= 512 || k < E / 2) {
+                        const uint32_t e0 = k + (k & hm), e1 = e0 + pb;
+                        const double2 a = ld2(tile[e0]), b = ld2(tile[e1]);
+                        tile[e0] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
+                        tile[e1] = st2<V>(cmad2<double2, double>(u4, u5, a, u6, u7, b));
+                    }
+                }
+            } else {
+#pragma unroll 4
+                for (int s = 0; s < (PER + 1) / 2; ++s) {
+                    const uint32_t k = tid + 256 * s;
+                    if (E >= 512 || k < E / 2) {
+                        const uint32_t e0 = k + (k & hm), e1 = e0 + pb;
                         if ((e0 & lcm) == lcv) {
                             const double2 a = ld2(tile[e0]), b = ld2(tile[e1]);
                             tile[e0] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
@@ -177,190 +153,465 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
                         }
                     }
                 }
-            } else if (kind == TK_DENSE2) {
-                const int p0 = d.p[0], p1 = d.p[1];
-                const int lo = p0 < p1 ? p0 : p1, hi = p0 < p1 ? p1 : p0;
-                const uint32_t b0 = 1u << p0, b1 = 1u << p1;
+            }
+        } else if (kind == TK_DENSE2) {
+            const int p0 = d.p[0], p1 = d.p[1];
+            const int lo = p0 < p1 ? p0 : p1, hi = p0 < p1 ? p1 : p0;
+            const uint32_t b0 = 1u << p0, b1 = 1u << p1;
+#pragma unroll 2
+            for (int s = 0; s < (PER + 3) / 4; ++s) {
+                const uint32_t k = tid + 256 * s;
+                if (k < E / 4) {
+                    const uint32_t e = ins0_32(ins0_32(k, lo), hi);
+                    if ((e & lcm) == lcv) {
+                        const double2 v0 = ld2(tile[e]), v1 = ld2(tile[e | b0]), v2 = ld2(tile[e | b1]),
+                                      v3 = ld2(tile[e | b0 | b1]);
+                        double2 out[4];
 #pragma unroll
-                for (int s = 0; s < (PER + 3) / 4; ++s) {
-                    const uint32_t k = tid + 256 * s;
-                    if (k < E / 4) {
-                        const uint32_t e = ins0_32(ins0_32(k, lo), hi);
-                        if ((e & lcm) == lcv) {
-                            const double2 v0 = ld2(tile[e]), v1 = ld2(tile[e | b0]), v2 = ld2(tile[e | b1]),
-                                          v3 = ld2(tile[e | b0 | b1]);
-                            double2 out[4];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) {
-                                const double* ur = u + 8 * r;
-                                const double2 s1 = cmad2<double2, double>(ur[0], ur[1], v0, ur[2], ur[3], v1);
-                                const double2 s2 = cmad2<double2, double>(ur[4], ur[5], v2, ur[6], ur[7], v3);
-                                out[r].x = s1.x + s2.x;
-                                out[r].y = s1.y + s2.y;
-                            }
-                            tile[e] = st2<V>(out[0]);
-                            tile[e | b0] = st2<V>(out[1]);
-                            tile[e | b1] = st2<V>(out[2]);
-                            tile[e | b0 | b1] = st2<V>(out[3]);
+                        for (int r = 0; r < 4; ++r) {
+                            const double* ur = u + 8 * r;
+                            const double2 s1 = cmad2<double2, double>(ur[0], ur[1], v0, ur[2], ur[3], v1);
+                            const double2 s2 = cmad2<double2, double>(ur[4], ur[5], v2, ur[6], ur[7], v3);
+                            out[r].x = s1.x + s2.x;
+                            out[r].y = s1.y + s2.y;
                         }
+                        tile[e] = st2<V>(out[0]);
+                        tile[e | b0] = st2<V>(out[1]);
+                        tile[e | b1] = st2<V>(out[2]);
+                        tile[e | b0 | b1] = st2<V>(out[3]);
                     }
                 }
-            } else if (kind == TK_DENSEK) {
-                // Rounds of 256 slots; a round holds whole groups (D <= 64
-                // divides 256), so every lane reads its group, all wait, and
-                // all write: no group is overwritten while still being read.
-                const int k = d.k;
-                const uint32_t D = 1u << k;
-                uint32_t tm = 0;
-                for (int j = 0; j < k; ++j) tm |= 1u << d.p[j];
-                for (uint32_t r0 = 0; r0 < E; r0 += 256) {
-                    const uint32_t slot = r0 + tid;
-                    bool act = false;
-                    uint32_t eo = 0;
-                    double2 res;
-                    if (slot < E) {
-                        const uint32_t g = slot >> k, r = slot & (D - 1);
-                        uint32_t gb = g; // insert zeros at the target positions (ascending)
-                        for (int b = 0; b < M; ++b)
-                            if ((tm >> b) & 1) gb = ins0_32(gb, b);
-                        if ((gb & lcm) == lcv) {
-                            act = true;
-                            double sr = 0, si = 0;
+            }
+        } else if (kind == TK_DENSEK) {
+            // Rounds of 256 slots; a round holds whole groups (D <= 64
+            // divides 256), so every lane reads its group, all wait, and
+            // all write: no group is overwritten while still being read.
+            const int k = d.k;
+            const uint32_t D = 1u << k;
+            uint32_t tm = 0;
+            for (int j = 0; j < k; ++j) tm |= 1u << d.p[j];
+            for (uint32_t r0 = 0; r0 < E; r0 += 256) {
+                const uint32_t slot = r0 + tid;
+                bool act = false;
+                uint32_t eo = 0;
+                double2 res;
+                if (slot < E) {
+                    const uint32_t g = slot >> k, r = slot & (D - 1);
+                    uint32_t gb = g; // insert zeros at the target positions (ascending)
+                    for (int b = 0; b < M; ++b)
+                        if ((tm >> b) & 1) gb = ins0_32(gb, b);
+                    if ((gb & lcm) == lcv) {
+                        act = true;
+                        double sr = 0, si = 0;
 #pragma unroll 4
-                            for (uint32_t mm = 0; mm < D; ++mm) {
-                                uint32_t ei = gb;
-                                for (int j = 0; j < k; ++j)
-                                    if ((mm >> j) & 1) ei |= 1u << d.p[j];
-                                const double2 x = ld2(tile[ei]);
-                                const double ar = u[2 * (r * D + mm)], ai = u[2 * (r * D + mm) + 1];
-                                sr += ar * x.x - ai * x.y;
-                                si += ar * x.y + ai * x.x;
-                            }
-                            eo = gb;
+                        for (uint32_t mm = 0; mm < D; ++mm) {
+                            uint32_t ei = gb;
                             for (int j = 0; j < k; ++j)
-                                if ((r >> j) & 1) eo |= 1u << d.p[j];
-                            res.x = sr;
-                            res.y = si;
+                                if ((mm >> j) & 1) ei |= 1u << d.p[j];
+                            const double2 x = ld2(tile[ei]);
+                            const double ar = u[2 * (r * D + mm)], ai = u[2 * (r * D + mm) + 1];
+                            sr += ar * x.x - ai * x.y;
+                            si += ar * x.y + ai * x.x;
                         }
-                    }
-                    __syncthreads();
-                    if (act) tile[eo] = st2<V>(res);
-                    __syncthreads();
-                }
-            } else if (kind == TK_MFMA) {
-                if constexpr (sizeof(R) == 4 && M >= 8) {
-                    if (d.k == 5) {
-                        if constexpr (M >= 9) mfma_block<5, M>((float2*)tile, d, mats, tid);
-                    } else {
-                        mfma_block<4, M>((float2*)tile, d, mats, tid);
+                        eo = gb;
+                        for (int j = 0; j < k; ++j)
+                            if ((r >> j) & 1) eo |= 1u << d.p[j];
+                        res.x = sr;
+                        res.y = si;
                     }
                 }
-            } else if (kind == TK_DIAG) {
-                // A run of diagonal gates [o, o2) is applied in one sweep with
-                // the lane's elements in registers.  Per tile the gates' bits
-                // outside the tile are fixed, so most gates reduce to a factor
-                // on one local bit (or to one factor for the whole tile); such
-                // factors are multiplied together in uniform (scalar) code and
-                // reach each element as one complex multiply per local bit.
-                int o2 = o + 1;
-                while (o2 < nops && ops[o2].kind == TK_DIAG) ++o2;
-                double2 v[PER];
-#pragma unroll
+                __syncthreads();
+                if (act) tile[eo] = st2<V>(res);
+                __syncthreads();
+            }
+        } else if (kind == TK_MFMA) {
+            if constexpr (sizeof(R) == 4 && M >= 8) {
+                if (d.k == 5) {
+                    if constexpr (M >= 9) mfma_block<5, M>((float2*)tile, d, mats, tid);
+                } else {
+                    mfma_block<4, M>((float2*)tile, d, mats, tid);
+                }
+            }
+        } else if (kind == TK_DIAG) {
+            // A run of diagonal gates [o, o2) is applied in one sweep with
+            // the lane's elements in registers.  Per tile the gates' bits
+            // outside the tile are fixed, so most gates reduce to a factor
+            // on one local bit (or to one factor for the whole tile); such
+            // factors are multiplied together in uniform (scalar) code and
+            // reach each element as one complex multiply per local bit.
+            int o2 = o + 1;
+            while (o2 < nops && ops[o2].kind == TK_DIAG) ++o2;
+            // Every lane touches only its own elements (e = tid + 256 s) during
+            // the run, so the run needs no barrier until its end; values stay
+            // in LDS (no per-lane register copy of the tile).
+            double cr = 1.0, ci = 0.0;              // whole-tile factor
+            int abit = -1;                          // pending one-bit factor
+            double a0r = 1.0, a0i = 0.0, a1r = 1.0, a1i = 0.0;
+            auto flush = [&]() {
+                if (abit < 0) return;
+#pragma unroll 4
                 for (int s = 0; s < PER; ++s) {
                     const uint32_t e = tid + 256 * s;
-                    v[s] = (E >= 256 || e < E) ? ld2(tile[e]) : make_double2(0.0, 0.0);
+                    if (E >= 256 || e < E) {
+                        const bool one = (e >> abit) & 1;
+                        tile[e] = st2<V>(cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, ld2(tile[e])));
+                    }
                 }
-                double cr = 1.0, ci = 0.0;              // whole-tile factor
-                int abit = -1;                          // pending one-bit factor
-                double a0r = 1.0, a0i = 0.0, a1r = 1.0, a1i = 0.0;
-                auto flush = [&]() {
-                    if (abit < 0) return;
-#pragma unroll
+                abit = -1;
+            };
+            auto merge = [&](int bit, double f0r, double f0i, double f1r, double f1i) {
+                if (bit != abit) {
+                    flush();
+                    abit = bit;
+                    a0r = f0r; a0i = f0i; a1r = f1r; a1i = f1i;
+                } else {
+                    const double t0r = a0r * f0r - a0i * f0i, t0i = a0r * f0i + a0i * f0r;
+                    const double t1r = a1r * f1r - a1i * f1i, t1i = a1r * f1i + a1i * f1r;
+                    a0r = t0r; a0i = t0i; a1r = t1r; a1i = t1i;
+                }
+            };
+            for (int q = o; q < o2; ++q) {
+                const TileOp& g = ops[q];
+                if ((base & g.gcm) != g.gcv) continue;
+                const double* dd = mats + g.moff;
+                uint32_t gidx = 0; // index bits contributed by targets outside the tile
+                for (int j = 0; j < g.k; ++j)
+                    if (g.lp[j] < 0) gidx |= (uint32_t)((base >> g.p[j]) & 1) << j;
+                const int cls = g.dclass;
+                if (cls == DG_UNIFORM) {
+                    const double fr = dd[2 * gidx], fi = dd[2 * gidx + 1];
+                    const double tr = cr * fr - ci * fi, ti = cr * fi + ci * fr;
+                    cr = tr; ci = ti;
+                } else if (cls == DG_LTARGET) {
+                    const uint32_t i1 = gidx | (1u << g.dj);
+                    merge(g.dbit, dd[2 * gidx], dd[2 * gidx + 1], dd[2 * i1], dd[2 * i1 + 1]);
+                } else if (cls == DG_LCONTROL) {
+                    const double fr = dd[2 * gidx], fi = dd[2 * gidx + 1];
+                    if (g.lcv) merge(g.dbit, 1.0, 0.0, fr, fi);
+                    else merge(g.dbit, fr, fi, 1.0, 0.0);
+                } else if (cls == DG_CT) {
+                    // one local target bit and one local control bit (CZ, CP)
+                    flush();
+                    const int tb = g.dbit, cb = (int)__builtin_ctzll(g.lcm);
+                    const uint32_t cv = g.lcv ? 1u : 0u;
+                    const uint32_t i1 = gidx | (1u << g.dj);
+                    const double f0r = dd[2 * gidx], f0i = dd[2 * gidx + 1], f1r = dd[2 * i1], f1i = dd[2 * i1 + 1];
+#pragma unroll 4
                     for (int s = 0; s < PER; ++s) {
                         const uint32_t e = tid + 256 * s;
-                        const bool one = (e >> abit) & 1;
-                        v[s] = cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, v[s]);
+                        if ((E >= 256 || e < E) && ((e >> cb) & 1) == cv) {
+                            const bool one = (e >> tb) & 1;
+                            tile[e] = st2<V>(cmul<double2, double>(one ? f1r : f0r, one ? f1i : f0i, ld2(tile[e])));
+                        }
                     }
-                    abit = -1;
-                };
-                auto merge = [&](int bit, double f0r, double f0i, double f1r, double f1i) {
-                    if (bit != abit) {
-                        flush();
-                        abit = bit;
-                        a0r = f0r; a0i = f0i; a1r = f1r; a1i = f1i;
-                    } else {
-                        const double t0r = a0r * f0r - a0i * f0i, t0i = a0r * f0i + a0i * f0r;
-                        const double t1r = a1r * f1r - a1i * f1i, t1i = a1r * f1i + a1i * f1r;
-                        a0r = t0r; a0i = t0i; a1r = t1r; a1i = t1i;
-                    }
-                };
-                for (int q = o; q < o2; ++q) {
-                    const TileOp& g = ops[q];
-                    if ((base & g.gcm) != g.gcv) continue;
-                    const double* dd = mats + g.moff;
-                    uint32_t gidx = 0; // index bits contributed by targets outside the tile
-                    for (int j = 0; j < g.k; ++j)
-                        if (g.lp[j] < 0) gidx |= (uint32_t)((base >> g.p[j]) & 1) << j;
-                    const int cls = g.dclass;
-                    if (cls == DG_UNIFORM) {
-                        const double fr = dd[2 * gidx], fi = dd[2 * gidx + 1];
-                        const double tr = cr * fr - ci * fi, ti = cr * fi + ci * fr;
-                        cr = tr; ci = ti;
-                    } else if (cls == DG_LTARGET) {
-                        const uint32_t i1 = gidx | (1u << g.dj);
-                        merge(g.dbit, dd[2 * gidx], dd[2 * gidx + 1], dd[2 * i1], dd[2 * i1 + 1]);
-                    } else if (cls == DG_LCONTROL) {
-                        const double fr = dd[2 * gidx], fi = dd[2 * gidx + 1];
-                        if (g.lcv) merge(g.dbit, 1.0, 0.0, fr, fi);
-                        else merge(g.dbit, fr, fi, 1.0, 0.0);
-                    } else {
-                        flush();
-                        const uint32_t lc = (uint32_t)g.lcm, lv = (uint32_t)g.lcv;
-#pragma unroll
-                        for (int s = 0; s < PER; ++s) {
-                            const uint32_t e = tid + 256 * s;
-                            if ((e & lc) == lv) {
-                                uint32_t idx = gidx;
-                                for (int j = 0; j < g.k; ++j)
-                                    if (g.lp[j] >= 0) idx |= ((e >> g.lp[j]) & 1) << j;
-                                v[s] = cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], v[s]);
-                            }
+                } else {
+                    flush();
+                    const uint32_t lc = (uint32_t)g.lcm, lv = (uint32_t)g.lcv;
+#pragma unroll 4
+                    for (int s = 0; s < PER; ++s) {
+                        const uint32_t e = tid + 256 * s;
+                        if ((E >= 256 || e < E) && (e & lc) == lv) {
+                            uint32_t idx = gidx;
+                            for (int j = 0; j < g.k; ++j)
+                                if (g.lp[j] >= 0) idx |= ((e >> g.lp[j]) & 1) << j;
+                            tile[e] = st2<V>(cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], ld2(tile[e])));
                         }
                     }
                 }
-                if (abit >= 0) {
-                    const double t0r = a0r * cr - a0i * ci, t0i = a0r * ci + a0i * cr;
-                    const double t1r = a1r * cr - a1i * ci, t1i = a1r * ci + a1i * cr;
-                    a0r = t0r; a0i = t0i; a1r = t1r; a1i = t1i;
-                    flush();
-                } else if (cr != 1.0 || ci != 0.0) {
-#pragma unroll
-                    for (int s = 0; s < PER; ++s) v[s] = cmul<double2, double>(cr, ci, v[s]);
-                }
-#pragma unroll
+            }
+            if (abit >= 0) {
+                const double t0r = a0r * cr - a0i * ci, t0i = a0r * ci + a0i * cr;
+                const double t1r = a1r * cr - a1i * ci, t1i = a1r * ci + a1i * cr;
+                a0r = t0r; a0i = t0i; a1r = t1r; a1i = t1i;
+                flush();
+            } else if (cr != 1.0 || ci != 0.0) {
+#pragma unroll 4
                 for (int s = 0; s < PER; ++s) {
                     const uint32_t e = tid + 256 * s;
-                    if (E >= 256 || e < E) tile[e] = st2<V>(v[s]);
-                }
-                o = o2 - 1;
-            }
-            __syncthreads();
-        }
-        {
-#pragma unroll
-            for (int s = 0; s < PER; ++s) {
-                const uint32_t e = tid + 256 * s;
-                if (e < E) {
-                    V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
-                    if (nt)
-                        gst<true>(a, tile[e]);
-                    else
-                        gst<false>(a, tile[e]);
+                    if (E >= 256 || e < E) tile[e] = st2<V>(cmul<double2, double>(cr, ci, ld2(tile[e])));
                 }
             }
+            o = o2 - 1;
         }
         __syncthreads();
     }
+}
+
+// Tile element e <-> amplitude base | (e & lowm) | (hoff[e >> L] << L).
+template <typename R, int M>
+__device__ __forceinline__ void tile_load(const typename CT<R>::V* __restrict__ psi, uint64_t base, int L,
+                                          const uint32_t* hoff, typename CT<R>::V* tile, int nt)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    constexpr int PER = (E + 255) / 256;
+    const uint32_t lowm = (1u << L) - 1;
+    const int tid = threadIdx.x;
+    // all loads of the tile are issued before the first LDS write
+    R rx[PER], ry[PER];
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t e = tid + 256 * s;
+        if (E >= 256 || e < E) {
+            const V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
+            const V v = nt ? gld<true>(a) : gld<false>(a);
+            rx[s] = v.x;
+            ry[s] = v.y;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t e = tid + 256 * s;
+        if (E >= 256 || e < E) {
+            V v;
+            v.x = rx[s];
+            v.y = ry[s];
+            tile[e] = v;
+        }
+    }
+}
+
+template <typename R, int M>
+__device__ __forceinline__ void tile_store(typename CT<R>::V* __restrict__ psi, uint64_t base, int L,
+                                           const uint32_t* hoff, const typename CT<R>::V* tile, int nt)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    constexpr int PER = (E + 255) / 256;
+    const uint32_t lowm = (1u << L) - 1;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+        const uint32_t e = tid + 256 * s;
+        if (e < E) {
+            V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
+            if (nt)
+                gst<true>(a, tile[e]);
+            else
+                gst<false>(a, tile[e]);
+        }
+    }
+}
+
+// hoff[h] = dep_Q of the tile bits above L, shifted right by L.
+__device__ __forceinline__ void build_hoff(uint32_t* hoff, int M, int L, const int32_t* q)
+{
+    const uint32_t H = 1u << (M - L);
+    for (uint32_t h = threadIdx.x; h < H; h += 256) {
+        uint64_t off = 0;
+        for (int j = L; j < M; ++j)
+            if ((h >> (j - L)) & 1) off |= 1ull << q[j];
+        hoff[h] = (uint32_t)(off >> L);
+    }
+}
+
+template <typename R, int M, bool MF>
+__global__ void __launch_bounds__(256)
+k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
+       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = (V*)smem;
+    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
+    build_hoff(hoff, M, ql.L, ql.q);
+    __syncthreads();
+    for (uint64_t tau = blockIdx.x; tau < ntiles; tau += gridDim.x) {
+        const uint64_t base = ins_bits(tau, ipQ);
+        tile_load<R, M>(psi, base, ql.L, hoff, tile, nt);
+        __syncthreads();
+        tile_ops<R, M, MF>(tile, base, ops, nops, mats);
+        tile_store<R, M>(psi, base, ql.L, hoff, tile, nt);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- batches
+
+template <typename R, int M, bool MF>
+__global__ void __launch_bounds__(256)
+k_batch_whole(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
+              const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
+              const double* __restrict__ mats)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = (V*)smem;
+    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
+    const BatchCirc& c = circs[list[blockIdx.x]];
+    V* psi = (V*)(arena + c.psi_off);
+    for (uint32_t e = threadIdx.x; e < E; e += 256) {
+        V v;
+        v.x = (e == c.basis) ? (R)1 : (R)0;
+        v.y = 0;
+        tile[e] = v;
+    }
+    if (threadIdx.x == 0) hoff[0] = 0;
+    __syncthreads();
+    for (int p = 0; p < c.npass; ++p) {
+        const BatchPass& bp = passes[c.pass0 + p];
+        tile_ops<R, M, MF>(tile, 0, ops + bp.op0, bp.nops, mats);
+    }
+    tile_store<R, M>(psi, 0, M, hoff, tile, M >= 4 ? 1 : 0);
+}
+
+template <typename R, int M, bool MF>
+__global__ void __launch_bounds__(256)
+k_batch_persist(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
+                const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
+                const double* __restrict__ mats)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = (V*)smem;
+    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
+    const BatchCirc& c = circs[list[blockIdx.x]];
+    V* psi = (V*)(arena + c.psi_off);
+    const uint64_t N = 1ull << c.n;
+    for (uint64_t i = threadIdx.x; i < N; i += 256) {
+        V v;
+        v.x = (i == c.basis) ? (R)1 : (R)0;
+        v.y = 0;
+        psi[i] = v;
+    }
+    __syncthreads(); // global writes of this block are visible to its own later loads
+    const uint64_t ntiles = 1ull << (c.n - M);
+    for (int p = 0; p < c.npass; ++p) {
+        const BatchPass& bp = passes[c.pass0 + p];
+        build_hoff(hoff, M, bp.L, bp.q);
+        __syncthreads();
+        for (uint64_t tau = 0; tau < ntiles; ++tau) {
+            const uint64_t base = ins_bits(tau, bp.ip);
+            tile_load<R, M>(psi, base, bp.L, hoff, tile, 0);
+            __syncthreads();
+            tile_ops<R, M, MF>(tile, base, ops + bp.op0, bp.nops, mats);
+            tile_store<R, M>(psi, base, bp.L, hoff, tile, 0);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename R, int M, bool MF>
+__global__ void __launch_bounds__(256)
+k_batch_round(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const BatchPass* __restrict__ passes,
+              const TileOp* __restrict__ ops, const double* __restrict__ mats,
+              const RoundEntry* __restrict__ entries, int nentries)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = (V*)smem;
+    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
+    // the entry owning this block: last one with first_block <= blockIdx.x
+    int lo = 0, hi = nentries - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (entries[mid].first_block <= blockIdx.x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const RoundEntry& en = entries[lo];
+    const BatchCirc& c = circs[en.circ];
+    const BatchPass& bp = passes[en.pass];
+    V* psi = (V*)(arena + c.psi_off);
+    build_hoff(hoff, M, bp.L, bp.q);
+    __syncthreads();
+    const uint64_t base = ins_bits((uint64_t)(blockIdx.x - en.first_block), bp.ip);
+    const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
+    tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
+    __syncthreads();
+    tile_ops<R, M, MF>(tile, base, ops + bp.op0, bp.nops, mats);
+    tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
+}
+
+template <typename V>
+__global__ void __launch_bounds__(256)
+k_batch_init(char* __restrict__ arena, uint64_t n16, const BatchCirc* __restrict__ circs,
+             const int32_t* __restrict__ list, int count)
+{
+    // zero the arena with 16-byte stores, then (last block) the basis amplitudes
+    uint4* z = (uint4*)arena;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * 256)
+        z[i] = make_uint4(0, 0, 0, 0);
+}
+
+template <typename V>
+__global__ void __launch_bounds__(256)
+k_batch_basis(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
+              int count)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
+        const BatchCirc& c = circs[list[i]];
+        V v;
+        v.x = 1;
+        v.y = 0;
+        ((V*)(arena + c.psi_off))[c.basis] = v;
+    }
+}
+
+template <typename R, int M, bool MF>
+static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const BatchPass* passes, const TileOp* ops,
+                                 const double* mats, const RoundEntry* entries, int nentries, uint32_t nblocks,
+                                 hipStream_t st)
+{
+    const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
+    const size_t lds = lds_max > 163840 ? 163840 : lds_max;
+    if (lds > 65536) {
+        static bool set = false;
+        if (!set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_round<R, M, MF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+    }
+    hipLaunchKernelGGL((k_batch_round<R, M, MF>), dim3(nblocks), dim3(256), lds, st, arena, circs, passes, ops, mats,
+                       entries, nentries);
+    return hipGetLastError();
+}
+
+template <typename R, int M, bool MF>
+static hipError_t launch_whole_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
+                                 const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
+{
+    const size_t lds = sizeof(typename CT<R>::V) * (1ull << M) + 16;
+    if (lds > 65536) {
+        static bool set = false;
+        if (!set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_whole<R, M, MF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+    }
+    hipLaunchKernelGGL((k_batch_whole<R, M, MF>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops, mats);
+    return hipGetLastError();
+}
+
+template <typename R, int M, bool MF>
+static hipError_t launch_persist_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
+                                   const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
+{
+    const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
+    if (lds_max > 65536) {
+        static bool set = false;
+        if (!set) {
+            const int lim = lds_max > 163840 ? 163840 : (int)lds_max;
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_persist<R, M, MF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+    }
+    // LDS for the smallest L any pass may have
+    const size_t lds = lds_max > 163840 ? 163840 : lds_max;
+    hipLaunchKernelGGL((k_batch_persist<R, M, MF>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops,
+                       mats);
+    return hipGetLastError();
 }
 
 template <typename R, int M>
@@ -385,8 +636,10 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
     if (!attr_set && lds_max > 65536) {
         const int lim = lds_max > 163840 ? 163840 : (int)lds_max;
-        hipError_t e = hipFuncSetAttribute((const void*)k_tile<R, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           lim);
+        hipError_t e = hipFuncSetAttribute((const void*)k_tile<R, M, false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_tile<R, M, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -397,8 +650,16 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     const int line_bits = sizeof(R) == 8 ? 3 : 4;
     static int nt_env = env_int("QS_NT", 1);
     const int nt = (nt_env && pass.L >= line_bits) ? 1 : 0;
-    hipLaunchKernelGGL((k_tile<R, M>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                       (int)pass.ops.size(), (const double*)dmats, nt);
+    // the matrix-core variant only when the pass holds a fused block (its
+    // fragments would otherwise cost every pass registers)
+    bool mf = false;
+    for (const TileOp& t : pass.ops) mf |= t.kind == TK_MFMA;
+    if (mf)
+        hipLaunchKernelGGL((k_tile<R, M, true>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
+                           (int)pass.ops.size(), (const double*)dmats, nt);
+    else
+        hipLaunchKernelGGL((k_tile<R, M, false>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
+                           (int)pass.ops.size(), (const double*)dmats, nt);
     return hipGetLastError();
 }
 
@@ -417,11 +678,101 @@ hipError_t launch_r(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     }
 }
 
+template <typename R, bool MF>
+static hipError_t batch_whole_r(int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
+                                const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
+{
+    switch (M) {
+#define QS_WCASE(MM) \
+    case MM: return launch_whole_m<R, MM, MF>(arena, circs, list, count, passes, ops, mats, st);
+        QS_WCASE(1) QS_WCASE(2) QS_WCASE(3) QS_WCASE(4) QS_WCASE(5) QS_WCASE(6) QS_WCASE(7) QS_WCASE(8)
+        QS_WCASE(9) QS_WCASE(10) QS_WCASE(11) QS_WCASE(12) QS_WCASE(13)
+#undef QS_WCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, bool MF>
+static hipError_t batch_persist_r(int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
+                                  const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
+{
+    switch (M) {
+#define QS_PCASE(MM) \
+    case MM: return launch_persist_m<R, MM, MF>(arena, circs, list, count, passes, ops, mats, st);
+        QS_PCASE(9) QS_PCASE(10) QS_PCASE(11) QS_PCASE(12) QS_PCASE(13)
+#undef QS_PCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
 } // namespace
 
 size_t tile_lds_bytes(int dt, int m, int L)
 {
     return amp_bytes(dt) * (1ull << m) + 4ull * (1ull << (m - L));
+}
+
+hipError_t launch_batch_whole(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
+                              const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                              hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (dt == QS_C128) return batch_whole_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
+    return mf ? batch_whole_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
+              : batch_whole_r<float, false>(M, arena, circs, list, count, passes, ops, mats, st);
+}
+
+hipError_t launch_batch_persist(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list,
+                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                                hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    if (dt == QS_C128) return batch_persist_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
+    return mf ? batch_persist_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
+              : batch_persist_r<float, false>(M, arena, circs, list, count, passes, ops, mats, st);
+}
+
+template <typename R, bool MF>
+static hipError_t batch_round_r(int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
+                                const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
+                                uint32_t nblocks, hipStream_t st)
+{
+    switch (M) {
+#define QS_RCASE(MM) \
+    case MM: return launch_round_m<R, MM, MF>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+        QS_RCASE(9) QS_RCASE(10) QS_RCASE(11) QS_RCASE(12) QS_RCASE(13)
+#undef QS_RCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
+                              const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
+                              uint32_t nblocks, bool mf, hipStream_t st)
+{
+    if (nentries <= 0 || nblocks == 0) return hipSuccess;
+    if (dt == QS_C128)
+        return batch_round_r<double, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+    return mf ? batch_round_r<float, true>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st)
+              : batch_round_r<float, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+}
+
+hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCirc* circs, const int32_t* list,
+                             int count, hipStream_t st)
+{
+    const uint64_t n16 = bytes / 16;
+    uint64_t g = (n16 + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_batch_init<double2>, dim3((unsigned)g), dim3(256), 0, st, arena, n16, circs, list, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || count <= 0) return e;
+    const unsigned gb = (unsigned)((count + 255) / 256);
+    if (dt == QS_C128)
+        hipLaunchKernelGGL(k_batch_basis<double2>, dim3(gb), dim3(256), 0, st, arena, circs, list, count);
+    else
+        hipLaunchKernelGGL(k_batch_basis<float2>, dim3(gb), dim3(256), 0, st, arena, circs, list, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_tile_pass(void* psi, int dt, int n, const PlanPass& pass, const TileOp* dops,

@@ -300,3 +300,62 @@ def test_fused_mfma_blocks_c64(qs, name, fk, tq, fmin, monkeypatch):
     s = _state(qs, n, 1, psi0, c.init_basis)
     s.run(ops, mats, mode=0, fuse_k=fk, tile_qubits=tq)
     _check(s.download(), want, 1, f"{name} fuse_k={fk} tq={tq} ({nops} ops in {npass} passes)")
+
+
+def _batch_mix(seed):
+    rng = np.random.default_rng(seed)
+    circs = []
+    for n in (3, 7, 10, 12, 13, 14, 15, 16, 17, 18):
+        kind = int(rng.integers(3))
+        if kind == 0:
+            c = W.rqc_chain(n, int(rng.integers(3, 9)), int(rng.integers(1000)))
+        elif kind == 1:
+            c = W.qft(n, int(rng.integers(1 << n)))
+        else:
+            c = W.grover(n, int(rng.integers(1 << n)))
+        circs.append(c)
+    circs.append(W.random_u3_cnot(11, 150, seed=5))
+    return circs
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_matches_oracle(qs, dt, mode):
+    circs = _batch_mix(3)
+    b = qs.qs_batch_submit(circs, dtype=dt, mode=mode, streams=4)
+    try:
+        qs.qs_batch_wait(b)
+        st = qs.qs_batch_get_stats(b)
+        assert st["launches"] >= 1 and st["device_ms"] > 0
+        for i, c in enumerate(circs):
+            want = oracle.run_circuit(c)
+            got = qs.qs_batch_download(b, i, dt)
+            _check(got, want, dt, f"batch mode={mode} circuit {i} {c.name}")
+    finally:
+        qs.qs_batch_release(b)
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_batch_result_independent_of_co_residents(qs, dt):
+    circs = _batch_mix(4)
+    b = qs.qs_batch_submit(circs, dtype=dt, mode=0)
+    try:
+        qs.qs_batch_wait(b)
+        together = [qs.qs_batch_download(b, i, dt) for i in range(len(circs))]
+    finally:
+        qs.qs_batch_release(b)
+    for i in (0, 3, 5, 8):
+        b1 = qs.qs_batch_submit([circs[i]], dtype=dt, mode=0)
+        try:
+            alone = qs.qs_batch_download(b1, 0, dt)
+        finally:
+            qs.qs_batch_release(b1)
+        assert alone.tobytes() == together[i].tobytes(), circs[i].name
+
+
+def test_batch_rejects_invalid_circuit_before_any_work(qs):
+    good = W.qft(6, 1)
+    bad = W.Circuit(4).g1(5, W.H)
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_batch_submit([good, bad])
+    assert e.value.status == qs.QS_ERR_ARG and "circuit 1" in str(e.value)
