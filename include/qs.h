@@ -243,6 +243,70 @@ qs_status qs_batch_get_stats(qs_batch b, qs_batch_stats* out);
 /* Wait for outstanding work and free the batch (NULL accepted). */
 qs_status qs_batch_release(qs_batch b);
 
+/* ------------------------------------------------------------------ serving */
+
+typedef struct qs_server_s* qs_server;
+
+typedef struct {
+    int32_t dtype;        /* QS_C64 or QS_C128 (0 = QS_C128) */
+    int32_t rounds_ahead; /* rounds enqueued ahead of completion (0 = 3, max 16) */
+    uint64_t hbm_budget;  /* bytes of device memory for request states (0 = half the free memory) */
+    uint64_t plan_budget; /* bytes of device memory for request plans (0 = 256 MiB) */
+    int32_t tile_qubits;  /* tile size of the passes (0 = default; 9..13) */
+    int32_t fuse_k;       /* as in qs_run_opts */
+    int32_t rsv[4];
+} qs_server_opts;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;       /* QS_OK, or why the request failed / was cancelled */
+    int32_t n;
+    double t_submit_ms;   /* milliseconds since qs_server_create, steady clock */
+    double t_admit_ms;
+    double t_done_ms;     /* when the server saw the last round of the request complete */
+} qs_result;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, failed, cancelled;
+    uint64_t rounds, launches;
+    uint64_t budget_bytes, used_bytes, peak_bytes;
+    uint32_t queued, active;
+} qs_server_stats;
+
+/* Create a serving loop with its own stream and device pools (serving
+ * survey item; the paper runs one circuit at a time).  Requests are admitted
+ * in arrival order (later small ones may pass a large one that does not fit
+ * yet, up to 64 times) while their state fits hbm_budget; admitted requests
+ * advance together in rounds of one tile pass each, and requests arriving
+ * while others run join the next round (continuous batching).  Each result is
+ * bitwise the same as the request run alone. */
+qs_status qs_server_create(const qs_server_opts* opts, qs_server* out);
+
+/* Queue a request (validated and copied; the caller's tables may be freed).
+ * QS_ERR_OOM at once if its state could never fit the budget. */
+qs_status qs_server_submit(qs_server s, const qs_circuit* c, uint64_t* id);
+
+/* One scheduler tick: retire finished rounds, admit queued requests that fit,
+ * enqueue up to rounds_ahead rounds, and return up to `max` newly finished
+ * requests (*count of them).  Never blocks on the GPU. */
+qs_status qs_server_poll(qs_server s, qs_result* out, int max, int* count);
+
+/* A finished request's state: device pointer (owned by the server) and n;
+ * QS_ERR_BUSY while it is queued or running. */
+qs_status qs_server_state(qs_server s, uint64_t id, void** dev_ptr, int* n);
+qs_status qs_server_download(qs_server s, uint64_t id, void* host);
+
+/* Free a finished (or failed / cancelled) request and its state. */
+qs_status qs_server_release(qs_server s, uint64_t id);
+
+/* Cancel a request that is still queued (QS_ERR_BUSY otherwise). */
+qs_status qs_server_cancel(qs_server s, uint64_t id);
+
+qs_status qs_server_get_stats(qs_server s, qs_server_stats* out);
+
+/* Wait for outstanding rounds and free the server and every state it holds. */
+qs_status qs_server_destroy(qs_server s);
+
 /* ------------------------------------------------------------------ tracing */
 
 /* One traced kernel launch. */

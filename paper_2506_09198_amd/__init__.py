@@ -53,6 +53,23 @@ class _BatchStats(ctypes.Structure):
                 ("class_ms", ctypes.c_double * 3), ("class_circuits", ctypes.c_uint32 * 3), ("rsv", ctypes.c_uint32)]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("rounds_ahead", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64),
+                ("plan_budget", ctypes.c_uint64), ("tile_qubits", ctypes.c_int32), ("fuse_k", ctypes.c_int32),
+                ("rsv", ctypes.c_int32 * 4)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "admitted", "completed", "failed", "cancelled",
+                                               "rounds", "launches", "budget_bytes", "used_bytes", "peak_bytes")] + \
+               [("queued", ctypes.c_uint32), ("active", ctypes.c_uint32)]
+
+
 class _RunOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
                 ("rsv", ctypes.c_int32 * 5)]
@@ -98,6 +115,15 @@ def _load():
         "qs_batch_download": ([vp, i32, vp], i32),
         "qs_batch_get_stats": ([vp, ctypes.POINTER(_BatchStats)], i32),
         "qs_batch_release": ([vp], i32),
+        "qs_server_create": ([ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)], i32),
+        "qs_server_submit": ([vp, ctypes.POINTER(_Circuit), ctypes.POINTER(ctypes.c_uint64)], i32),
+        "qs_server_poll": ([vp, ctypes.POINTER(_Result), i32, ctypes.POINTER(i32)], i32),
+        "qs_server_state": ([vp, ctypes.c_uint64, ctypes.POINTER(vp), ctypes.POINTER(i32)], i32),
+        "qs_server_download": ([vp, ctypes.c_uint64, vp], i32),
+        "qs_server_release": ([vp, ctypes.c_uint64], i32),
+        "qs_server_cancel": ([vp, ctypes.c_uint64], i32),
+        "qs_server_get_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
+        "qs_server_destroy": ([vp], i32),
         "qs_trace_enable": ([vp, i32], i32),
         "qs_trace_read": ([vp, vp, i32, ctypes.POINTER(i32)], i32),
     }
@@ -310,6 +336,67 @@ def qs_batch_get_stats(b: int) -> dict:
 
 def qs_batch_release(b: int):
     _check(lib.qs_batch_release(ctypes.c_void_p(b)))
+
+
+def qs_server_create(dtype: int = QS_C128, hbm_budget: int = 0, rounds_ahead: int = 0, tile_qubits: int = 0,
+                     fuse_k: int = 0, plan_budget: int = 0) -> int:
+    o = _ServerOpts(dtype, rounds_ahead, hbm_budget, plan_budget, tile_qubits, fuse_k)
+    h = ctypes.c_void_p()
+    _check(lib.qs_server_create(ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def qs_server_submit(srv: int, circ) -> int:
+    if hasattr(circ, "arrays"):
+        n, (ops, mats), basis = circ.n, circ.arrays(), circ.init_basis
+    else:
+        n, ops, mats, basis = circ
+    ops = np.ascontiguousarray(ops)
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    c = _Circuit(n, 0, int(basis), ops.ctypes.data if len(ops) else 0, len(ops), mats.ctypes.data if mats.size else 0,
+                 mats.size)
+    rid = ctypes.c_uint64()
+    _check(lib.qs_server_submit(ctypes.c_void_p(srv), ctypes.byref(c), ctypes.byref(rid)))
+    return rid.value
+
+
+def qs_server_poll(srv: int, max_results: int = 256) -> list:
+    out = (_Result * max_results)()
+    c = ctypes.c_int()
+    _check(lib.qs_server_poll(ctypes.c_void_p(srv), out, max_results, ctypes.byref(c)))
+    return [{"id": r.id, "status": r.status, "n": r.n, "t_submit_ms": r.t_submit_ms, "t_admit_ms": r.t_admit_ms,
+             "t_done_ms": r.t_done_ms} for r in out[: c.value]]
+
+
+def qs_server_state(srv: int, rid: int):
+    p, n = ctypes.c_void_p(), ctypes.c_int()
+    _check(lib.qs_server_state(ctypes.c_void_p(srv), rid, ctypes.byref(p), ctypes.byref(n)))
+    return p.value, n.value
+
+
+def qs_server_download(srv: int, rid: int, dtype: int = QS_C128) -> np.ndarray:
+    _, n = qs_server_state(srv, rid)
+    out = np.empty(1 << n, dtype=_np_dtype(dtype))
+    _check(lib.qs_server_download(ctypes.c_void_p(srv), rid, ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+def qs_server_release(srv: int, rid: int):
+    _check(lib.qs_server_release(ctypes.c_void_p(srv), rid))
+
+
+def qs_server_cancel(srv: int, rid: int):
+    _check(lib.qs_server_cancel(ctypes.c_void_p(srv), rid))
+
+
+def qs_server_get_stats(srv: int) -> dict:
+    st = _ServerStats()
+    _check(lib.qs_server_get_stats(ctypes.c_void_p(srv), ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+
+def qs_server_destroy(srv: int):
+    _check(lib.qs_server_destroy(ctypes.c_void_p(srv)))
 
 
 def qs_trace_enable(s: int, on: bool = True):

@@ -110,6 +110,26 @@ hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs
 hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCirc* circs, const int32_t* list,
                              int count, hipStream_t st);
 
+// ---------------------------------------------------------------- serving
+
+// One request's share of a serving round, with absolute device pointers.
+// Round entries: blocks [first_block, first_block + 2^(n - M)) apply pass
+// `pass` to the request's state.  Whole entries (n <= M): one block runs the
+// request's single pass on a basis state built in LDS.
+struct ServeEntry {
+    void* psi;
+    const BatchPass* pass;
+    const TileOp* ops;     // base the pass's op0 indexes
+    const double* mats;    // base the ops' moff index
+    uint64_t basis;
+    uint32_t first_block;
+    int32_t n;
+};
+
+hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool mf,
+                              hipStream_t st);
+hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool mf, hipStream_t st);
+
 qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats);
 qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int tile_qubits, PlanOpts& po);
 

@@ -81,7 +81,7 @@ void dev_free(void* p, uint64_t bytes)
 // without a real GPU fault.
 static std::atomic<long> g_launch_no{0};
 
-static bool inject_fault_now()
+bool inject_fault_now()
 {
     static long target = [] {
         const char* v = std::getenv("QS_FAULT_INJECT");

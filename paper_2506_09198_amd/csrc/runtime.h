@@ -52,6 +52,8 @@ qs_status validate_gate(int n, const int* t, int k, uint64_t cm, uint64_t cv);
 qs_status dev_alloc(void** p, uint64_t bytes, const char* what);
 void dev_free(void* p, uint64_t bytes);
 uint64_t allocated_bytes();
+// QS_FAULT_INJECT=launch:N: true exactly at the N-th launch of the process.
+bool inject_fault_now();
 
 qs_status apply_1q_internal(qs_state s, int target, const double* U, uint64_t cm, uint64_t cv);
 qs_status apply_2q_internal(qs_state s, int t0, int t1, const double* U, uint64_t cm, uint64_t cv);

@@ -575,6 +575,93 @@ static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const Batc
 }
 
 template <typename R, int M, bool MF>
+__global__ void __launch_bounds__(256)
+k_serve_round(const ServeEntry* __restrict__ entries, int nentries)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = (V*)smem;
+    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
+    int lo = 0, hi = nentries - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (entries[mid].first_block <= blockIdx.x)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const ServeEntry& en = entries[lo];
+    const BatchPass& bp = *en.pass;
+    V* psi = (V*)en.psi;
+    build_hoff(hoff, M, bp.L, bp.q);
+    __syncthreads();
+    const uint64_t base = ins_bits((uint64_t)(blockIdx.x - en.first_block), bp.ip);
+    const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
+    tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
+    __syncthreads();
+    tile_ops<R, M, MF>(tile, base, en.ops + bp.op0, bp.nops, en.mats);
+    tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
+}
+
+template <typename R, int M, bool MF>
+__global__ void __launch_bounds__(256)
+k_serve_whole(const ServeEntry* __restrict__ entries)
+{
+    using V = typename CT<R>::V;
+    constexpr uint32_t E = 1u << M;
+    extern __shared__ __align__(16) unsigned char smem[];
+    V* tile = (V*)smem;
+    uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
+    const ServeEntry& en = entries[blockIdx.x];
+    for (uint32_t e = threadIdx.x; e < E; e += 256) {
+        V v;
+        v.x = (e == en.basis) ? (R)1 : (R)0;
+        v.y = 0;
+        tile[e] = v;
+    }
+    if (threadIdx.x == 0) hoff[0] = 0;
+    __syncthreads();
+    if (en.pass) tile_ops<R, M, MF>(tile, 0, en.ops + en.pass->op0, en.pass->nops, en.mats);
+    tile_store<R, M>((V*)en.psi, 0, M, hoff, tile, M >= 4 ? 1 : 0);
+}
+
+template <typename R, int M, bool MF>
+static hipError_t launch_serve_round_m(const ServeEntry* entries, int nentries, uint32_t nblocks, hipStream_t st)
+{
+    const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
+    const size_t lds = lds_max > 163840 ? 163840 : lds_max;
+    if (lds > 65536) {
+        static bool set = false;
+        if (!set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_serve_round<R, M, MF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+    }
+    hipLaunchKernelGGL((k_serve_round<R, M, MF>), dim3(nblocks), dim3(256), lds, st, entries, nentries);
+    return hipGetLastError();
+}
+
+template <typename R, int M, bool MF>
+static hipError_t launch_serve_whole_m(const ServeEntry* entries, int nentries, hipStream_t st)
+{
+    const size_t lds = sizeof(typename CT<R>::V) * (1ull << M) + 16;
+    if (lds > 65536) {
+        static bool set = false;
+        if (!set) {
+            hipError_t e = hipFuncSetAttribute((const void*)k_serve_whole<R, M, MF>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            set = true;
+        }
+    }
+    hipLaunchKernelGGL((k_serve_whole<R, M, MF>), dim3(nentries), dim3(256), lds, st, entries);
+    return hipGetLastError();
+}
+
+template <typename R, int M, bool MF>
 static hipError_t launch_whole_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                  const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
@@ -773,6 +860,48 @@ hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCir
     else
         hipLaunchKernelGGL(k_batch_basis<float2>, dim3(gb), dim3(256), 0, st, arena, circs, list, count);
     return hipGetLastError();
+}
+
+template <typename R, bool MF>
+static hipError_t serve_round_r(int M, const ServeEntry* entries, int nentries, uint32_t nblocks, hipStream_t st)
+{
+    switch (M) {
+#define QS_SRCASE(MM) \
+    case MM: return launch_serve_round_m<R, MM, MF>(entries, nentries, nblocks, st);
+        QS_SRCASE(9) QS_SRCASE(10) QS_SRCASE(11) QS_SRCASE(12) QS_SRCASE(13)
+#undef QS_SRCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, bool MF>
+static hipError_t serve_whole_r(int M, const ServeEntry* entries, int nentries, hipStream_t st)
+{
+    switch (M) {
+#define QS_SWCASE(MM) \
+    case MM: return launch_serve_whole_m<R, MM, MF>(entries, nentries, st);
+        QS_SWCASE(1) QS_SWCASE(2) QS_SWCASE(3) QS_SWCASE(4) QS_SWCASE(5) QS_SWCASE(6) QS_SWCASE(7)
+        QS_SWCASE(8) QS_SWCASE(9) QS_SWCASE(10) QS_SWCASE(11) QS_SWCASE(12) QS_SWCASE(13)
+#undef QS_SWCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool mf,
+                              hipStream_t st)
+{
+    if (nentries <= 0 || nblocks == 0) return hipSuccess;
+    if (dt == QS_C128) return serve_round_r<double, false>(M, entries, nentries, nblocks, st);
+    return mf ? serve_round_r<float, true>(M, entries, nentries, nblocks, st)
+              : serve_round_r<float, false>(M, entries, nentries, nblocks, st);
+}
+
+hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool mf, hipStream_t st)
+{
+    if (nentries <= 0) return hipSuccess;
+    if (dt == QS_C128) return serve_whole_r<double, false>(M, entries, nentries, st);
+    return mf ? serve_whole_r<float, true>(M, entries, nentries, st)
+              : serve_whole_r<float, false>(M, entries, nentries, st);
 }
 
 hipError_t launch_tile_pass(void* psi, int dt, int n, const PlanPass& pass, const TileOp* dops,
