@@ -23,9 +23,9 @@ using cd = std::complex<double>;
 // Inside one pass, consecutive operations whose qubits (targets and local
 // controls, all inside the tile, no per-tile controls) fit in K qubits are
 // multiplied into one 2^K x 2^K matrix in FP64 and applied as a single dense
-// block on matrix cores.  The product is split into FP32 hi and lo parts
-// (hi + lo carries ~48 bits) and stored in the A-fragment order of
-// v_mfma_f32_16x16x4f32 for the real embedding [[Ur, -Ui], [Ui, Ur]].
+// block on matrix cores.  The product stays FP64 and is stored in the
+// A-fragment order of v_mfma_f64_16x16x4f64 for the real embedding
+// [[Ur, -Ui], [Ui, Ur]].
 
 static bool op_local_bits(const TileOp& t, uint32_t* bits)
 {
@@ -117,7 +117,7 @@ static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_den
             for (int i = 0; i < D; ++i) G[(size_t)i * D + i] = 1.0;
             for (size_t i : blk) embed_op(P.ops[i], pool, bq, K, G);
             const int DR = 2 * D, RB = DR / 16, KS = DR / 4, NF = RB * KS;
-            std::vector<float> fr((size_t)2 * NF * 64); // hi fragments, then lo
+            std::vector<double> fr((size_t)NF * 64); // [q][lane][2], fragment f = 2q + j
             for (int lane = 0; lane < 64; ++lane)
                 for (int rb = 0; rb < RB; ++rb)
                     for (int ks = 0; ks < KS; ++ks) {
@@ -129,10 +129,7 @@ static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_den
                         else
                             v = (col & 1) == 0 ? u.imag() : u.real();
                         const int f = rb * KS + ks;
-                        const float hi = (float)v;
-                        const float lo = (float)(v - (double)hi);
-                        fr[((size_t)(f / 4) * 64 + lane) * 4 + (f % 4)] = hi;
-                        fr[((size_t)(NF / 4 + f / 4) * 64 + lane) * 4 + (f % 4)] = lo;
+                        fr[((size_t)(f / 2) * 64 + lane) * 2 + (f % 2)] = v;
                     }
             TileOp t;
             std::memset(&t, 0, sizeof t);
@@ -140,10 +137,10 @@ static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_den
             t.k = K;
             for (int j = 0; j < K; ++j) t.p[j] = bq[j];
             size_t off = pool.size();
-            pool.resize(off + fr.size() / 2 + 2);
+            pool.resize(off + fr.size() + 2);
             // fragments start on a 16-byte boundary inside the pool
             if (off & 1) ++off;
-            std::memcpy(pool.data() + off, fr.data(), fr.size() * sizeof(float));
+            std::memcpy(pool.data() + off, fr.data(), fr.size() * sizeof(double));
             t.moff = off;
             out.push_back(t);
         }

@@ -24,15 +24,21 @@ struct QList {
     int32_t q[QS_MAX_QUBITS];
 };
 
-// Fused dense block on K = 4 or 5 tile-local qubits with FP32 matrix cores
+// Fused dense block on K = 4 or 5 tile-local qubits with FP64 matrix cores
 // (complex64 tiles).  The complex 2^K x 2^K matrix acts as its real embedding
 // [[Ur, -Ui], [Ui, Ur]] (interleaved rows/columns, 2^(K+1) square) on the
-// tile's 2^(M-K) groups ("columns"), with v_mfma_f32_16x16x4f32: lane l holds
-// A[l%16][l/16], B[l/16][l%16] and D[4(l/16)+v][l%16].  The A fragments come
-// pre-arranged by the planner ([q][lane][4] floats, q*4+j = rb*KS + ks), so a
-// wave loads them with 16-byte coalesced loads.  Each wave owns whole column
-// blocks of 16 groups, so its in-place writes never race another wave.
-typedef float f4_t __attribute__((ext_vector_type(4)));
+// tile's 2^(M-K) groups ("columns"), with v_mfma_f64_16x16x4f64: lane l holds
+// A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16].  The FP32 amplitudes
+// convert to FP64 exactly and the result is rounded once, to nearest, when it
+// is stored; FP32 matrix-core accumulation instead shrinks the norm by a
+// one-signed ~1e-8 per block, which adds up over a deep circuit.  One FP64
+// MFMA costs as much as the two FP32 ones an exact (hi + lo) matrix would
+// need.  The A fragments come pre-arranged by the planner ([q][lane][2]
+// doubles, q*2+j = rb*KS + ks), so a wave loads them with 16-byte coalesced
+// loads.  Each wave owns whole column blocks of 16 groups, so its in-place
+// writes never race another wave.
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 
 template <int K, int M>
 __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const double* mats, int tid)
@@ -46,20 +52,13 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
     static_assert(CB >= 1, "tile too small for a fused block");
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    // hi fragments, then lo fragments: the FP64 product U = U_hi + U_lo with
-    // both parts FP32, so the matrix is not rounded (a rounded H^n block would
-    // shrink the norm by the same factor at every pass).
-    const f4_t* frag = (const f4_t*)(mats + d.moff);
-    float a[NF], al[NF];
+    const d2_t* frag = (const d2_t*)(mats + d.moff);
+    double a[NF];
 #pragma unroll
-    for (int q = 0; q < NF / 4; ++q) {
-        const f4_t v = frag[q * 64 + lane];
-        const f4_t w = frag[(NF / 4 + q) * 64 + lane];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            a[4 * q + j] = v[j];
-            al[4 * q + j] = w[j];
-        }
+    for (int q = 0; q < NF / 2; ++q) {
+        const d2_t v = frag[q * 64 + lane];
+        a[2 * q] = v[0];
+        a[2 * q + 1] = v[1];
     }
     uint32_t tm = 0;
     int pos[K];
@@ -68,14 +67,15 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
         pos[j] = d.p[j];
         tm |= 1u << pos[j];
     }
+    float* tf = (float*)tile;
     for (int cb = wave; cb < CB; cb += 4) {
         const uint32_t col = cb * 16 + li;
         uint32_t gb = col; // insert zeros at the block qubits (ascending)
         for (int b = 0; b < M; ++b)
             if ((tm >> b) & 1) gb = ins0_32(gb, b);
-        f4_t acc[RB];
+        d4_t acc[RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = f4_t{0.f, 0.f, 0.f, 0.f};
+        for (int rb = 0; rb < RB; ++rb) acc[rb] = d4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const int mm = 2 * ks + (lk >> 1); // group member of real row 4ks + lk
@@ -83,24 +83,22 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 if ((mm >> j) & 1) e |= 1u << pos[j];
-            const float2 x = tile[e];
-            const float bv = (lk & 1) ? x.y : x.x;
+            const double bv = (double)tf[2 * e + (lk & 1)];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(al[rb * KS + ks], bv, acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb * KS + ks], bv, acc[rb], 0, 0, 0);
-            }
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb * KS + ks], bv, acc[rb], 0, 0, 0);
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int mm = 8 * rb + 2 * lk + h; // rows 16rb + 4lk + 2h (+1) = (re, im) of member mm
+            for (int v = 0; v < 4; ++v) {
+                // real row 16rb + lk + 4v = component (lk & 1) of member 8rb + 2v + lk/2
+                const int mm = 8 * rb + 2 * v + (lk >> 1);
                 uint32_t e = gb;
 #pragma unroll
                 for (int j = 0; j < K; ++j)
                     if ((mm >> j) & 1) e |= 1u << pos[j];
-                tile[e] = make_float2(acc[rb][2 * h], acc[rb][2 * h + 1]);
+                tf[2 * e + (lk & 1)] = (float)acc[rb][v];
             }
         }
     }

@@ -135,21 +135,26 @@ class Circuit:
 
     def arrays(self):
         """Pack into (ops, mats) in the IR described in the module docstring."""
-        ops = np.zeros(len(self.gates), dtype=OP_DTYPE)
-        chunks, off = [], 0
-        for i, (tg, u, cm, cv) in enumerate(self.gates):
-            ops[i]["nt"] = len(tg)
-            tt = list(tg) + [-1] * (6 - len(tg))
-            ops[i]["t"] = tt
-            ops[i]["cmask"] = cm
-            ops[i]["cvals"] = cv
-            ops[i]["moff"] = off
-            flat = np.empty(2 * u.size, dtype=np.float64)
-            flat[0::2] = u.real.ravel()
-            flat[1::2] = u.imag.ravel()
-            chunks.append(flat)
-            off += flat.size
-        mats = np.concatenate(chunks) if chunks else np.zeros(0, dtype=np.float64)
+        G = len(self.gates)
+        ops = np.zeros(G, dtype=OP_DTYPE)
+        if G == 0:
+            return ops, np.zeros(0, dtype=np.float64)
+        nt = np.fromiter((len(g[0]) for g in self.gates), dtype=np.int32, count=G)
+        t = np.full((G, 6), -1, dtype=np.int32)
+        for k in range(1, 7):
+            sel = np.nonzero(nt == k)[0]
+            if sel.size:
+                t[sel, :k] = np.array([self.gates[i][0] for i in sel], dtype=np.int32)
+        sizes = 2 * (1 << (2 * nt.astype(np.int64)))
+        moff = np.zeros(G, dtype=np.uint64)
+        moff[1:] = np.cumsum(sizes[:-1]).astype(np.uint64)
+        ops["nt"] = nt
+        ops["t"] = t
+        ops["cmask"] = np.fromiter((g[2] for g in self.gates), dtype=np.uint64, count=G)
+        ops["cvals"] = np.fromiter((g[3] for g in self.gates), dtype=np.uint64, count=G)
+        ops["moff"] = moff
+        mats = np.concatenate([np.ascontiguousarray(g[1], dtype=np.complex128).ravel().view(np.float64)
+                               for g in self.gates])
         return ops, mats
 
     def inverse(self) -> "Circuit":
@@ -208,16 +213,20 @@ def gate_microbench(n=30, seed_u3=2, seed_haar=3, seed_ctrl=4, far=15) -> Circui
 def rqc_chain(n: int, depth: int, seed: int) -> Circuit:
     """Random circuit on a 1D chain: each layer applies an i.i.d. uniform choice of
     sqrt(X)/sqrt(Y)/sqrt(W) to every qubit, then CZ on (2j, 2j+1) in even layers
-    and on (2j+1, 2j+2) in odd layers (open chain)."""
+    and on (2j+1, 2j+2) in odd layers (open chain).  The choices of all layers
+    are drawn at once, layer-major, from Generator([seed, 2])."""
     rng = _rng(seed, 2)
+    pick = rng.integers(3, size=(depth, n))
     c = Circuit(n, f"rqc_n{n}_d{depth}_s{seed}")
     choices = (SQRT_X, SQRT_Y, SQRT_W)
+    gates = c.gates
     for layer in range(depth):
+        row = pick[layer]
         for q in range(n):
-            c.g1(q, choices[int(rng.integers(3))])
-        start = layer % 2
-        for a in range(start, n - 1, 2):
-            c.g1(a + 1, Z, controls=(a,))
+            gates.append(((q,), choices[row[q]], 0, 0))
+        for a in range(layer % 2, n - 1, 2):
+            m = 1 << a
+            gates.append(((a + 1,), Z, m, m))
     return c
 
 
