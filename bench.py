@@ -1,16 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the gate engine on one MI355X.
 
-Default workload (one "step"): the per-target gate sweep on a 30-qubit
-complex128 state (16 GiB) -- one seeded U3 on every target 0..29, then seeded
-Haar-random 4x4 unitaries on adjacent pairs (t, t+1) and far pairs (t, t+15),
-each once uncontrolled and once with one control: 118 gates, each one launch
-of the per-gate kernels, state resident in HBM.
+Workloads (``--workload``), each printing ONE JSON line:
 
-Prints ONE JSON line: amplitude-updates/s (value), algorithmic HBM GB/s, the
-roofline of the dominant kernel measured with HIP events recorded by the
-library around every launch in the timed region, and the FP64 oracle timed on
-host cores on a bounded sample of the same workload.
+- ``sweep`` (default): the per-target gate sweep on a 30-qubit complex128 state
+  (16 GiB) -- one seeded U3 on every target 0..29, then seeded Haar-random 4x4
+  unitaries on adjacent pairs (t, t+1) and far pairs (t, t+15), each once
+  uncontrolled and once with one control: 118 gates, one launch each, state
+  resident in HBM.  Value: amplitude-updates/s.
+- ``circuits``: 32-qubit random chain circuit (depth 20) and full QFT of a
+  random basis state, complex64 in tile passes with 5-qubit fused blocks on
+  matrix cores, beside complex128 tile passes and complex128 gate by gate.
+  Value: credited amplitude-updates/s of the fused complex64 runs.
+- ``batch``: 4096 circuits (n log-uniform in [10, 22]; random chain / QFT /
+  Grover) in one batch: fused complex64 against plain per-gate complex128 on
+  8 streams and on 1 stream.  Value: circuits/s of the fused complex64 batch.
+- ``serve``: Poisson stream of requests (n log-uniform in [8, 28]) admitted by
+  HBM footprint, at 0.7x the saturated throughput, beside a 34-qubit complex64
+  depth-24 chain circuit with fused blocks.  Value: served circuits/s, with
+  p50/p99 latency.
+
+Each line carries the roofline of the dominant kernel (HIP events recorded by
+the library around its launches, or the batch's device time) and the FP64
+oracle timed on host cores on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -34,17 +46,67 @@ def _args():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--n", type=int, default=30)
-    p.add_argument("--dtype", choices=["c128", "c64"], default="c128")
-    p.add_argument("--mode", choices=["pergate", "planned"], default="pergate")
+    p.add_argument("--workload", choices=["sweep", "circuits", "batch", "serve"], default="sweep")
+    p.add_argument("--n", type=int, default=0, help="qubits (0 = the workload's default: 30 / 32 / - / 34)")
+    p.add_argument("--dtype", choices=["c128", "c64"], default="c128", help="sweep only")
+    p.add_argument("--mode", choices=["pergate", "planned"], default="pergate", help="sweep only")
+    p.add_argument("--count", type=int, default=0, help="circuits of the batch / requests of the stream")
+    p.add_argument("--no-baselines", action="store_true",
+                   help="circuits/batch: skip the per-gate complex128 comparison runs")
+    p.add_argument("--qps-sweep", action="store_true", help="serve: also run 0.3x, 0.5x and 1.0x of saturation")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    p.add_argument("--cpu-n", type=int, default=26, help="qubits of the oracle sample")
+    p.add_argument("--cpu-n", type=int, default=0, help="qubits of the oracle sample (0 = workload default)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run 3 torch copies of 4 GiB (reference for HBM byte counters) and exit")
     return p.parse_args()
 
 
-def cpu_baseline(n_cpu: int) -> dict:
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _updates(n, ops):
+    """Amplitude-updates credited to a gate list: 2^(n - controls) per gate."""
+    cm = np.ascontiguousarray(ops["cmask"], dtype=np.uint64)
+    nc = np.unpackbits(cm.view(np.uint8)).reshape(-1, 64).sum(axis=1, dtype=np.int64)
+    return int(np.sum(np.left_shift(np.int64(1), n - nc)))
+
+
+def _header(a, metric, value, unit, ms_per_step, dtype, data, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": data, "config": config}
+
+
+def _kinds(qs, recs):
+    """Per kernel class totals from the library's launch trace."""
+    kinds = {}
+    for r in recs:
+        k = qs.KIND_NAMES[int(r["kind"])]
+        d = kinds.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0})
+        d["launches"] += 1
+        d["ms"] += float(r["ms"])
+        d["bytes"] += int(r["bytes"])
+    for d in kinds.values():
+        d["avg_ms"] = d["ms"] / d["launches"]
+        d["avg_bytes"] = d["bytes"] / d["launches"]
+        d["gbs"] = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    return kinds
+
+
+def _roofline(kinds, traffic=None):
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    D = kinds[dom]
+    achieved = D["avg_bytes"] / (D["avg_ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": D["avg_bytes"]}
+
+
+# ------------------------------------------------------------------ CPU legs
+
+def cpu_baseline_sweep(n_cpu: int) -> dict:
     """The FP64 oracle on the same gate sweep at n_cpu qubits (bounded sample)."""
     import oracle
     import workloads as W
@@ -55,9 +117,450 @@ def cpu_baseline(n_cpu: int) -> dict:
     t0 = time.perf_counter()
     oracle.run(n_cpu, ops, mats, psi)
     dt = time.perf_counter() - t0
-    updates = sum(1 << (n_cpu - bin(int(o["cmask"])).count("1")) for o in ops)
-    return {"value": updates / dt, "unit": "amp-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": _updates(n_cpu, ops) / dt, "unit": "amp-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
             "sample": f"gate sweep at n={n_cpu} complex128 ({len(ops)} gates, one pass, {dt:.1f} s)"}
+
+
+def cpu_baseline_circuits(n_cpu: int) -> dict:
+    """The oracle on the same two circuits at n_cpu qubits."""
+    import oracle
+    import workloads as W
+
+    upd, dt = 0, 0.0
+    for c in (W.rqc_chain(n_cpu, 20, 5), W.qft(n_cpu, 12345 % (1 << n_cpu))):
+        ops, mats = c.arrays()
+        t0 = time.perf_counter()
+        oracle.run_circuit(c)
+        dt += time.perf_counter() - t0
+        upd += _updates(n_cpu, ops)
+    return {"value": upd / dt, "unit": "amp-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"depth-20 chain circuit + QFT at n={n_cpu} complex128 ({dt:.1f} s)"}
+
+
+def cpu_baseline_mix(circs, budget_s: float = 15.0) -> dict:
+    """The oracle on the circuits of the mix in order until budget_s is spent,
+    skipping any whose estimated time exceeds what is left of the budget; its
+    amplitude-update rate is scaled to circuits/s with the whole mix's mean
+    amplitude-updates per circuit."""
+    import oracle
+
+    upd_all = [_updates(c.n, c.arrays()[0]) for c in circs]
+    done, skipped, upd, dt, rate = 0, 0, 0, 0.0, 1e9
+    for c, u in zip(circs, upd_all):
+        if dt >= budget_s:
+            break
+        if u / rate > budget_s - dt:
+            skipped += 1
+            continue
+        t0 = time.perf_counter()
+        oracle.run_circuit(c)
+        dt += time.perf_counter() - t0
+        upd += u
+        done += 1
+        rate = upd / dt
+    return {"value": rate / (sum(upd_all) / len(upd_all)), "unit": "circuits/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "amp_updates_per_s": rate,
+            "sample": f"{done} circuits of the same mix in order ({skipped} skipped as too long for the "
+                      f"{budget_s:.0f} s budget) in {dt:.1f} s, complex128; rate scaled by the mix's mean "
+                      f"amplitude-updates per circuit"}
+
+
+# ------------------------------------------------------------------ workloads
+
+def _random_state_torch(torch, n, tdt, seed):
+    """Seeded complex Gaussian state, normalised in FP64, generated on the device."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    psi = torch.empty(1 << n, dtype=tdt, device="cuda")
+    chunk = 1 << 26
+    nrm2 = 0.0
+    for i in range(0, 1 << n, chunk):
+        blk = torch.randn(min(chunk, (1 << n) - i), dtype=torch.complex128, device="cuda", generator=g)
+        nrm2 += float((blk.real.square().sum() + blk.imag.square().sum()).item())
+        psi[i:i + blk.numel()] = blk.to(tdt)
+    psi /= math.sqrt(nrm2)
+    return psi
+
+
+def run_sweep(a, qs, torch, W):
+    n = a.n or 30
+    dt = qs.QS_C128 if a.dtype == "c128" else qs.QS_C64
+    tdt = torch.complex128 if dt == qs.QS_C128 else torch.complex64
+    S = 16 if dt == qs.QS_C128 else 8
+    circ = W.gate_microbench(n)
+    ops, mats = circ.arrays()
+    gates = list(circ.gates)
+    upd_step = _updates(n, ops)
+    bytes_step = 2 * S * upd_step
+    psi = _random_state_torch(torch, n, tdt, 2)
+    torch.cuda.synchronize()
+    s = qs.State.from_torch(psi)
+
+    def step():
+        if a.mode == "planned":
+            s.run(ops, mats, mode=0)
+        else:
+            for tg, u, cm, cv in gates:
+                if len(tg) == 1:
+                    qs.qs_apply_1q(s.h, tg[0], u, cm, cv)
+                else:
+                    qs.qs_apply_2q(s.h, tg[0], tg[1], u, cm, cv)
+
+    for _ in range(a.warmup):
+        step()
+    s.sync()
+    torch.cuda.synchronize()
+    qs.qs_trace_enable(s.h, True)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    s.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    recs = qs.qs_trace_read(s.h, 1 << 20)
+    qs.qs_trace_enable(s.h, False)
+    norm = s.norm()
+    s.close()
+    kinds = _kinds(qs, recs)
+    rl = _roofline(kinds)
+    if a.mode == "pergate":
+        rl["traffic"] = measured_traffic(rl["kernel"], f"gate_sweep_n{n}_{a.dtype}")
+    out = _header(a, "amplitude-updates/s", upd_step * a.steps / elapsed, "amp-updates/s",
+                  elapsed * 1e3 / a.steps, "f64" if dt == qs.QS_C128 else "f32",
+                  "synthetic (seeded complex Gaussian state, seeded U3 and Haar 4x4 gates)",
+                  {"workload": f"gate sweep n={n} {a.dtype}: U3 on t=0..{n-1}, Haar 4x4 on (t,t+1) and "
+                               f"(t,t+15), uncontrolled and 1-controlled; {len(gates)} gates/step",
+                   "n": n, "state_bytes": (1 << n) * S, "gates_per_step": len(gates), "mode": a.mode})
+    out.update({
+        "hbm_gbs_algorithmic": bytes_step * a.steps / elapsed / 1e9,
+        "hbm_frac_algorithmic": bytes_step * a.steps / elapsed / 1e9 / PEAK_HBM_GBS,
+        "roofline": rl,
+        "kernels": {k: {"launches": d["launches"], "avg_ms": round(d["avg_ms"], 4), "gbs": round(d["gbs"], 1)}
+                    for k, d in kinds.items()},
+        "event_coverage": sum(d["ms"] for d in kinds.values()) / (elapsed * 1e3),
+        "norm_minus_1": norm - 1.0,
+    })
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_sweep(a.cpu_n or 26)
+    return out
+
+
+def _fidelity(torch, ref, x):
+    """<ref|x> and ||x||^2 accumulated in FP64 over chunks; max |x - ref|."""
+    acc, nx, err = 0j, 0.0, 0.0
+    step = 1 << 26
+    for i in range(0, ref.numel(), step):
+        r = ref[i:i + step]
+        b = x[i:i + step].to(torch.complex128)
+        acc += complex(torch.vdot(r, b).item())
+        nx += float((b.real.square().sum() + b.imag.square().sum()).item())
+        err = max(err, float((b - r).abs().max().item()))
+    return abs(acc) ** 2, nx - 1.0, err
+
+
+def run_circuits(a, qs, torch, W):
+    n = a.n or 32
+    work = {"rqc_d20": W.rqc_chain(n, 20, 5),
+            "qft": W.qft(n, int(np.random.default_rng(6).integers(1 << n)))}
+    arrs = {k: c.arrays() for k, c in work.items()}
+    upd = {k: _updates(n, arrs[k][0]) for k in work}
+    variants = [("c64_fused5", qs.QS_C64, 0, 5, a.steps, a.warmup), ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
+    if not a.no_baselines:
+        variants.append(("c128_pergate", qs.QS_C128, 1, 0, 1, 0))
+    res, traces, states = {}, {}, {}
+    for name, dt, mode, fk, steps, warm in variants:
+        tdt = torch.complex128 if dt == qs.QS_C128 else torch.complex64
+        for k, c in work.items():
+            ops, mats = arrs[k]
+            psi = torch.empty(1 << n, dtype=tdt, device="cuda")
+            s = qs.State.from_torch(psi)
+            plan = qs.qs_plan_circuit(n, dt, ops, mats, mode=0, fuse_k=fk) if mode == 0 else None
+            for _ in range(warm):
+                s.init_basis(c.init_basis)
+                s.run(ops, mats, mode=mode, fuse_k=fk)
+            s.sync()
+            if name == "c64_fused5":
+                qs.qs_trace_enable(s.h, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                s.init_basis(c.init_basis)
+                s.run(ops, mats, mode=mode, fuse_k=fk)
+            s.sync()
+            el = (time.perf_counter() - t0) / steps
+            if name == "c64_fused5":
+                traces[k] = qs.qs_trace_read(s.h, 1 << 20)
+                qs.qs_trace_enable(s.h, False)
+            s.close()
+            res.setdefault(name, {})[k] = {"ms": el * 1e3, "amp_updates_per_s": upd[k] / el,
+                                           "gates": len(ops), "passes": None if plan is None else plan[0]}
+            _log(f"circuits {name} {k}: {el * 1e3:.1f} ms")
+            if name in ("c64_fused5", "c128_tiles"):
+                states.setdefault(k, {})[name] = psi
+            else:
+                del psi
+        torch.cuda.synchronize()
+        if name == "c128_tiles":  # both precisions of each circuit are resident: compare them
+            for k in work:
+                f, dn, err = _fidelity(torch, states[k]["c128_tiles"], states[k]["c64_fused5"])
+                res["c64_fused5"][k].update({"fidelity_vs_c128": f, "norm2_minus_1": dn, "max_abs_err_vs_c128": err})
+                del states[k]["c64_fused5"]
+            if work["qft"].name.startswith("qft"):  # c128 QFT against its closed form on samples
+                x, N = work["qft"].init_basis, 1 << n
+                y = np.random.default_rng(7).integers(0, N, size=1 << 16, dtype=np.int64)
+                want = np.exp(2j * np.pi * ((x * y.astype(object)) % N).astype(np.float64) / N) / math.sqrt(N)
+                got = states["qft"]["c128_tiles"][torch.from_numpy(y).cuda()].cpu().numpy()
+                res["c128_tiles"]["qft"]["max_abs_err_closed_form_sampled"] = float(np.max(np.abs(got - want)))
+            states.clear()
+            torch.cuda.empty_cache()
+    tot = sum(upd.values())
+    ms64 = sum(r["ms"] for r in res["c64_fused5"].values())
+    kinds = _kinds(qs, np.concatenate(list(traces.values())))
+    out = _header(a, "amplitude-updates/s", tot / (ms64 * 1e-3), "amp-updates/s", ms64, "f32",
+                  "synthetic (seeded chain circuit of sqrt(X)/sqrt(Y)/sqrt(W) + CZ layers; QFT of a seeded basis "
+                  "state)",
+                  {"workload": f"n={n}: depth-20 chain circuit ({len(arrs['rqc_d20'][0])} gates) + QFT "
+                               f"({len(arrs['qft'][0])} gates); complex64 tile passes with 5-qubit fused blocks",
+                   "n": n, "state_bytes_c64": 8 << n, "state_bytes_c128": 16 << n})
+    for name in res:
+        ms = sum(r["ms"] for r in res[name].values())
+        res[name]["total_ms"] = ms
+        res[name]["speedup_of_c64_fused5"] = ms / ms64
+    out.update({"variants": res, "roofline": _roofline(kinds),
+                "kernels": {k: {"launches": d["launches"], "avg_ms": round(d["avg_ms"], 4), "gbs": round(d["gbs"], 1)}
+                            for k, d in kinds.items()}})
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_circuits(a.cpu_n or 25)
+    return out
+
+
+def _closed_form(c):
+    """QFT and Grover results in closed form (None for other circuits)."""
+    n = c.n
+    if c.name.startswith("qft"):
+        x, N = c.init_basis, 1 << n
+        yv = np.arange(N, dtype=np.int64)
+        return np.exp(2j * np.pi * ((x * yv) % N) / N) / math.sqrt(N)
+    if c.name.startswith("grover"):
+        mark = int(c.name.split("_m")[1].split("_")[0])
+        R = int(c.name.split("_r")[1])
+        th = math.asin(2.0 ** (-n / 2))
+        sg = (-1) ** R
+        v = np.full(1 << n, sg * math.cos((2 * R + 1) * th) / math.sqrt((1 << n) - 1), dtype=complex)
+        v[mark] = sg * math.sin((2 * R + 1) * th)
+        return v
+    return None
+
+
+def run_batch(a, qs, torch, W):
+    count = a.count or 4096
+    t0 = time.perf_counter()
+    circs = W.circuit_mix(count, 7)
+    arrs = [(c.n, *c.arrays(), c.init_basis) for c in circs]
+    _log(f"batch: generated {count} circuits in {time.perf_counter() - t0:.1f} s")
+    upd_total = sum(_updates(c.n, x[1]) for c, x in zip(circs, arrs))
+
+    def one(dt, mode, streams, steps, warm):
+        for _ in range(warm):
+            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams)
+            qs.qs_batch_wait(b)
+            qs.qs_batch_release(b)
+        e2e, dev, keep = [], [], None
+        for i in range(steps):
+            t0 = time.perf_counter()
+            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams)
+            t1 = time.perf_counter()
+            qs.qs_batch_wait(b)
+            t2 = time.perf_counter()
+            st = qs.qs_batch_get_stats(b)
+            e2e.append(t2 - t0)
+            dev.append(st["device_ms"])
+            if i == steps - 1:
+                keep = b
+            else:
+                qs.qs_batch_release(b)
+        r = {"circuits_per_s": count / float(np.median(e2e)), "end_to_end_ms": 1e3 * float(np.median(e2e)),
+             "device_ms": float(np.median(dev)), "submit_ms": 1e3 * (t1 - t0), "launches": st["launches"],
+             "passes": st["passes"], "class_ms": st["class_ms"], "class_circuits": st["class_circuits"],
+             "amp_updates_per_s": upd_total / float(np.median(e2e))}
+        return r, keep
+
+    res = {}
+    r, b64 = one(qs.QS_C64, 0, 0, a.steps, a.warmup)
+    res["c64_fused"] = r
+    _log(f"batch c64 fused: {r['circuits_per_s']:.0f} circuits/s")
+    # closed-form check of sampled QFT / Grover circuits of the fused complex64 batch
+    rng = np.random.default_rng(3)
+    pick = [i for i in rng.permutation(count) if circs[i].n <= 16 and _closed_form(circs[i]) is not None][:32]
+    fmin, emax = 1.0, 0.0
+    for i in pick:
+        got = qs.qs_batch_download(b64, int(i), qs.QS_C64).astype(np.complex128)
+        want = _closed_form(circs[i])
+        fmin = min(fmin, abs(np.vdot(want, got)) ** 2)
+        emax = max(emax, float(np.max(np.abs(got - want))))
+    r["closed_form_check"] = {"circuits": len(pick), "min_fidelity": fmin, "max_abs_err": emax}
+    qs.qs_batch_release(b64)
+    r, b = one(qs.QS_C128, 0, 0, 1, 1)
+    qs.qs_batch_release(b)
+    res["c128_fused"] = r
+    _log(f"batch c128 fused: {r['circuits_per_s']:.0f} circuits/s")
+    if not a.no_baselines:
+        for name, streams in (("c128_pergate_8streams", 8), ("c128_pergate_1stream", 1)):
+            r, b = one(qs.QS_C128, 1, streams, 1, 0)
+            qs.qs_batch_release(b)
+            res[name] = r
+            _log(f"batch {name}: {r['circuits_per_s']:.0f} circuits/s")
+        res["c64_fused"]["ratio_vs_c128_pergate_8streams"] = (res["c64_fused"]["circuits_per_s"] /
+                                                              res["c128_pergate_8streams"]["circuits_per_s"])
+    v = res["c64_fused"]
+    ns = np.array([c.n for c in circs])
+    out = _header(a, "batched circuits/s", v["circuits_per_s"], "circuits/s", v["end_to_end_ms"], "f32",
+                  "synthetic (seeded mix of chain circuits, QFTs and Grover searches)",
+                  {"workload": f"{count} circuits, n log-uniform in [10,22] (mean {ns.mean():.1f}), one third each "
+                               "chain circuit (depth 20-200), QFT, Grover (<=200 gates); complex64 fused batch",
+                   "circuits": count, "gates": int(sum(len(x[1]) for x in arrs))})
+    # aggregate roofline: algorithmic bytes of every pass of every circuit over the batch's device time
+    alg = 0
+    for c, x in zip(circs, arrs):
+        if c.n <= 13:  # whole circuit in LDS: one read of nothing, one write of the state
+            alg += 8 << c.n
+        else:
+            alg += qs.qs_plan_circuit(c.n, qs.QS_C64, x[1], x[2], mode=0)[0] * (16 << c.n)
+    ach = alg / (v["device_ms"] * 1e-3) / 1e9
+    out.update({"variants": res, "roofline": {
+        "bound": "hbm", "kernel": "all batch launches (aggregate)", "achieved": ach, "peak": PEAK_HBM_GBS,
+        "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
+        "note": "states of n<=22 (<=32 MiB) stay in L2/Infinity Cache, so HBM is a loose roof here"}})
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_mix(circs)
+    return out
+
+
+def _serve_stream(qs, circs, arrivals, dt, budget=0, hook=None):
+    """Submit each request at its arrival time; poll until every one is done
+    (calling hook() between polls).  Returns latencies and the served rate."""
+    srv = qs.qs_server_create(dtype=dt, hbm_budget=budget)
+    done, ids = {}, []
+    try:
+        t0 = time.perf_counter()
+        i = 0
+        while len(done) < len(circs):
+            now = time.perf_counter() - t0
+            while i < len(circs) and arrivals[i] <= now:
+                ids.append(qs.qs_server_submit(srv, circs[i]))
+                i += 1
+            for r in qs.qs_server_poll(srv):
+                done[r["id"]] = r
+                qs.qs_server_release(srv, r["id"])
+            if hook is not None:
+                hook()
+            if i == len(circs) and time.perf_counter() - t0 > arrivals[-1] + 900:
+                raise RuntimeError("serving did not drain")
+            time.sleep(0.0001)
+        st = qs.qs_server_get_stats(srv)
+    finally:
+        qs.qs_server_destroy(srv)
+    lat = np.array([done[k]["t_done_ms"] - done[k]["t_submit_ms"] for k in ids])
+    fails = sum(1 for k in ids if done[k]["status"] != 0)
+    span = (max(done[k]["t_done_ms"] for k in ids) - min(done[k]["t_submit_ms"] for k in ids)) * 1e-3
+    return {"requests": len(ids), "failed": fails, "circuits_per_s": len(ids) / span,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "rounds": st["rounds"], "launches": st["launches"],
+            "peak_bytes": st["peak_bytes"], "budget_bytes": st["budget_bytes"]}
+
+
+class _BigJob:
+    """A large complex64 circuit kept running beside the request stream: it is
+    run forward and then inverted (echo), and the cycle is enqueued again
+    whenever the previous one has finished, until stop()."""
+
+    def __init__(self, qs, torch, W, n):
+        self.qs, self.torch, self.n = qs, torch, n
+        c = W.rqc_chain(n, 24, 9)
+        self.ops, self.mats = c.arrays()
+        self.iops, self.imats = c.inverse().arrays()
+        self.side = torch.cuda.Stream()
+        self.psi = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+        self.psi[0] = 1
+        torch.cuda.synchronize()
+        self.s = qs.State.from_torch(self.psi, stream=self.side.cuda_stream)
+        self.cycles = []  # (ev_start, ev_forward_done, ev_echo_done)
+        self.enqueue()
+
+    def enqueue(self):
+        ev = [self.torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(self.side)
+        self.s.run(self.ops, self.mats, mode=0, fuse_k=5)
+        ev[1].record(self.side)
+        self.s.run(self.iops, self.imats, mode=0, fuse_k=5)
+        ev[2].record(self.side)
+        self.cycles.append(ev)
+
+    def hook(self):
+        if self.cycles[-1][2].query():
+            self.enqueue()
+
+    def stop(self):
+        self.side.synchronize()
+        qs = self.qs
+        a0 = complex(self.psi[0].item())
+        fw = [c[0].elapsed_time(c[1]) for c in self.cycles]
+        ec = [c[1].elapsed_time(c[2]) for c in self.cycles]
+        out = {"n": self.n, "dtype": "c64", "gates": len(self.ops), "cycles": len(self.cycles),
+               "forward_ms": fw, "echo_ms": ec, "echo_prob_0": abs(a0) ** 2, "norm2_minus_1": self.s.norm() - 1.0,
+               "passes": qs.qs_plan_circuit(self.n, qs.QS_C64, self.ops, self.mats, mode=0, fuse_k=5)[0]}
+        out["pass_gbs_algorithmic"] = out["passes"] * (16 << self.n) / (float(np.median(fw)) * 1e-3) / 1e9
+        self.s.close()
+        del self.psi
+        self.torch.cuda.empty_cache()
+        return out
+
+
+def run_serve(a, qs, torch, W):
+    nb = 34 if a.n == 0 else a.n
+    count = a.count or 200
+    circs = W.circuit_mix(count, 8, n_lo=8, n_hi=28)
+    _log(f"serve: {count} requests, {sum(len(c) for c in circs)} gates")
+    dt = qs.QS_C64
+    sat_n = min(count, 100)
+    # saturated throughput with nothing alongside: the first requests all at once
+    alone = _serve_stream(qs, circs[:sat_n], np.zeros(sat_n), dt)
+    _log(f"serve saturated, alone: {alone['circuits_per_s']:.1f} circuits/s")
+    big, hook, sat = None, None, alone
+    if nb > 0:
+        big = _BigJob(qs, torch, W, nb)
+        hook = big.hook
+        sat = _serve_stream(qs, circs[:sat_n], np.zeros(sat_n), dt, hook=hook)
+        _log(f"serve saturated, beside n={nb}: {sat['circuits_per_s']:.1f} circuits/s")
+    qps = 0.7 * sat["circuits_per_s"]
+    main = _serve_stream(qs, circs, W.poisson_arrivals(count, qps, 8), dt, hook=hook)
+    main["qps"] = qps
+    _log(f"serve at {qps:.1f} qps: p50 {main['p50_ms']:.1f} ms p99 {main['p99_ms']:.1f} ms")
+    sweep = {}
+    if a.qps_sweep:
+        for f in (0.3, 0.5, 1.0):
+            r = _serve_stream(qs, circs, W.poisson_arrivals(count, f * sat["circuits_per_s"], 8), dt, hook=hook)
+            sweep[str(f)] = {k: r[k] for k in ("circuits_per_s", "p50_ms", "p99_ms", "failed")}
+    if big is not None:
+        big = big.stop()
+    ns = np.array([c.n for c in circs])
+    out = _header(a, "served circuits/s", main["circuits_per_s"], "circuits/s", None, "f32",
+                  "synthetic (seeded Poisson arrivals; seeded mix of chain circuits, QFTs and Grover searches)",
+                  {"workload": f"{count} requests, n log-uniform in [8,28] (mean {ns.mean():.1f}), complex64, "
+                               f"Poisson at 0.7x the saturated rate" +
+                               (f", beside an n={nb} complex64 depth-24 chain circuit with 5-qubit fused blocks "
+                                "run forward and back for the whole stream" if nb else ""),
+                   "requests": count, "qps": qps})
+    out.update({"latency_ms": {"p50": main["p50_ms"], "p99": main["p99_ms"]}, "stream": main,
+                "saturated": sat, "saturated_alone": alone, "big_circuit": big, "qps_sweep": sweep or None})
+    if big:
+        ach = big["pass_gbs_algorithmic"]
+        out["roofline"] = {"bound": "hbm", "kernel": f"tile passes of the n={nb} circuit (beside the stream)",
+                           "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                           "traffic": None}
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_mix(circs)
+    return out
 
 
 def measured_traffic(kernel_class: str, tag: str):
@@ -103,103 +606,8 @@ def main():
     import paper_2506_09198_amd as qs
     import workloads as W
 
-    n = a.n
-    dt = qs.QS_C128 if a.dtype == "c128" else qs.QS_C64
-    tdt = torch.complex128 if dt == qs.QS_C128 else torch.complex64
-    S = 16 if dt == qs.QS_C128 else 8
-    circ = W.gate_microbench(n)
-    ops, mats = circ.arrays()
-    gates = [(tg, u, cm, cv) for (tg, u, cm, cv) in circ.gates]
-    upd_step = sum(1 << (n - bin(cm).count("1")) for (_, _, cm, _) in gates)
-    bytes_step = 2 * S * upd_step
-
-    # seeded synthetic input, resident in HBM: complex Gaussian normalised in FP64
-    g = torch.Generator(device="cuda")
-    g.manual_seed(2)
-    psi = torch.empty(1 << n, dtype=tdt, device="cuda")
-    chunk = 1 << 26
-    nrm2 = 0.0
-    for i in range(0, 1 << n, chunk):
-        blk = torch.randn(min(chunk, (1 << n) - i), dtype=torch.complex128, device="cuda", generator=g)
-        nrm2 += float((blk.real.square().sum() + blk.imag.square().sum()).item())
-        psi[i:i + blk.numel()] = blk.to(tdt)
-    psi /= math.sqrt(nrm2)
-    torch.cuda.synchronize()
-    s = qs.State.from_torch(psi)
-
-    def step():
-        if a.mode == "planned":
-            s.run(ops, mats, mode=0)
-        else:
-            for tg, u, cm, cv in gates:
-                if len(tg) == 1:
-                    qs.qs_apply_1q(s.h, tg[0], u, cm, cv)
-                else:
-                    qs.qs_apply_2q(s.h, tg[0], tg[1], u, cm, cv)
-
-    for _ in range(a.warmup):
-        step()
-    s.sync()
-    torch.cuda.synchronize()
-    qs.qs_trace_enable(s.h, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step()
-    s.sync()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    recs = qs.qs_trace_read(s.h, 1 << 20)
-    qs.qs_trace_enable(s.h, False)
-    norm = s.norm()
-
-    value = upd_step * a.steps / elapsed
-    # per kernel class, from the HIP events around each launch
-    kinds = {}
-    for r in recs:
-        k = qs.KIND_NAMES[int(r["kind"])]
-        d = kinds.setdefault(k, {"launches": 0, "ms": 0.0, "bytes": 0})
-        d["launches"] += 1
-        d["ms"] += float(r["ms"])
-        d["bytes"] += int(r["bytes"])
-    for k, d in kinds.items():
-        d["avg_ms"] = d["ms"] / d["launches"]
-        d["avg_bytes"] = d["bytes"] / d["launches"]
-        d["gbs"] = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    dom = max(kinds, key=lambda k: kinds[k]["ms"])
-    D = kinds[dom]
-    achieved = D["avg_bytes"] / (D["avg_ms"] * 1e-3) / 1e9
-    kern_ms = sum(d["ms"] for d in kinds.values())
-    out = {
-        "metric": "amplitude-updates/s",
-        "value": value,
-        "unit": "amp-updates/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": elapsed * 1e3 / a.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if dt == qs.QS_C128 else "f32",
-        "data": "synthetic (seeded complex Gaussian state, seeded U3 and Haar 4x4 gates)",
-        "config": {"workload": f"gate sweep n={n} {a.dtype}: U3 on t=0..{n-1}, Haar 4x4 on (t,t+1) and "
-                               f"(t,t+15), uncontrolled and 1-controlled; {len(gates)} gates/step",
-                   "n": n, "state_bytes": (1 << n) * S, "gates_per_step": len(gates), "mode": a.mode},
-        "hbm_gbs_algorithmic": bytes_step * a.steps / elapsed / 1e9,
-        "hbm_frac_algorithmic": bytes_step * a.steps / elapsed / 1e9 / PEAK_HBM_GBS,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": (measured_traffic(dom, f"gate_sweep_n{n}_{a.dtype}") if a.mode == "pergate" else None),
-                     "traffic_unit": "HBM bytes/launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": D["avg_bytes"]},
-        "kernels": {k: {"launches": d["launches"], "avg_ms": round(d["avg_ms"], 4), "gbs": round(d["gbs"], 1)}
-                    for k, d in kinds.items()},
-        "event_coverage": kern_ms / (elapsed * 1e3),
-        "norm_minus_1": norm - 1.0,
-    }
-    if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(a.cpu_n)
+    fn = {"sweep": run_sweep, "circuits": run_circuits, "batch": run_batch, "serve": run_serve}[a.workload]
+    out = fn(a, qs, torch, W)
     print(json.dumps(out), flush=True)
 
 

@@ -168,6 +168,18 @@ qs_status qs_run_circuit(qs_state s, const qs_op* ops, int64_t n_ops,
 qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
                           int64_t n_mats, const qs_run_opts* opts, int64_t* n_passes, int64_t* n_ops_out);
 
+/* The execution order qs_run_circuit (mode 0, no fused blocks) gives the
+ * circuit's gates (host only; needs no GPU).  Gates that commute (neither
+ * acts non-diagonally on a qubit the other touches; controls act
+ * diagonally) may be reordered so that one tile pass absorbs more of them.
+ * order[i] is the circuit index of the i-th gate executed and pass_of[i] its
+ * pass (both n_ops long, caller-owned); tile_mask, if not NULL, receives each
+ * pass's tile qubits as a bit mask (room for n_ops entries).  Same validation
+ * as qs_run_circuit. */
+qs_status qs_plan_order(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                        int64_t n_mats, const qs_run_opts* opts, int64_t* order, int32_t* pass_of,
+                        uint64_t* tile_mask);
+
 /* ------------------------------------------------------------------ reductions */
 
 /* Marginal probabilities over m distinct qubits (0 <= m <= 24): out[o] (2^m

@@ -106,6 +106,8 @@ def _load():
         "qs_run_circuit": ([vp, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts)], i32),
         "qs_plan_circuit": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
+        "qs_plan_order": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
+                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(u64)], i32),
         "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
         "qs_norm": ([vp, dp], i32),
         "qs_sync": ([vp], i32),
@@ -270,6 +272,24 @@ def qs_plan_circuit(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, mode:
                                mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o),
                                ctypes.byref(npass), ctypes.byref(nops)))
     return npass.value, nops.value
+
+
+def qs_plan_order(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_qubits: int = 0):
+    """Host-only: (order, pass_of, tile_masks) of the planned execution."""
+    ops = np.ascontiguousarray(ops)
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    k = len(ops)
+    order = np.zeros(max(k, 1), dtype=np.int64)
+    pass_of = np.zeros(max(k, 1), dtype=np.int32)
+    masks = np.zeros(max(k, 1), dtype=np.uint64)
+    o = _RunOpts(0, 0, tile_qubits)
+    _check(lib.qs_plan_order(n, dtype, ctypes.c_void_p(ops.ctypes.data if k else 0), k,
+                             mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o),
+                             order.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             pass_of.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
+    npass = int(pass_of[:k].max()) + 1 if k else 0
+    return order[:k], pass_of[:k], masks[:npass]
 
 
 def qs_probabilities(s: int, qubits) -> np.ndarray:

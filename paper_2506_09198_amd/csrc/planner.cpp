@@ -1,18 +1,20 @@
 // Circuit planner and tile-pass executor.
 //
-// Gates are taken strictly in circuit order.  A pass keeps a set Q of at most
-// m tile qubits; a non-diagonal gate joins the current pass when its targets
-// fit into Q (growing Q), otherwise the pass is closed and a new one starts.
-// Diagonal gates (CZ, controlled phases, phase flips) join whatever pass is
-// open: they scale amplitudes elementwise and need no tile qubits.  A closed
-// pass is padded with the lowest unused qubits so its tiles are built from the
-// longest possible contiguous runs.  Each pass costs one read and one write of
-// the state, against one per gate when gates are launched one by one.
+// A pass keeps a set Q of at most m tile qubits and takes every gate that is
+// ready (all gates it does not commute with are done) and fits: a
+// non-diagonal gate when its targets fit into Q (growing Q), a diagonal gate
+// (CZ, controlled phases, phase flips) always, since it scales amplitudes
+// elementwise and needs no tile qubits.  Gates that commute are reordered;
+// gates that do not keep their circuit order.  A closed pass is padded with
+// the lowest unused qubits so its tiles are built from the longest possible
+// contiguous runs.  Each pass costs one read and one write of the state,
+// against one per gate when gates are launched one by one.
 #include "planner.h"
 
 #include <algorithm>
 #include <complex>
 #include <cstring>
+#include <set>
 
 namespace qs {
 
@@ -264,6 +266,7 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
                 pool.insert(pool.end(), U, U + 2 * d * d);
             }
             P.ops.push_back(t);
+            P.src.push_back((int64_t)(it.op - ops));
             P.gates += 1;
             P.updates += 1ull << (n - __builtin_popcountll(o.cmask));
         }
@@ -274,26 +277,93 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
         qmask = 0;
     };
 
-    for (int64_t g = 0; g < n_ops; ++g) {
-        const qs_op& o = ops[g];
-        const bool diag = is_diagonal(mats + o.moff, o.nt);
-        if (diag) {
-            items.push_back({&o, true});
-            continue;
+    // Dependencies.  A gate acts non-diagonally on its dense targets and
+    // diagonally on its controls (and on a diagonal gate's targets); two
+    // gates commute when neither acts non-diagonally on a qubit the other
+    // touches.  Gate g waits for the last non-diagonal gate on each of its
+    // qubits and, on its non-diagonal qubits, for the diagonal gates since.
+    std::vector<uint8_t> isdiag((size_t)n_ops);
+    std::vector<uint64_t> ndq((size_t)n_ops);
+    std::vector<int> indeg((size_t)n_ops, 0);
+    std::vector<std::pair<int, int>> edges;
+    {
+        int last_nd[64];
+        std::vector<int> since[64];
+        for (int q = 0; q < 64; ++q) last_nd[q] = -1;
+        for (int64_t g = 0; g < n_ops; ++g) {
+            const qs_op& o = ops[g];
+            const bool diag = is_diagonal(mats + o.moff, o.nt);
+            uint64_t tm = 0;
+            for (int j = 0; j < o.nt; ++j) tm |= 1ull << o.t[j];
+            const uint64_t nd = diag ? 0 : tm, dq = (diag ? tm : 0) | o.cmask;
+            isdiag[g] = diag;
+            ndq[g] = nd;
+            for (uint64_t b = nd | dq; b; b &= b - 1) {
+                const int q = __builtin_ctzll(b);
+                if (last_nd[q] >= 0) edges.push_back({last_nd[q], (int)g});
+                if ((nd >> q) & 1)
+                    for (int h : since[q]) edges.push_back({h, (int)g});
+            }
+            for (uint64_t b = nd; b; b &= b - 1) {
+                const int q = __builtin_ctzll(b);
+                last_nd[q] = (int)g;
+                since[q].clear();
+            }
+            for (uint64_t b = dq; b; b &= b - 1) since[__builtin_ctzll(b)].push_back((int)g);
         }
-        uint64_t tm = 0;
-        for (int j = 0; j < o.nt; ++j) tm |= 1ull << o.t[j];
-        uint64_t need = qmask | tm | lowQ;
-        if (__builtin_popcountll(need) > m) {
-            close();
-            need = tm | lowQ;
-            if (__builtin_popcountll(need) > m) need = tm; // the gate alone: padding fills low qubits
-        }
-        qmask = need;
-        items.push_back({&o, false});
     }
-    if (qmask == 0 && !items.empty()) qmask = lowQ; // only diagonal gates
-    close();
+    std::vector<int> eoff((size_t)n_ops + 1, 0), esucc(edges.size());
+    for (auto& e : edges) eoff[e.first + 1] += 1;
+    for (int64_t g = 0; g < n_ops; ++g) eoff[g + 1] += eoff[g];
+    {
+        std::vector<int> fill(eoff.begin(), eoff.end() - 1);
+        for (auto& e : edges) {
+            esucc[fill[e.first]++] = e.second;
+            indeg[e.second] += 1;
+        }
+    }
+
+    // Passes.  Each pass starts from the forced low qubits and takes the
+    // ready gates in circuit order: a diagonal gate always (its qubits need
+    // not be in the tile), a dense gate when its targets fit the tile, which
+    // then grows by them.  Gates made ready inside the pass are considered in
+    // the same sweep, so one pass runs as deep as its qubits allow (for a
+    // nearest-neighbour chain, a staircase over several layers).  A circuit
+    // that fits one tile keeps its original order.
+    std::set<int> ready;
+    for (int64_t g = 0; g < n_ops; ++g)
+        if (indeg[g] == 0) ready.insert((int)g);
+    const uint64_t nmask = n >= 64 ? ~0ull : ((1ull << n) - 1);
+    int64_t done = 0;
+    while (done < n_ops) {
+        qmask = lowQ & nmask;
+        bool dense_in = false;
+        for (auto it = ready.begin(); it != ready.end();) {
+            const int g = *it;
+            bool ok = isdiag[g] != 0;
+            if (!ok) {
+                const uint64_t need = qmask | ndq[g];
+                if (__builtin_popcountll(need) <= m) {
+                    qmask = need;
+                    ok = true;
+                } else if (!dense_in) { // the gate alone: padding fills low qubits
+                    qmask = ndq[g];
+                    ok = true;
+                }
+                dense_in |= ok;
+            }
+            if (!ok) {
+                ++it;
+                continue;
+            }
+            items.push_back({&ops[g], isdiag[g] != 0});
+            for (int e = eoff[g]; e < eoff[g + 1]; ++e)
+                if (--indeg[esucc[e]] == 0) ready.insert(esucc[e]);
+            it = ready.erase(it);
+            ++done;
+        }
+        close();
+    }
 }
 
 static int default_tile_qubits(int dt)
@@ -407,5 +477,38 @@ extern "C" qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64
     for (auto& p : passes) c += (int64_t)p.ops.size();
     *n_passes = (int64_t)passes.size();
     *n_ops_out = c;
+    return QS_OK;
+}
+
+extern "C" qs_status qs_plan_order(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                                  int64_t n_mats, const qs_run_opts* opts, int64_t* order, int32_t* pass_of,
+                                  uint64_t* tile_mask)
+{
+    using namespace qs;
+    if (n_ops > 0 && (!order || !pass_of)) return set_err(QS_ERR_ARG, "null output");
+    if (n < 1 || n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "n=%d outside [1, %d]", n, QS_MAX_QUBITS);
+    if (dt != QS_C64 && dt != QS_C128) return set_err(QS_ERR_ARG, "unknown dtype %d", (int)dt);
+    qs_status st = validate_circuit(n, ops, n_ops, mats, n_mats);
+    if (st != QS_OK) return st;
+    qs_run_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    PlanOpts po;
+    if ((st = plan_opts(dt, ops, n_ops, o, po)) != QS_OK) return st;
+    po.fuse_k = 0; // the order of the circuit's own gates
+    std::vector<PlanPass> passes;
+    std::vector<double> pool;
+    if (n_ops > 0) plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+    int64_t c = 0;
+    for (size_t p = 0; p < passes.size(); ++p) {
+        uint64_t qm = 0;
+        for (int q : passes[p].Q) qm |= 1ull << q;
+        if (tile_mask) tile_mask[p] = qm;
+        for (int64_t g : passes[p].src) {
+            order[c] = g;
+            pass_of[c] = (int32_t)p;
+            ++c;
+        }
+    }
     return QS_OK;
 }

@@ -45,6 +45,7 @@ struct PlanPass {
     int L = 0;                 // lowest L qubits are in the tile (contiguous runs)
     std::vector<int> Q;        // sorted tile qubits (size m)
     std::vector<TileOp> ops;
+    std::vector<int64_t> src;  // circuit index of each absorbed gate, in execution order
     uint64_t gates = 0;        // circuit gates absorbed
     uint64_t updates = 0;      // amplitude updates credited (sum over gates)
 };

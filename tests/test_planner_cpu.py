@@ -1,0 +1,104 @@
+"""The pass planner's gate order, checked on the CPU (no GPU needed).
+
+The planner may reorder gates that commute, so that one tile pass absorbs
+more of them.  Here the planned order is checked to be a permutation that
+keeps every pass's dense targets inside its tile, and the FP64 oracle applied
+in the planned order must give the state of the circuit order (gates that do
+not commute keep their order, so the two agree to rounding).  A swap of two
+gates that do not commute is shown to change the result, so the comparison
+can fail."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import paper_2506_09198_amd as qs
+
+    return qs
+
+
+def _random_mixed(n, count, seed):
+    """Dense and diagonal gates with and without controls (control values 0 or 1)."""
+    rng = np.random.default_rng(seed)
+    c = W.Circuit(n, f"mixed_n{n}_s{seed}")
+    for _ in range(count):
+        kind = int(rng.integers(6))
+        k = {0: 1, 1: 2, 2: 1, 3: 2, 4: 3, 5: 1}[kind]
+        qs_ = [int(x) for x in rng.permutation(n)[: k + int(rng.integers(0, 3))]]
+        tg, ctl = qs_[:k], qs_[k:]
+        cv = sum(int(b) << q for b, q in zip(rng.integers(0, 2, size=len(ctl)), ctl))
+        if kind in (0, 5):
+            u = W.u3(*rng.uniform(0, 2 * np.pi, 3))
+        elif kind in (1, 4):
+            u = W.haar_unitary(1 << k, rng)
+        else:
+            u = np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 1 << k)))
+        c.add(tg, u, ctl, cv)
+    return c
+
+
+def _circuits():
+    return [W.random_u3_cnot(9, 150, seed=3), W.rqc_chain(10, 8, 4), W.qft(9, 300), W.grover(8, 77),
+            _random_mixed(9, 160, 5), _random_mixed(10, 200, 6)]
+
+
+@pytest.mark.parametrize("tq,low", [(4, 2), (5, 3), (6, 0)])
+@pytest.mark.parametrize("ci", range(6))
+def test_planned_order_matches_oracle(qs, monkeypatch, ci, tq, low):
+    monkeypatch.setenv("QS_TILE_LOW", str(low))
+    c = _circuits()[ci]
+    ops, mats = c.arrays()
+    order, pass_of, masks = qs.qs_plan_order(c.n, qs.QS_C128, ops, mats, tile_qubits=tq)
+    assert sorted(order.tolist()) == list(range(len(ops)))
+    assert np.all(np.diff(pass_of) >= 0)
+    assert len(masks) == qs.qs_plan_circuit(c.n, qs.QS_C128, ops, mats, tile_qubits=tq)[0]
+    for g, p in zip(order, pass_of):
+        o = ops[g]
+        dense = not np.allclose(np.diag(np.diag(c.gates[g][1])), c.gates[g][1], atol=0, rtol=0)
+        if dense:
+            tm = sum(1 << int(t) for t in o["t"][: o["nt"]])
+            assert tm & ~int(masks[p]) == 0, (g, p)
+        assert bin(int(masks[p])).count("1") <= max(tq, int(o["nt"]))
+    ref = oracle.run_circuit(c)
+    got = oracle.run(c.n, ops[order], mats, oracle.basis(c.n, c.init_basis))
+    assert float(np.max(np.abs(got - ref))) <= 1e-12
+
+
+def test_reordering_pays_for_chain_circuits(qs):
+    r = W.rqc_chain(32, 20, 5)
+    ops, mats = r.arrays()
+    order, pass_of, _ = qs.qs_plan_order(32, qs.QS_C128, ops, mats, tile_qubits=11)
+    assert pass_of[-1] + 1 <= 45  # in circuit order it takes 90
+    assert not np.array_equal(order, np.arange(len(ops)))
+
+
+def test_single_tile_keeps_circuit_order(qs):
+    c = _random_mixed(8, 120, 9)
+    ops, mats = c.arrays()
+    order, pass_of, _ = qs.qs_plan_order(8, qs.QS_C128, ops, mats, tile_qubits=8)
+    assert np.array_equal(order, np.arange(len(ops))) and pass_of.max() == 0
+
+
+def test_noncommuting_swap_is_detected():
+    """The oracle comparison above is sharp: exchanging two adjacent
+    uncontrolled dense gates that share a target changes the state far beyond
+    rounding.  (Controlled gates can commute by their control values alone.)"""
+    c = _random_mixed(6, 40, 11)
+    ops, mats = c.arrays()
+    ref = oracle.run_circuit(c)
+    for i in range(len(ops) - 1):
+        a = set(ops[i]["t"][: ops[i]["nt"]].tolist())
+        b = set(ops[i + 1]["t"][: ops[i + 1]["nt"]].tolist())
+        da = np.allclose(np.diag(np.diag(c.gates[i][1])), c.gates[i][1], atol=0, rtol=0)
+        db = np.allclose(np.diag(np.diag(c.gates[i + 1][1])), c.gates[i + 1][1], atol=0, rtol=0)
+        if a & b and not da and not db and ops[i]["cmask"] == 0 and ops[i + 1]["cmask"] == 0:
+            perm = np.arange(len(ops))
+            perm[i], perm[i + 1] = i + 1, i
+            got = oracle.run(c.n, ops[perm], mats, oracle.basis(c.n, c.init_basis))
+            assert float(np.max(np.abs(got - ref))) > 1e-6
+            return
+    pytest.fail("no adjacent non-commuting pair in the sample circuit")
