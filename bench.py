@@ -265,7 +265,8 @@ def run_circuits(a, qs, torch, W):
             "qft": W.qft(n, int(np.random.default_rng(6).integers(1 << n)))}
     arrs = {k: c.arrays() for k, c in work.items()}
     upd = {k: _updates(n, arrs[k][0]) for k in work}
-    variants = [("c64_fused5", qs.QS_C64, 0, 5, a.steps, a.warmup), ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
+    variants = [("c64_fused5", qs.QS_C64, 0, 5, a.steps, a.warmup), ("c64_tiles", qs.QS_C64, 0, 0, 1, 1),
+                ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
     if not a.no_baselines:
         variants.append(("c128_pergate", qs.QS_C128, 1, 0, 1, 0))
     res, traces, states = {}, {}, {}

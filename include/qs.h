@@ -163,8 +163,8 @@ qs_status qs_run_circuit(qs_state s, const qs_op* ops, int64_t n_ops,
 /* Plan a circuit for an n-qubit state of type dt without executing it (host
  * only; needs no GPU).  *n_passes receives the number of LDS tile passes
  * (state read+write sweeps) qs_run_circuit would launch in mode 0, and
- * *n_ops_out the total operations inside them.  Same validation as
- * qs_run_circuit. */
+ * *n_ops_out the total operations inside them (a fused block counts once).
+ * Same validation as qs_run_circuit. */
 qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
                           int64_t n_mats, const qs_run_opts* opts, int64_t* n_passes, int64_t* n_ops_out);
 
@@ -179,6 +179,23 @@ qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, c
 qs_status qs_plan_order(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
                         int64_t n_mats, const qs_run_opts* opts, int64_t* order, int32_t* pass_of,
                         uint64_t* tile_mask);
+
+/* The tile passes qs_run_circuit (mode 0) would launch, for inspection and
+ * for checking the planner on a host (host only; needs no GPU).  Call once
+ * with pass_desc, ops_out and pool_out NULL to get *n_passes, *n_tile_ops
+ * and *n_pool; then again with buffers of at least those sizes (the three
+ * counts in, the actual counts out).  pass_desc: 36 int32 per pass: tile
+ * qubits m, forced low qubits L, first op, op count, then the 32 tile qubit
+ * positions ascending (-1 past m).  ops_out: *n_tile_ops records of
+ * QS_TILE_OP_BYTES bytes in the library's internal op layout (kind, k,
+ * p[6] as int32; lcm, lcv, gcm, gcv, moff as uint64; lp[6], dclass, dbit as
+ * int8; dj, rsv as int32), which may change between versions.  pool_out:
+ * the FP64 matrix pool the ops' moff index.  Same validation as
+ * qs_run_circuit. */
+#define QS_TILE_OP_BYTES 88
+qs_status qs_plan_export(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                         int64_t n_mats, const qs_run_opts* opts, int32_t* pass_desc, int64_t* n_passes,
+                         void* ops_out, int64_t* n_tile_ops, double* pool_out, int64_t* n_pool);
 
 /* ------------------------------------------------------------------ reductions */
 

@@ -108,6 +108,9 @@ def _load():
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
         "qs_plan_order": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(u64)], i32),
+        "qs_plan_export": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
+                            ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64), vp, ctypes.POINTER(ctypes.c_int64),
+                            dp, ctypes.POINTER(ctypes.c_int64)], i32),
         "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
         "qs_norm": ([vp, dp], i32),
         "qs_sync": ([vp], i32),
@@ -290,6 +293,33 @@ def qs_plan_order(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_qu
                              masks.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))))
     npass = int(pass_of[:k].max()) + 1 if k else 0
     return order[:k], pass_of[:k], masks[:npass]
+
+
+TILE_OP_DTYPE = np.dtype([("kind", "<i4"), ("k", "<i4"), ("p", "<i4", (6,)), ("lcm", "<u8"), ("lcv", "<u8"),
+                          ("gcm", "<u8"), ("gcv", "<u8"), ("moff", "<u8"), ("lp", "i1", (6,)), ("dclass", "i1"),
+                          ("dbit", "i1"), ("dj", "<i4"), ("rsv", "<i4")])
+assert TILE_OP_DTYPE.itemsize == 88
+
+
+def qs_plan_export(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_qubits: int = 0, fuse_k: int = 0):
+    """Host-only: (passes, tile_ops, pool) as planned for mode 0.  passes is a
+    list of dicts {m, L, op0, nops, Q}."""
+    ops = np.ascontiguousarray(ops)
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    o = _RunOpts(0, fuse_k, tile_qubits)
+    np_, nt, npool = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    args = (n, dtype, ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
+            mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o))
+    _check(lib.qs_plan_export(*args, None, ctypes.byref(np_), None, ctypes.byref(nt), None, ctypes.byref(npool)))
+    desc = np.zeros((max(np_.value, 1), 36), dtype=np.int32)
+    tops = np.zeros(max(nt.value, 1), dtype=TILE_OP_DTYPE)
+    pool = np.zeros(max(npool.value, 1), dtype=np.float64)
+    _check(lib.qs_plan_export(*args, desc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(np_),
+                              ctypes.c_void_p(tops.ctypes.data), ctypes.byref(nt),
+                              pool.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(npool)))
+    passes = [{"m": int(d[0]), "L": int(d[1]), "op0": int(d[2]), "nops": int(d[3]),
+               "Q": [int(q) for q in d[4:4 + d[0]]]} for d in desc[:np_.value]]
+    return passes, tops[:nt.value], pool[:npool.value]
 
 
 def qs_probabilities(s: int, qubits) -> np.ndarray:

@@ -30,13 +30,18 @@ def hipcc() -> str:
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{ROOT}/include", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
+# The tile kernels dispatch on a runtime register bit into copies of the same
+# unrolled code, each with compile-time register indices.  LLVM's CFG
+# sinking/hoisting would merge those copies into one with a runtime index,
+# which moves the register array to scratch memory.
+EXTRA = {"tile.hip": ["-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-simplifycfg-hoist-common=false"]}
 
 
 def _compile(src: str) -> str:
     base = os.path.splitext(os.path.basename(src))[0]
     obj = os.path.join(BUILD, base + ".o")
     if src.endswith(".hip"):
-        cmd = [hipcc(), *COMMON, *DEVICE, "-x", "hip", "-c", src, "-o", obj]
+        cmd = [hipcc(), *COMMON, *DEVICE, *EXTRA.get(os.path.basename(src), []), "-x", "hip", "-c", src, "-o", obj]
     else:
         cmd = [hipcc(), *COMMON, "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", "-x", "c++", "-c", src,
                "-o", obj]

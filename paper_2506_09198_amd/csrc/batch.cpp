@@ -324,8 +324,8 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         return QS_OK;
     };
     const int NS = (int)b->st.size();
-    bool any_mfma = false;
-    for (const TileOp& t : bops) any_mfma |= t.kind == TK_MFMA;
+    bool any_full = false; // any pass needs the full tile kernel
+    for (const BatchPass& d : bpass) any_full |= ops_need_full(bops.data() + d.op0, (size_t)d.nops, d.m);
     if (b->mode == 0) {
         // whole circuits on stream 0, persistent ones on stream 1 (if any), the
         // rest round-robin over the remaining streams
@@ -335,14 +335,14 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         for (int i = 0; i < count; ++i) b->stats.class_circuits[cls[i]] += 1;
         for (auto& g : whole_groups) {
             st = launched(launch_batch_whole(b->dt, g.first, b->arena, dcirc, dlist + g.second.first,
-                                             g.second.second, dpass, dops, dmats, any_mfma, s0),
+                                             g.second.second, dpass, dops, dmats, any_full, s0),
                           "batch whole launch");
             if (st != QS_OK) break;
         }
         if (!whole_groups.empty()) mark(0, s0);
         if (st == QS_OK && persist_count > 0) {
             st = launched(launch_batch_persist(b->dt, persist_m, b->arena, dcirc, dlist + persist_l0, persist_count,
-                                               dpass, dops, dmats, any_mfma, b->st[NS > 1 ? 1 : 0]),
+                                               dpass, dops, dmats, any_full, b->st[NS > 1 ? 1 : 0]),
                           "batch persistent launch");
             mark(1, b->st[NS > 1 ? 1 : 0]);
         }
@@ -350,7 +350,7 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         for (size_t r = 0; r < rounds.size() && st == QS_OK; ++r)
             st = launched(launch_batch_round(b->dt, stream_m, b->arena, dcirc, dpass, dops, dmats,
                                              dents + rounds[r].first, rounds[r].second.first,
-                                             rounds[r].second.second, any_mfma, sr),
+                                             rounds[r].second.second, any_full, sr),
                           "batch round launch");
         if (!rounds.empty()) mark(2, sr);
     } else {

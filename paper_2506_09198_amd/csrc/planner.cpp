@@ -101,13 +101,17 @@ static void embed_op(const TileOp& t, const std::vector<double>& pool, const int
 static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_dense)
 {
     std::vector<TileOp> out;
+    std::vector<int64_t> osrc;
     std::vector<size_t> blk;
     uint32_t bbits = 0;
     int bdense = 0;
     auto emit = [&]() {
         if (blk.empty()) return;
         if (bdense < min_dense) {
-            for (size_t i : blk) out.push_back(P.ops[i]);
+            for (size_t i : blk) {
+                out.push_back(P.ops[i]);
+                osrc.push_back(P.src[i]);
+            }
         } else {
             uint32_t bits = bbits;
             for (int q = 0; __builtin_popcount(bits) < K && q < P.m; ++q) bits |= 1u << q;
@@ -145,6 +149,7 @@ static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_den
             std::memcpy(pool.data() + off, fr.data(), fr.size() * sizeof(double));
             t.moff = off;
             out.push_back(t);
+            osrc.push_back(-1);
         }
         blk.clear();
         bbits = 0;
@@ -166,10 +171,368 @@ static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_den
             bdense = P.ops[i].kind != TK_DIAG;
         } else {
             out.push_back(P.ops[i]);
+            osrc.push_back(P.src[i]);
         }
     }
     emit();
     P.ops.swap(out);
+    P.src.swap(osrc);
+}
+
+// ------------------------------------------------------- register segments
+//
+// Inside a pass, ops are grouped into segments whose dense targets lie on at
+// most r tile positions; the kernel then moves each thread's 2^r amplitudes
+// between LDS and registers once per segment instead of once per op.  Ops
+// are reordered within the pass by the commutation rule the pass scheduler
+// uses (on tile-local positions); a diagonal op joins any segment.  k >= 3
+// dense ops and fused blocks run on their own, in LDS.
+
+// A diagonal op inside a segment is rewritten for the register kernel:
+// local controls become extra targets (factor 1 where a control fails), and
+// the targets are ordered register positions first (by register rank), then
+// thread positions, then positions outside the tile.  dclass then holds the
+// number of register targets kr (SD_GATHER when the fast form does not
+// apply) and dbit the number of thread targets kt; the kernel reads the
+// same from 32-bit fields: dj = kr | kt << 4 (SD_GATHER << 8 for the
+// gather form), rsv = register ranks (target 0 | target 1 << 8), and p[j] =
+// the tile position of a local target, the global position of one outside.
+
+// Opcode of a segment member (rsv >> 16): one switch in the kernel picks the
+// code with the member's register bits fixed at compile time.
+static int seg_pair_index(int a, int b) // a < b < 4
+{
+    static const int idx[4][4] = {{-1, 0, 1, 3}, {-1, -1, 2, 4}, {-1, -1, -1, 5}, {-1, -1, -1, -1}};
+    return idx[a][b];
+}
+
+// Diagonal member: SO_DG (gather), SO_D0 (no register target: one factor per
+// thread), SO_D1 + rank, SO_D2 + pair (every register combination), or, when
+// a single register combination ri has a factor other than 1 for every
+// thread and outside bit, SO_D1X + 2 rank + ri / SO_D2X + 4 pair + ri (only
+// those registers are multiplied).
+static int seg_diag_opcode(const TileOp& t, const std::vector<double>& pool)
+{
+    if ((t.dj >> 8) == SD_GATHER) return SO_DG;
+    const int kr = t.dj & 15;
+    if (kr == 0) return SO_D0;
+    const int nri = 1 << kr, D = 1 << t.k;
+    const double* T = pool.data() + t.moff;
+    uint32_t notone = 0;
+    for (int i = 0; i < D; ++i)
+        if (T[2 * i] != 1.0 || T[2 * i + 1] != 0.0) notone |= 1u << (i & (nri - 1));
+    const int r0 = t.rsv & 255, r1 = (t.rsv >> 8) & 255;
+    if (__builtin_popcount(notone) == 1) {
+        const int ri = __builtin_ctz(notone);
+        return kr == 1 ? SO_D1X + 2 * r0 + ri : SO_D2X + 4 * seg_pair_index(r0, r1) + ri;
+    }
+    return kr == 1 ? SO_D1 + r0 : SO_D2 + seg_pair_index(r0, r1);
+}
+
+static void seg_diag_form(TileOp& t, std::vector<double>& pool, uint32_t R, const int* rank)
+{
+    int reg[6], thr[6], glo[6], nr = 0, nt = 0, ng = 0;
+    for (int j = 0; j < t.k; ++j) {
+        const int q = t.lp[j];
+        if (q < 0) glo[ng++] = j;
+        else if ((R >> q) & 1) reg[nr++] = j;
+        else thr[nt++] = j;
+    }
+    int creg[32], cthr[32], ncr = 0, nct = 0;
+    for (uint32_t b = (uint32_t)t.lcm; b; b &= b - 1) {
+        const int q = __builtin_ctz(b);
+        if ((R >> q) & 1) creg[ncr++] = q;
+        else cthr[nct++] = q;
+    }
+    const int kn = t.k + ncr + nct;
+    if (kn > 6 || nr + ncr > 2 || nt + nct > 2) {
+        t.dclass = SD_GATHER;
+        t.dj = SD_GATHER << 8;
+        return;
+    }
+    // new target list: (kind, old index or control position)
+    struct Tg {
+        int local; // tile position or -1
+        int gpos;  // global position
+        int oldj;  // index bit in the old table, or -1 for a control
+        int cval;  // control value (controls only)
+        int rk;    // register rank (register targets only)
+    };
+    Tg nl[6];
+    int c = 0;
+    auto add_reg_target = [&](int local, int gpos, int oldj, int cval) {
+        nl[c++] = {local, gpos, oldj, cval, rank[local]};
+    };
+    for (int i = 0; i < nr; ++i) add_reg_target(t.lp[reg[i]], t.p[reg[i]], reg[i], 0);
+    for (int i = 0; i < ncr; ++i) add_reg_target(creg[i], -1, -1, (int)((t.lcv >> creg[i]) & 1));
+    if (c == 2 && nl[0].rk > nl[1].rk) std::swap(nl[0], nl[1]);
+    for (int i = 0; i < nt; ++i) nl[c++] = {t.lp[thr[i]], t.p[thr[i]], thr[i], 0, -1};
+    for (int i = 0; i < nct; ++i) nl[c++] = {cthr[i], -1, -1, (int)((t.lcv >> cthr[i]) & 1), -1};
+    for (int i = 0; i < ng; ++i) nl[c++] = {-1, t.p[glo[i]], glo[i], 0, -1};
+    const int D = 1 << kn;
+    const size_t off = pool.size();
+    pool.resize(off + 2 * (size_t)D);
+    const double* U = pool.data() + t.moff;
+    double* W = pool.data() + off;
+    for (int ni = 0; ni < D; ++ni) {
+        int oi = 0;
+        bool on = true;
+        for (int j = 0; j < kn; ++j) {
+            const int b = (ni >> j) & 1;
+            if (nl[j].oldj >= 0) oi |= b << nl[j].oldj;
+            else if (b != nl[j].cval) on = false;
+        }
+        W[2 * ni] = on ? U[2 * oi] : 1.0;
+        W[2 * ni + 1] = on ? U[2 * oi + 1] : 0.0;
+    }
+    t.moff = off;
+    t.k = kn;
+    for (int j = 0; j < kn; ++j) {
+        t.lp[j] = (int8_t)nl[j].local;
+        t.p[j] = nl[j].local >= 0 ? nl[j].local : nl[j].gpos; // tile position, or global outside the tile
+    }
+    t.lcm = t.lcv = 0;
+    t.dclass = (int8_t)(nr + ncr);
+    t.dbit = (int8_t)(nt + nct);
+    t.dj = (nr + ncr) | ((nt + nct) << 4);
+    t.rsv = (nr + ncr > 0 ? nl[0].rk : 0) | (nr + ncr > 1 ? nl[1].rk << 8 : 0);
+}
+
+static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
+{
+    const size_t N = P.ops.size();
+    std::vector<uint32_t> nd(N), dq(N);
+    std::vector<uint8_t> cap(N); // 0: dense in registers, 1: diagonal, 2: on its own
+    for (size_t i = 0; i < N; ++i) {
+        const TileOp& t = P.ops[i];
+        uint32_t tm = 0;
+        if (t.kind == TK_DIAG) {
+            for (int j = 0; j < t.k; ++j)
+                if (t.lp[j] >= 0) tm |= 1u << t.lp[j];
+            nd[i] = 0;
+            dq[i] = tm | (uint32_t)t.lcm;
+            cap[i] = 1;
+        } else {
+            for (int j = 0; j < t.k; ++j) tm |= 1u << t.p[j];
+            nd[i] = tm;
+            dq[i] = (uint32_t)t.lcm;
+            cap[i] = (t.kind == TK_DENSE1 || t.kind == TK_DENSE2) && t.k <= r ? 0 : 2;
+        }
+    }
+    std::vector<std::pair<int, int>> edges;
+    {
+        int last_nd[32];
+        std::vector<int> since[32];
+        for (int q = 0; q < 32; ++q) last_nd[q] = -1;
+        for (size_t g = 0; g < N; ++g) {
+            for (uint32_t b = nd[g] | dq[g]; b; b &= b - 1) {
+                const int q = __builtin_ctz(b);
+                if (last_nd[q] >= 0) edges.push_back({last_nd[q], (int)g});
+                if ((nd[g] >> q) & 1)
+                    for (int h : since[q]) edges.push_back({h, (int)g});
+            }
+            for (uint32_t b = nd[g]; b; b &= b - 1) {
+                const int q = __builtin_ctz(b);
+                last_nd[q] = (int)g;
+                since[q].clear();
+            }
+            for (uint32_t b = dq[g]; b; b &= b - 1) since[__builtin_ctz(b)].push_back((int)g);
+        }
+    }
+    std::vector<int> eoff(N + 1, 0), esucc(edges.size()), indeg(N, 0);
+    for (auto& e : edges) eoff[e.first + 1] += 1;
+    for (size_t g = 0; g < N; ++g) eoff[g + 1] += eoff[g];
+    {
+        std::vector<int> fill(eoff.begin(), eoff.end() - 1);
+        for (auto& e : edges) {
+            esucc[fill[e.first]++] = e.second;
+            indeg[e.second] += 1;
+        }
+    }
+    std::set<int> ready;
+    for (size_t g = 0; g < N; ++g)
+        if (indeg[g] == 0) ready.insert((int)g);
+    std::vector<TileOp> out;
+    std::vector<int64_t> osrc, ord;
+    auto unlock = [&](int g) {
+        for (int e = eoff[g]; e < eoff[g + 1]; ++e)
+            if (--indeg[esucc[e]] == 0) ready.insert(esucc[e]);
+    };
+    size_t done = 0;
+    std::vector<int> mem;
+    while (done < N) {
+        uint32_t R = 0;
+        mem.clear();
+        for (auto it = ready.begin(); it != ready.end();) {
+            const int g = *it;
+            bool ok = cap[g] == 1;
+            if (cap[g] == 0 && __builtin_popcount(R | nd[g]) <= r) {
+                R |= nd[g];
+                ok = true;
+            }
+            if (!ok) {
+                ++it;
+                continue;
+            }
+            mem.push_back(g);
+            unlock(g);
+            it = ready.erase(it);
+            ++done;
+        }
+        if (mem.empty()) { // the first ready op runs on its own
+            const int g = *ready.begin();
+            ready.erase(ready.begin());
+            unlock(g);
+            ++done;
+            out.push_back(P.ops[g]);
+            osrc.push_back(P.src[g]);
+            ord.push_back(P.src[g]);
+            continue;
+        }
+        {
+            // pad with the positions the segment's diagonal ops use most (a
+            // diagonal op whose bits are register bits touches only the
+            // registers it changes), then with high positions
+            int freq[32] = {0};
+            for (int g : mem)
+                if (cap[g] == 1)
+                    for (uint32_t b = dq[g]; b; b &= b - 1) freq[__builtin_ctz(b)] += 1;
+            while (__builtin_popcount(R) < r) {
+                int best = -1;
+                for (int q = P.m - 1; q >= 0; --q)
+                    if (!((R >> q) & 1) && (best < 0 || freq[q] > freq[best])) best = q;
+                R |= 1u << best;
+            }
+        }
+        TileOp h;
+        std::memset(&h, 0, sizeof h);
+        h.kind = TK_SEG;
+        h.k = r;
+        int rank[32], nr = 0;
+        for (int q = 0; q < 32; ++q)
+            if ((R >> q) & 1) {
+                rank[q] = nr;
+                h.p[nr++] = q;
+            }
+        const size_t hpos = out.size();
+        out.push_back(h);
+        osrc.push_back(-1);
+
+        auto emit_member = [&](int g) {
+            TileOp t = P.ops[g];
+            ord.push_back(P.src[g]);
+            if (t.kind == TK_DIAG) {
+                seg_diag_form(t, pool, R, rank);
+                t.rsv |= seg_diag_opcode(t, pool) << 16;
+                out.push_back(t);
+                osrc.push_back(P.src[g]);
+                return;
+            }
+            const uint32_t lc = (uint32_t)t.lcm;
+            t.dj = ((lc & R) ? 1 : 0) | ((lc & ~R) ? 2 : 0); // controls at register / thread positions
+            if (t.kind == TK_DENSE1) {
+                t.lp[0] = (int8_t)rank[t.p[0]];
+                t.rsv = rank[t.p[0]];
+            } else if (t.kind == TK_DENSE2) {
+                int a = rank[t.p[0]], b = rank[t.p[1]];
+                if (a > b) { // make target 0 the lower register bit: swap the matrix index bits
+                    const size_t off = pool.size();
+                    pool.resize(off + 32);
+                    const double* U = pool.data() + t.moff;
+                    double* W = pool.data() + off;
+                    auto sw = [](int x) { return ((x & 1) << 1) | ((x >> 1) & 1); };
+                    for (int rr = 0; rr < 4; ++rr)
+                        for (int cc = 0; cc < 4; ++cc) {
+                            W[2 * (rr * 4 + cc)] = U[2 * (sw(rr) * 4 + sw(cc))];
+                            W[2 * (rr * 4 + cc) + 1] = U[2 * (sw(rr) * 4 + sw(cc)) + 1];
+                        }
+                    t.moff = off;
+                    std::swap(t.p[0], t.p[1]);
+                    std::swap(a, b);
+                }
+                t.lp[0] = (int8_t)a;
+                t.lp[1] = (int8_t)b;
+                t.rsv = a | (b << 8);
+            }
+            const bool ctl = t.dj != 0;
+            int opc;
+            if (t.kind == TK_DENSE1) opc = SO_1Q + (t.rsv & 255) + (ctl ? 4 : 0);
+            else opc = SO_2Q + seg_pair_index(t.rsv & 255, (t.rsv >> 8) & 255) + (ctl ? 6 : 0);
+            t.rsv |= opc << 16;
+            out.push_back(t);
+            osrc.push_back(P.src[g]);
+        };
+
+        // Runs of register-only ops (dense ops and diagonal ops whose qubits
+        // and controls are all register positions, no outside control) are
+        // multiplied into one 2^r x 2^r block when that is cheaper than the
+        // ops one by one.  An op that cannot join moves after later run ops
+        // it commutes with; otherwise it closes the run.
+        auto absorbable = [&](int g) {
+            const TileOp& t = P.ops[g];
+            if (t.gcm != 0 || ((uint32_t)t.lcm & ~R) != 0) return false;
+            if (t.kind == TK_DENSE1 || t.kind == TK_DENSE2) return true;
+            if (t.kind != TK_DIAG) return false;
+            for (int j = 0; j < t.k; ++j)
+                if (t.lp[j] < 0 || !((R >> t.lp[j]) & 1)) return false;
+            return true;
+        };
+        auto commute = [&](int x, int y) {
+            return (nd[x] & (nd[y] | dq[y])) == 0 && (nd[y] & (nd[x] | dq[x])) == 0;
+        };
+        auto op_cost = [&](int g) {
+            const TileOp& t = P.ops[g];
+            return t.kind == TK_DENSE1 ? 20.0 : (t.kind == TK_DENSE2 ? 40.0 : 8.0);
+        };
+        const double block_cost = 4.0 * (1 << r) + 10.0;
+        std::vector<int> run, pend;
+        auto flush = [&]() {
+            double c = 0;
+            for (int g : run) c += op_cost(g);
+            if (run.size() >= 2 && c > block_cost) {
+                const int D = 1 << r;
+                std::vector<cd> G((size_t)D * D, cd(0, 0));
+                for (int i = 0; i < D; ++i) G[(size_t)i * D + i] = 1.0;
+                for (int g : run) {
+                    embed_op(P.ops[g], pool, h.p, r, G);
+                    ord.push_back(P.src[g]);
+                }
+                TileOp t;
+                std::memset(&t, 0, sizeof t);
+                t.kind = TK_DENSEK;
+                t.k = r;
+                for (int j = 0; j < r; ++j) t.p[j] = h.p[j];
+                t.moff = pool.size();
+                for (const cd& z : G) {
+                    pool.push_back(z.real());
+                    pool.push_back(z.imag());
+                }
+                t.rsv = SO_BLOCK << 16;
+                out.push_back(t);
+                osrc.push_back(-1);
+            } else {
+                for (int g : run) emit_member(g);
+            }
+            for (int g : pend) emit_member(g);
+            run.clear();
+            pend.clear();
+        };
+        for (int g : mem) {
+            if (!absorbable(g)) {
+                pend.push_back(g);
+                continue;
+            }
+            bool ok = true;
+            for (int q : pend) ok = ok && commute(q, g);
+            if (!ok) flush();
+            run.push_back(g);
+        }
+        flush();
+        out[hpos].dj = (int32_t)(out.size() - hpos - 1);
+    }
+    P.ops.swap(out);
+    P.src.swap(osrc);
+    P.order.swap(ord);
 }
 
 static bool is_diagonal(const double* U, int nt)
@@ -267,11 +630,14 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
             }
             P.ops.push_back(t);
             P.src.push_back((int64_t)(it.op - ops));
+            P.order.push_back((int64_t)(it.op - ops));
             P.gates += 1;
             P.updates += 1ull << (n - __builtin_popcountll(o.cmask));
         }
         if ((po.fuse_k == 4 || po.fuse_k == 5) && po.dt == QS_C64 && m >= po.fuse_k + 4)
             fuse_pass(P, pool, po.fuse_k, po.fuse_min);
+        const int r = po.segments ? seg_reg_qubits(po.dt, m) : 0;
+        if (r > 0) segment_pass(P, pool, r);
         passes.push_back(std::move(P));
         items.clear();
         qmask = 0;
@@ -370,7 +736,7 @@ static int default_tile_qubits(int dt)
 {
     const int e = env_int("QS_TILE_QUBITS", 0);
     if (e > 0) return e;
-    return dt == QS_C128 ? 11 : 12;
+    return 11; // measured best for both types on the random chain and QFT circuits
 }
 
 static int default_low_qubits(int dt)
@@ -396,6 +762,7 @@ qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int
     po.fuse_k = fuse_k > 0 ? fuse_k : env_int("QS_FUSE_K", 0);
     po.fuse_min = env_int("QS_FUSE_MIN", 3);
     po.dt = dt;
+    po.segments = env_int("QS_REG_SEGMENTS", 1) != 0;
     if (po.fuse_k != 0 && po.fuse_k != 4 && po.fuse_k != 5)
         return set_err(QS_ERR_ARG, "fuse_k=%d: fused blocks have 4 or 5 qubits", po.fuse_k);
     return QS_OK;
@@ -473,8 +840,9 @@ extern "C" qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64
     std::vector<PlanPass> passes;
     std::vector<double> pool;
     if (n_ops > 0) plan_circuit(n, ops, n_ops, mats, po, passes, pool);
-    int64_t c = 0;
-    for (auto& p : passes) c += (int64_t)p.ops.size();
+    int64_t c = 0; // segment headers are bookkeeping, not operations
+    for (auto& p : passes)
+        for (auto& t : p.ops) c += t.kind != TK_SEG;
     *n_passes = (int64_t)passes.size();
     *n_ops_out = c;
     return QS_OK;
@@ -504,11 +872,57 @@ extern "C" qs_status qs_plan_order(int n, qs_dtype dt, const qs_op* ops, int64_t
         uint64_t qm = 0;
         for (int q : passes[p].Q) qm |= 1ull << q;
         if (tile_mask) tile_mask[p] = qm;
-        for (int64_t g : passes[p].src) {
+        for (int64_t g : passes[p].order) {
+            if (g < 0) continue;
             order[c] = g;
             pass_of[c] = (int32_t)p;
             ++c;
         }
     }
+    return QS_OK;
+}
+
+extern "C" qs_status qs_plan_export(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                                   int64_t n_mats, const qs_run_opts* opts, int32_t* pass_desc,
+                                   int64_t* n_passes, void* ops_out, int64_t* n_tile_ops, double* pool_out,
+                                   int64_t* n_pool)
+{
+    using namespace qs;
+    if (!n_passes || !n_tile_ops || !n_pool) return set_err(QS_ERR_ARG, "null size output");
+    if (n < 1 || n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "n=%d outside [1, %d]", n, QS_MAX_QUBITS);
+    if (dt != QS_C64 && dt != QS_C128) return set_err(QS_ERR_ARG, "unknown dtype %d", (int)dt);
+    qs_status st = validate_circuit(n, ops, n_ops, mats, n_mats);
+    if (st != QS_OK) return st;
+    qs_run_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    PlanOpts po;
+    if ((st = plan_opts(dt, ops, n_ops, o, po)) != QS_OK) return st;
+    std::vector<PlanPass> passes;
+    std::vector<double> pool;
+    if (n_ops > 0) plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+    int64_t total = 0;
+    for (auto& p : passes) total += (int64_t)p.ops.size();
+    const bool fill = pass_desc && ops_out && pool_out;
+    if (fill && (*n_passes < (int64_t)passes.size() || *n_tile_ops < total || *n_pool < (int64_t)pool.size()))
+        return set_err(QS_ERR_ARG, "export buffers too small");
+    if (fill) {
+        int64_t op0 = 0;
+        for (size_t i = 0; i < passes.size(); ++i) {
+            int32_t* d = pass_desc + 36 * i;
+            const PlanPass& p = passes[i];
+            d[0] = p.m;
+            d[1] = p.L;
+            d[2] = (int32_t)op0;
+            d[3] = (int32_t)p.ops.size();
+            for (int j = 0; j < 32; ++j) d[4 + j] = j < (int)p.Q.size() ? p.Q[j] : -1;
+            std::memcpy((char*)ops_out + op0 * sizeof(TileOp), p.ops.data(), p.ops.size() * sizeof(TileOp));
+            op0 += (int64_t)p.ops.size();
+        }
+        if (!pool.empty()) std::memcpy(pool_out, pool.data(), pool.size() * sizeof(double));
+    }
+    *n_passes = (int64_t)passes.size();
+    *n_tile_ops = total;
+    *n_pool = (int64_t)pool.size();
     return QS_OK;
 }

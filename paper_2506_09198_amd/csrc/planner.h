@@ -17,7 +17,45 @@ namespace qs {
 //       controls gcm/gcv; it multiplies amplitude i by d[bits of i at p] and
 //       never needs its qubits inside the tile.
 //   kind TK_MFMA: dense k-qubit block applied with matrix cores.
-enum { TK_DENSE1 = 0, TK_DENSE2 = 1, TK_DENSEK = 2, TK_DIAG = 3, TK_MFMA = 4 };
+//   kind TK_SEG: header of a register segment: the next dj ops (TK_DENSE1,
+//       TK_DENSE2, TK_DIAG) act only on the k tile-local positions p[0..k)
+//       (ascending) as far as dense targets go, so each thread loads its 2^k
+//       amplitudes from LDS once, applies all of them in registers and
+//       stores them once.  Inside a segment the kernel reads 32-bit fields
+//       only: a dense op's rsv holds the register bits of its targets
+//       (target 0 | target 1 << 8, target 0 the lower) and dj its control
+//       kinds (1: a control at a register position, 2: at a thread
+//       position); diagonal members are described where the planner forms
+//       them.
+enum { TK_DENSE1 = 0, TK_DENSE2 = 1, TK_DENSEK = 2, TK_DIAG = 3, TK_MFMA = 4, TK_SEG = 5 };
+// A diagonal segment member the planner could not put in register form
+// (its dclass); the kernel gathers its factor per element.
+enum { SD_GATHER = 7 };
+// Segment member opcodes (rsv >> 16): dense 1q on register bit b (+4 with
+// controls), dense 2q on register pair p (+6 with controls), diagonal forms.
+// Register pairs (a < b < 4) are numbered 01, 02, 12, 03, 13, 23.
+enum {
+    SO_1Q = 0,    // 8 codes
+    SO_2Q = 8,    // 12 codes
+    SO_D0 = 20,   // 1
+    SO_D1 = 21,   // 4: by rank
+    SO_D2 = 25,   // 6: by pair
+    SO_D1X = 31,  // 8: 2 rank + ri
+    SO_D2X = 39,  // 24: 4 pair + ri
+    SO_BLOCK = 63, // a fused 2^r x 2^r block on all register bits (row-major complex)
+    SO_DG = 64,   // gather
+};
+static_assert(SO_D2X + 4 * 6 <= SO_BLOCK, "segment opcode ranges overlap");
+
+// Register qubits of a segment for tile size m (0: tiles below 2^10
+// elements run op by op in LDS).  Every one of a block's 256 threads holds
+// 2^r elements per loop step.  The tile kernels use the same formula.
+inline int seg_reg_qubits(int dt, int m)
+{
+    (void)dt;
+    if (m < 10) return 0;
+    return m - 8 < 4 ? m - 8 : 4;
+}
 
 struct TileOp {
     int32_t kind;
@@ -40,12 +78,29 @@ struct TileOp {
 static_assert(sizeof(TileOp) == 88, "TileOp layout");
 enum { DG_UNIFORM = 0, DG_LTARGET = 1, DG_LCONTROL = 2, DG_GENERAL = 3, DG_CT = 4 };
 
+// Whether a pass's op list needs the full tile kernel: any k >= 3 dense op or
+// fused block, or (tiles of >= 2^10 elements) any op outside a segment.  The
+// lean kernel holds only what the rest needs, which keeps its registers low.
+inline bool ops_need_full(const TileOp* ops, size_t n, int m)
+{
+    for (size_t i = 0; i < n; ++i) {
+        const int k = ops[i].kind;
+        if (k == TK_SEG) {
+            i += (size_t)ops[i].dj;
+            continue;
+        }
+        if (k == TK_DENSEK || k == TK_MFMA || m >= 10) return true;
+    }
+    return false;
+}
+
 struct PlanPass {
     int m = 0;                 // tile qubits
     int L = 0;                 // lowest L qubits are in the tile (contiguous runs)
     std::vector<int> Q;        // sorted tile qubits (size m)
     std::vector<TileOp> ops;
-    std::vector<int64_t> src;  // circuit index of each absorbed gate, in execution order
+    std::vector<int64_t> src;   // per op: circuit index of the gate (-1: segment header or fused block)
+    std::vector<int64_t> order; // circuit gates in execution order (fused blocks expanded)
     uint64_t gates = 0;        // circuit gates absorbed
     uint64_t updates = 0;      // amplitude updates credited (sum over gates)
 };
@@ -56,6 +111,7 @@ struct PlanOpts {
     int fuse_k = 0;   // 0: no dense fusion; 4 or 5: matrix-core blocks (complex64)
     int fuse_min = 3; // dense gates a block must absorb to be worth a fused block
     int dt = QS_C128;
+    bool segments = true; // group ops into register segments (tiles of >= 2^10 elements)
 };
 
 // Plan in FP64.  `mats_out` receives the pool the passes' moff index (FP64,
@@ -86,12 +142,12 @@ struct BatchCirc {
 // qubits runs whole in one block's LDS (initial basis state built in LDS; the
 // final state written once).
 hipError_t launch_batch_whole(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
-                              const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                              const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
                               hipStream_t st);
 // One launch for `count` circuits whose passes all use tile size M: one block
 // per circuit initialises its state and loops over its passes and tiles.
 hipError_t launch_batch_persist(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list,
-                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
                                 hipStream_t st);
 
 // One entry of a pass-major round: blocks [first_block, first_block + 2^(n-m))
@@ -106,7 +162,7 @@ struct RoundEntry {
 // One launch covering the same pass index of many circuits (all with tile size M).
 hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
                               const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
-                              uint32_t nblocks, bool mf, hipStream_t st);
+                              uint32_t nblocks, bool full, hipStream_t st);
 // Zero `bytes` bytes of the arena and set each listed circuit's basis amplitude.
 hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCirc* circs, const int32_t* list,
                              int count, hipStream_t st);
@@ -127,9 +183,9 @@ struct ServeEntry {
     int32_t n;
 };
 
-hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool mf,
+hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool full,
                               hipStream_t st);
-hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool mf, hipStream_t st);
+hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool full, hipStream_t st);
 
 qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats);
 qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int tile_qubits, PlanOpts& po);

@@ -118,7 +118,7 @@ struct qs_server_s {
     std::vector<uint64_t> active;
     std::deque<qs_result> completed;
     std::chrono::steady_clock::time_point t0;
-    bool any_mfma = false;
+    bool any_full = false;
     qs_server_stats stats;
 };
 
@@ -246,10 +246,8 @@ qs_status admit_one(qs_server s, Req& r)
         d.ip = make_insert_plan(qm);
         d.op0 = (int)to.size();
         d.nops = (int)p.ops.size();
-        for (auto& t : p.ops) {
-            to.push_back(t);
-            s->any_mfma |= t.kind == TK_MFMA;
-        }
+        for (auto& t : p.ops) to.push_back(t);
+        s->any_full |= ops_need_full(p.ops.data(), p.ops.size(), p.m); // sticky: the full kernel from then on
         bp.push_back(d);
     }
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
@@ -393,7 +391,7 @@ bool build_round(qs_server s)
             st = set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
             break;
         }
-        e = launch_serve_whole(s->dt, whole_n[order[i]], sl->dev + i, (int)(j - i), s->any_mfma, s->st);
+        e = launch_serve_whole(s->dt, whole_n[order[i]], sl->dev + i, (int)(j - i), s->any_full, s->st);
         s->stats.launches += 1;
         if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "whole launch: %s", hipGetErrorString(e));
         i = j;
@@ -402,7 +400,7 @@ bool build_round(qs_server s)
         if (inject_fault_now()) {
             st = set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
         } else {
-            e = launch_serve_round(s->dt, s->m, sl->dev + whole_e.size(), (int)round_e.size(), blocks, s->any_mfma,
+            e = launch_serve_round(s->dt, s->m, sl->dev + whole_e.size(), (int)round_e.size(), blocks, s->any_full,
                                    s->st);
             s->stats.launches += 1;
             if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "round launch: %s", hipGetErrorString(e));

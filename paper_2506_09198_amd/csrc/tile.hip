@@ -24,6 +24,24 @@ struct QList {
     int32_t q[QS_MAX_QUBITS];
 };
 
+// LDS placement of tile element e.  Each G-bit group of e above the lowest
+// is XORed into the lowest G bits (G = 4 for 16-byte, 5 for 8-byte
+// amplitudes: one 256-byte row of banks), so lanes whose elements lie a
+// power of two apart -- a register segment over low positions, a fused
+// block's column gather -- land in different banks.  A bijection on
+// [0, 2^M): the high bits are kept.
+template <int ES>
+__device__ __forceinline__ uint32_t swz(uint32_t e)
+{
+    constexpr int G = ES == 16 ? 4 : 5;
+    constexpr uint32_t MK = (1u << G) - 1;
+    uint32_t r = e;
+#pragma unroll
+    for (int s = G; s < 13; s += G) r ^= (e >> s) & MK;
+    return r;
+}
+#define QS_SW(e) swz<(int)sizeof(V)>(e)
+
 // Fused dense block on K = 4 or 5 tile-local qubits with FP64 matrix cores
 // (complex64 tiles).  The complex 2^K x 2^K matrix acts as its real embedding
 // [[Ur, -Ui], [Ui, Ur]] (interleaved rows/columns, 2^(K+1) square) on the
@@ -83,7 +101,7 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 if ((mm >> j) & 1) e |= 1u << pos[j];
-            const double bv = (double)tf[2 * e + (lk & 1)];
+            const double bv = (double)tf[2 * swz<8>(e) + (lk & 1)];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
                 acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb * KS + ks], bv, acc[rb], 0, 0, 0);
@@ -98,16 +116,356 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
 #pragma unroll
                 for (int j = 0; j < K; ++j)
                     if ((mm >> j) & 1) e |= 1u << pos[j];
-                tf[2 * e + (lk & 1)] = (float)acc[rb][v];
+                tf[2 * swz<8>(e) + (lk & 1)] = (float)acc[rb][v];
             }
         }
+    }
+}
+
+// ------------------------------------------------------------ segments
+//
+// A segment (TK_SEG header + dj member ops) acts on r register positions of
+// the tile.  Thread t holds, per loop step l, the 2^r elements whose other
+// bits spell t | l << 8 (deposited into the non-register positions in
+// ascending order): it loads them from LDS once, widened to FP64, applies
+// every member op with compile-time register indices, and rounds and stores
+// them once.  Every wave64 VALU instruction costs the same issue time here
+// (FP64 included), so the code keeps per-element work to the arithmetic
+// itself: a condition or factor index splits into a per-thread part
+// (non-register bits, evaluated once per op) and a per-register part (the
+// register bits, uniform across the wave, so it becomes a scalar branch).
+template <typename R, int M>
+struct Seg {
+    static constexpr int RMAX = 4;
+    static constexpr int RR = (M - 8 < RMAX) ? (M - 8) : RMAX; // register qubits (M >= 10)
+    static constexpr int NR = 1 << RR;
+    static constexpr int TB = M - RR;                           // thread + loop bits (>= 8)
+    static constexpr int LI = 1 << (TB - 8);                    // loop steps
+};
+
+// Dense 1q op on register bit B.  With CTL the op has controls: rcm/rcv are
+// control bits at register positions (uniform, tested per pair) and tok
+// says whether this thread's own bits pass the others (if not it applies the
+// identity).  Without CTL the loop has no branch at all.
+template <int NR, int B, bool CTL>
+__device__ __forceinline__ void seg_1q(double2 (&reg)[NR], const uint32_t (&roff)[NR], uint32_t rcm, uint32_t rcv,
+                                       bool tok, const double* __restrict__ u)
+{
+    double m[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const double id = (i == 0 || i == 6) ? 1.0 : 0.0;
+        m[i] = CTL ? (tok ? u[i] : id) : u[i];
+    }
+    constexpr int S = 1 << B;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j & S) continue;
+        if constexpr (CTL)
+            if ((roff[j] & rcm) != rcv) continue;
+        const double2 a = reg[j], b = reg[j + S];
+        reg[j] = cmad2<double2, double>(m[0], m[1], a, m[2], m[3], b);
+        reg[j + S] = cmad2<double2, double>(m[4], m[5], a, m[6], m[7], b);
+    }
+}
+
+template <int NR, int B0, int B1, bool CTL>
+__device__ __forceinline__ void seg_2q(double2 (&reg)[NR], const uint32_t (&roff)[NR], uint32_t rcm, uint32_t rcv,
+                                       bool tok, const double* __restrict__ u)
+{
+    constexpr int S0 = 1 << B0, S1 = 1 << B1;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j & (S0 | S1)) continue;
+        if constexpr (CTL)
+            if ((roff[j] & rcm) != rcv) continue;
+        const double2 v0 = reg[j], v1 = reg[j + S0], v2 = reg[j + S1], v3 = reg[j + S0 + S1];
+        double2 o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double m[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double id = ((i & 1) == 0 && (i >> 1) == r) ? 1.0 : 0.0;
+                m[i] = CTL ? (tok ? u[8 * r + i] : id) : u[8 * r + i];
+            }
+            const double2 s1 = cmad2<double2, double>(m[0], m[1], v0, m[2], m[3], v1);
+            const double2 s2 = cmad2<double2, double>(m[4], m[5], v2, m[6], m[7], v3);
+            o[r].x = s1.x + s2.x;
+            o[r].y = s1.y + s2.y;
+        }
+        reg[j] = o[0];
+        reg[j + S0] = o[1];
+        reg[j + S1] = o[2];
+        reg[j + S0 + S1] = o[3];
+    }
+}
+
+// Diagonal bodies: multiply each register by its factor F[ri], ri spelled
+// by the register's bits at ranks B0 (and B1); the X forms multiply only the
+// registers whose combination is RI (the others have factor 1).
+template <int NR, int B0>
+__device__ __forceinline__ void diag_r1(double2 (&reg)[NR], const double2 (&F)[4])
+{
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int ri = (j >> B0) & 1;
+        reg[j] = cmul<double2, double>(F[ri].x, F[ri].y, reg[j]);
+    }
+}
+
+template <int NR, int B0, int B1>
+__device__ __forceinline__ void diag_r2(double2 (&reg)[NR], const double2 (&F)[4])
+{
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int ri = ((j >> B0) & 1) | (((j >> B1) & 1) << 1);
+        reg[j] = cmul<double2, double>(F[ri].x, F[ri].y, reg[j]);
+    }
+}
+
+template <int NR, int B0, int RI>
+__device__ __forceinline__ void diag_r1x(double2 (&reg)[NR], const double2 (&F)[4])
+{
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (((j >> B0) & 1) == RI) reg[j] = cmul<double2, double>(F[RI].x, F[RI].y, reg[j]);
+}
+
+template <int NR, int B0, int B1, int RI>
+__device__ __forceinline__ void diag_r2x(double2 (&reg)[NR], const double2 (&F)[4])
+{
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if ((((j >> B0) & 1) | (((j >> B1) & 1) << 1)) == RI)
+            reg[j] = cmul<double2, double>(F[RI].x, F[RI].y, reg[j]);
+}
+
+// Per-thread factors of a diagonal member (register form): F[ri] for each
+// combination ri of its register targets, selected by the thread's own bits
+// among uniform loads of the factor table.
+__device__ __forceinline__ void diag_factors(double2 (&F)[4], const TileOp& g, uint64_t base, uint32_t eb,
+                                             const double* __restrict__ dd)
+{
+    const int kr = g.dj & 15, kt = (g.dj >> 4) & 15, k = g.k;
+    uint32_t gi = 0; // uniform: targets outside the tile
+    for (int j = kr + kt; j < k; ++j) gi |= (uint32_t)((base >> g.p[j]) & 1) << j;
+    const bool t0 = kt > 0 && ((eb >> g.p[kr]) & 1);
+    const bool t1 = kt > 1 && ((eb >> g.p[kr + 1]) & 1);
+#pragma unroll
+    for (int ri = 0; ri < 4; ++ri) {
+        // plain double selects: a select of double2 values is lowered through
+        // a per-lane indexed stack copy
+        double fx = 1.0, fy = 0.0;
+        if (ri < (1 << kr)) {
+            const uint32_t i0 = gi | (uint32_t)ri;
+            const uint32_t s0 = 1u << kr, s1 = 2u << kr;
+            fx = dd[2 * i0];
+            fy = dd[2 * i0 + 1];
+            if (kt > 0) {
+                const double ax = dd[2 * (i0 | s0)], ay = dd[2 * (i0 | s0) + 1];
+                if (kt > 1) {
+                    const double bx = dd[2 * (i0 | s1)], by = dd[2 * (i0 | s1) + 1];
+                    const double cx = dd[2 * (i0 | s0 | s1)], cy = dd[2 * (i0 | s0 | s1) + 1];
+                    const double lox = t0 ? ax : fx, loy = t0 ? ay : fy;
+                    const double hix = t0 ? cx : bx, hiy = t0 ? cy : by;
+                    fx = t1 ? hix : lox;
+                    fy = t1 ? hiy : loy;
+                } else {
+                    fx = t0 ? ax : fx;
+                    fy = t0 ? ay : fy;
+                }
+            }
+        }
+        F[ri].x = fx;
+        F[ri].y = fy;
+    }
+}
+
+// A diagonal member the planner left in general form: factor gathered per
+// element from its local bits (controls tested per element).
+template <int NR>
+__device__ __forceinline__ void diag_gather(double2 (&reg)[NR], const uint32_t (&roff)[NR], uint32_t rmask,
+                                            uint32_t eb, const TileOp& g, uint64_t base,
+                                            const double* __restrict__ dd)
+{
+    const uint32_t lcm = (uint32_t)g.lcm, lcv = (uint32_t)g.lcv;
+    const uint32_t tcm = lcm & ~rmask, rcm = lcm & rmask, rcv = lcv & rcm;
+    if ((eb & tcm) != (lcv & tcm)) return;
+    uint32_t tidx = 0;
+    for (int t = 0; t < g.k; ++t) {
+        const int q = g.lp[t];
+        if (q < 0) tidx |= (uint32_t)((base >> g.p[t]) & 1) << t;
+        else if (!((rmask >> q) & 1)) tidx |= ((eb >> q) & 1) << t;
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if ((roff[j] & rcm) != rcv) continue;
+        uint32_t idx = tidx;
+        for (int t = 0; t < g.k; ++t) {
+            const int q = g.lp[t];
+            if (q >= 0 && ((rmask >> q) & 1)) idx |= ((roff[j] >> q) & 1) << t;
+        }
+        reg[j] = cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], reg[j]);
+    }
+}
+
+// A fused block: the registers are multiplied by a 2^r x 2^r complex matrix
+// (row-major, FP64) that the planner formed from a run of register-only ops.
+template <int NR>
+__device__ __forceinline__ void seg_block(double2 (&reg)[NR], const double* __restrict__ u)
+{
+    double2 o[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            const double ar = u[2 * (r * NR + c)], ai = u[2 * (r * NR + c) + 1];
+            sr = fma(ar, reg[c].x, sr);
+            sr = fma(-ai, reg[c].y, sr);
+            si = fma(ar, reg[c].y, si);
+            si = fma(ai, reg[c].x, si);
+        }
+        o[r].x = sr;
+        o[r].y = si;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) reg[r] = o[r];
+}
+
+// One segment member, dispatched by its opcode in a single switch so the
+// register array has one join per op.
+template <int RR, int NR>
+__device__ __forceinline__ void seg_op(double2 (&reg)[NR], const uint32_t (&roff)[NR], uint32_t rmask, uint32_t eb,
+                                       const TileOp& d, uint64_t base, const double* __restrict__ mats)
+{
+    const int opc = d.rsv >> 16;
+    const double* u = mats + d.moff;
+    if (opc == SO_BLOCK) {
+        seg_block<NR>(reg, u);
+        return;
+    }
+    if (opc < SO_D0) {
+        const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
+        const uint32_t rcm = lcm & rmask, rcv = lcv & rcm, tcm = lcm & ~rmask;
+        const bool tok = (eb & tcm) == (lcv & tcm); // controls at thread positions
+        switch (opc) {
+#define QS_C1(B_)                                                                                    \
+    case SO_1Q + B_:                                                                                 \
+        if constexpr (B_ < RR) seg_1q<NR, B_, false>(reg, roff, 0, 0, true, u);                            \
+        break;                                                                                       \
+    case SO_1Q + 4 + B_:                                                                             \
+        if constexpr (B_ < RR) seg_1q<NR, B_, true>(reg, roff, rcm, rcv, tok, u);                         \
+        break;
+        QS_C1(0) QS_C1(1) QS_C1(2) QS_C1(3)
+#undef QS_C1
+#define QS_C2(P_, A_, B_)                                                                            \
+    case SO_2Q + P_:                                                                                 \
+        if constexpr (B_ < RR) seg_2q<NR, A_, B_, false>(reg, roff, 0, 0, true, u);                        \
+        break;                                                                                       \
+    case SO_2Q + 6 + P_:                                                                             \
+        if constexpr (B_ < RR) seg_2q<NR, A_, B_, true>(reg, roff, rcm, rcv, tok, u);                     \
+        break;
+        QS_C2(0, 0, 1) QS_C2(1, 0, 2) QS_C2(2, 1, 2) QS_C2(3, 0, 3) QS_C2(4, 1, 3) QS_C2(5, 2, 3)
+#undef QS_C2
+        default: break;
+        }
+        return;
+    }
+    if (opc == SO_DG) {
+        diag_gather<NR>(reg, roff, rmask, eb, d, base, u);
+        return;
+    }
+    double2 F[4];
+    diag_factors(F, d, base, eb, u);
+    switch (opc) {
+    case SO_D0:
+#pragma unroll
+        for (int j = 0; j < NR; ++j) reg[j] = cmul<double2, double>(F[0].x, F[0].y, reg[j]);
+        break;
+#define QS_D1(B_)                                                                                    \
+    case SO_D1 + B_:                                                                                 \
+        if constexpr (B_ < RR) diag_r1<NR, B_>(reg, F);                                              \
+        break;                                                                                       \
+    case SO_D1X + 2 * B_:                                                                            \
+        if constexpr (B_ < RR) diag_r1x<NR, B_, 0>(reg, F);                                          \
+        break;                                                                                       \
+    case SO_D1X + 2 * B_ + 1:                                                                        \
+        if constexpr (B_ < RR) diag_r1x<NR, B_, 1>(reg, F);                                          \
+        break;
+        QS_D1(0) QS_D1(1) QS_D1(2) QS_D1(3)
+#undef QS_D1
+#define QS_D2(P_, A_, B_)                                                                            \
+    case SO_D2 + P_:                                                                                 \
+        if constexpr (B_ < RR) diag_r2<NR, A_, B_>(reg, F);                                          \
+        break;                                                                                       \
+    case SO_D2X + 4 * P_:                                                                            \
+        if constexpr (B_ < RR) diag_r2x<NR, A_, B_, 0>(reg, F);                                      \
+        break;                                                                                       \
+    case SO_D2X + 4 * P_ + 1:                                                                        \
+        if constexpr (B_ < RR) diag_r2x<NR, A_, B_, 1>(reg, F);                                      \
+        break;                                                                                       \
+    case SO_D2X + 4 * P_ + 2:                                                                        \
+        if constexpr (B_ < RR) diag_r2x<NR, A_, B_, 2>(reg, F);                                      \
+        break;                                                                                       \
+    case SO_D2X + 4 * P_ + 3:                                                                        \
+        if constexpr (B_ < RR) diag_r2x<NR, A_, B_, 3>(reg, F);                                      \
+        break;
+        QS_D2(0, 0, 1) QS_D2(1, 0, 2) QS_D2(2, 1, 2) QS_D2(3, 0, 3) QS_D2(4, 1, 3) QS_D2(5, 2, 3)
+#undef QS_D2
+    default: break;
+    }
+}
+
+template <typename R, int M>
+__device__ __forceinline__ void run_segment(typename CT<R>::V* tile, uint64_t base, const TileOp* __restrict__ hdr,
+                                            const double* __restrict__ mats, int tid)
+{
+    using V = typename CT<R>::V;
+    using S = Seg<R, M>;
+    constexpr int RR = S::RR, NR = S::NR;
+    const int nmem = hdr->dj;
+    uint32_t rmask = 0;
+    int rp[RR];
+#pragma unroll
+    for (int b = 0; b < RR; ++b) {
+        rp[b] = hdr->p[b];
+        rmask |= 1u << rp[b];
+    }
+    uint32_t roff[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int b = 0; b < RR; ++b)
+            if ((j >> b) & 1) o |= 1u << rp[b];
+        roff[j] = o;
+    }
+    const uint32_t freem = ((1u << M) - 1) & ~rmask;
+    for (int li = 0; li < S::LI; ++li) {
+        uint32_t src = (uint32_t)tid | ((uint32_t)li << 8), eb = 0;
+        for (int b = 0; b < M; ++b)
+            if ((freem >> b) & 1) {
+                eb |= (src & 1u) << b;
+                src >>= 1;
+            }
+        double2 reg[NR];
+#pragma unroll
+        for (int j = 0; j < NR; ++j) reg[j] = ld2(tile[QS_SW(eb | roff[j])]);
+        for (int o = 1; o <= nmem; ++o) {
+            const TileOp& d = hdr[o];
+            if ((base & d.gcm) == d.gcv) seg_op<RR, NR>(reg, roff, rmask, eb, d, base, mats);
+        }
+#pragma unroll
+        for (int j = 0; j < NR; ++j) tile[QS_SW(eb | roff[j])] = st2<V>(reg[j]);
     }
 }
 
 // Apply a pass's operation list to the tile held in LDS (all lanes of the
 // block call this; it ends with the tile complete in LDS).  `base` is the
 // global index of tile element 0 (tile bits zero).
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base, const TileOp* __restrict__ ops,
                                          int nops, const double* __restrict__ mats)
 {
@@ -118,6 +476,15 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
     for (int o = 0; o < nops; ++o) {
         const TileOp& d = ops[o];
         const int kind = d.kind;
+        if (kind == TK_SEG) {
+            if constexpr (M >= 10) run_segment<R, M>(tile, base, ops + o, mats, tid);
+            o += d.dj;
+            __syncthreads();
+            continue;
+        }
+        // the lean kernel of a large tile holds segments only (the host
+        // launches the full kernel for any other op)
+        if constexpr (!FULL && M >= 10) continue;
         if (kind != TK_DIAG && (base & d.gcm) != d.gcv) continue; // tile fails the outside controls
         const double* u = mats + d.moff;
         const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
@@ -133,9 +500,9 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                     const uint32_t k = tid + 256 * s;
                     if (E >= 512 || k < E / 2) {
                         const uint32_t e0 = k + (k & hm), e1 = e0 + pb;
-                        const double2 a = ld2(tile[e0]), b = ld2(tile[e1]);
-                        tile[e0] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
-                        tile[e1] = st2<V>(cmad2<double2, double>(u4, u5, a, u6, u7, b));
+                        const double2 a = ld2(tile[QS_SW(e0)]), b = ld2(tile[QS_SW(e1)]);
+                        tile[QS_SW(e0)] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
+                        tile[QS_SW(e1)] = st2<V>(cmad2<double2, double>(u4, u5, a, u6, u7, b));
                     }
                 }
             } else {
@@ -145,9 +512,9 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                     if (E >= 512 || k < E / 2) {
                         const uint32_t e0 = k + (k & hm), e1 = e0 + pb;
                         if ((e0 & lcm) == lcv) {
-                            const double2 a = ld2(tile[e0]), b = ld2(tile[e1]);
-                            tile[e0] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
-                            tile[e1] = st2<V>(cmad2<double2, double>(u4, u5, a, u6, u7, b));
+                            const double2 a = ld2(tile[QS_SW(e0)]), b = ld2(tile[QS_SW(e1)]);
+                            tile[QS_SW(e0)] = st2<V>(cmad2<double2, double>(u0, u1, a, u2, u3, b));
+                            tile[QS_SW(e1)] = st2<V>(cmad2<double2, double>(u4, u5, a, u6, u7, b));
                         }
                     }
                 }
@@ -162,8 +529,8 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                 if (k < E / 4) {
                     const uint32_t e = ins0_32(ins0_32(k, lo), hi);
                     if ((e & lcm) == lcv) {
-                        const double2 v0 = ld2(tile[e]), v1 = ld2(tile[e | b0]), v2 = ld2(tile[e | b1]),
-                                      v3 = ld2(tile[e | b0 | b1]);
+                        const double2 v0 = ld2(tile[QS_SW(e)]), v1 = ld2(tile[QS_SW(e | b0)]), v2 = ld2(tile[QS_SW(e | b1)]),
+                                      v3 = ld2(tile[QS_SW(e | b0 | b1)]);
                         double2 out[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -173,14 +540,15 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                             out[r].x = s1.x + s2.x;
                             out[r].y = s1.y + s2.y;
                         }
-                        tile[e] = st2<V>(out[0]);
-                        tile[e | b0] = st2<V>(out[1]);
-                        tile[e | b1] = st2<V>(out[2]);
-                        tile[e | b0 | b1] = st2<V>(out[3]);
+                        tile[QS_SW(e)] = st2<V>(out[0]);
+                        tile[QS_SW(e | b0)] = st2<V>(out[1]);
+                        tile[QS_SW(e | b1)] = st2<V>(out[2]);
+                        tile[QS_SW(e | b0 | b1)] = st2<V>(out[3]);
                     }
                 }
             }
         } else if (kind == TK_DENSEK) {
+            if constexpr (!FULL) continue;
             // Rounds of 256 slots; a round holds whole groups (D <= 64
             // divides 256), so every lane reads its group, all wait, and
             // all write: no group is overwritten while still being read.
@@ -206,7 +574,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                             uint32_t ei = gb;
                             for (int j = 0; j < k; ++j)
                                 if ((mm >> j) & 1) ei |= 1u << d.p[j];
-                            const double2 x = ld2(tile[ei]);
+                            const double2 x = ld2(tile[QS_SW(ei)]);
                             const double ar = u[2 * (r * D + mm)], ai = u[2 * (r * D + mm) + 1];
                             sr += ar * x.x - ai * x.y;
                             si += ar * x.y + ai * x.x;
@@ -219,11 +587,11 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                     }
                 }
                 __syncthreads();
-                if (act) tile[eo] = st2<V>(res);
+                if (act) tile[QS_SW(eo)] = st2<V>(res);
                 __syncthreads();
             }
         } else if (kind == TK_MFMA) {
-            if constexpr (sizeof(R) == 4 && M >= 8) {
+            if constexpr (FULL && sizeof(R) == 4 && M >= 8) {
                 if (d.k == 5) {
                     if constexpr (M >= 9) mfma_block<5, M>((float2*)tile, d, mats, tid);
                 } else {
@@ -252,7 +620,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                     const uint32_t e = tid + 256 * s;
                     if (E >= 256 || e < E) {
                         const bool one = (e >> abit) & 1;
-                        tile[e] = st2<V>(cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, ld2(tile[e])));
+                        tile[QS_SW(e)] = st2<V>(cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, ld2(tile[QS_SW(e)])));
                     }
                 }
                 abit = -1;
@@ -299,7 +667,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                         const uint32_t e = tid + 256 * s;
                         if ((E >= 256 || e < E) && ((e >> cb) & 1) == cv) {
                             const bool one = (e >> tb) & 1;
-                            tile[e] = st2<V>(cmul<double2, double>(one ? f1r : f0r, one ? f1i : f0i, ld2(tile[e])));
+                            tile[QS_SW(e)] = st2<V>(cmul<double2, double>(one ? f1r : f0r, one ? f1i : f0i, ld2(tile[QS_SW(e)])));
                         }
                     }
                 } else {
@@ -312,7 +680,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                             uint32_t idx = gidx;
                             for (int j = 0; j < g.k; ++j)
                                 if (g.lp[j] >= 0) idx |= ((e >> g.lp[j]) & 1) << j;
-                            tile[e] = st2<V>(cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], ld2(tile[e])));
+                            tile[QS_SW(e)] = st2<V>(cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], ld2(tile[QS_SW(e)])));
                         }
                     }
                 }
@@ -326,7 +694,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
 #pragma unroll 4
                 for (int s = 0; s < PER; ++s) {
                     const uint32_t e = tid + 256 * s;
-                    if (E >= 256 || e < E) tile[e] = st2<V>(cmul<double2, double>(cr, ci, ld2(tile[e])));
+                    if (E >= 256 || e < E) tile[QS_SW(e)] = st2<V>(cmul<double2, double>(cr, ci, ld2(tile[QS_SW(e)])));
                 }
             }
             o = o2 - 1;
@@ -364,7 +732,7 @@ __device__ __forceinline__ void tile_load(const typename CT<R>::V* __restrict__ 
             V v;
             v.x = rx[s];
             v.y = ry[s];
-            tile[e] = v;
+            tile[QS_SW(e)] = v;
         }
     }
 }
@@ -384,9 +752,9 @@ __device__ __forceinline__ void tile_store(typename CT<R>::V* __restrict__ psi, 
         if (e < E) {
             V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
             if (nt)
-                gst<true>(a, tile[e]);
+                gst<true>(a, tile[QS_SW(e)]);
             else
-                gst<false>(a, tile[e]);
+                gst<false>(a, tile[QS_SW(e)]);
         }
     }
 }
@@ -403,7 +771,7 @@ __device__ __forceinline__ void build_hoff(uint32_t* hoff, int M, int L, const i
     }
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
        const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
@@ -419,7 +787,7 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
         const uint64_t base = ins_bits(tau, ipQ);
         tile_load<R, M>(psi, base, ql.L, hoff, tile, nt);
         __syncthreads();
-        tile_ops<R, M, MF>(tile, base, ops, nops, mats);
+        tile_ops<R, M, FULL>(tile, base, ops, nops, mats);
         tile_store<R, M>(psi, base, ql.L, hoff, tile, nt);
         __syncthreads();
     }
@@ -427,7 +795,7 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
 
 // ---------------------------------------------------------------- batches
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_batch_whole(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
               const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
@@ -444,18 +812,18 @@ k_batch_whole(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
         V v;
         v.x = (e == c.basis) ? (R)1 : (R)0;
         v.y = 0;
-        tile[e] = v;
+        tile[QS_SW(e)] = v;
     }
     if (threadIdx.x == 0) hoff[0] = 0;
     __syncthreads();
     for (int p = 0; p < c.npass; ++p) {
         const BatchPass& bp = passes[c.pass0 + p];
-        tile_ops<R, M, MF>(tile, 0, ops + bp.op0, bp.nops, mats);
+        tile_ops<R, M, FULL>(tile, 0, ops + bp.op0, bp.nops, mats);
     }
     tile_store<R, M>(psi, 0, M, hoff, tile, M >= 4 ? 1 : 0);
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_batch_persist(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
                 const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
@@ -485,14 +853,14 @@ k_batch_persist(char* __restrict__ arena, const BatchCirc* __restrict__ circs, c
             const uint64_t base = ins_bits(tau, bp.ip);
             tile_load<R, M>(psi, base, bp.L, hoff, tile, 0);
             __syncthreads();
-            tile_ops<R, M, MF>(tile, base, ops + bp.op0, bp.nops, mats);
+            tile_ops<R, M, FULL>(tile, base, ops + bp.op0, bp.nops, mats);
             tile_store<R, M>(psi, base, bp.L, hoff, tile, 0);
             __syncthreads();
         }
     }
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_batch_round(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const BatchPass* __restrict__ passes,
               const TileOp* __restrict__ ops, const double* __restrict__ mats,
@@ -522,7 +890,7 @@ k_batch_round(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
     const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
     tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
     __syncthreads();
-    tile_ops<R, M, MF>(tile, base, ops + bp.op0, bp.nops, mats);
+    tile_ops<R, M, FULL>(tile, base, ops + bp.op0, bp.nops, mats);
     tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
 }
 
@@ -551,7 +919,7 @@ k_batch_basis(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
     }
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const BatchPass* passes, const TileOp* ops,
                                  const double* mats, const RoundEntry* entries, int nentries, uint32_t nblocks,
                                  hipStream_t st)
@@ -561,18 +929,18 @@ static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const Batc
     if (lds > 65536) {
         static bool set = false;
         if (!set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_batch_round<R, M, MF>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_round<R, M, FULL>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_batch_round<R, M, MF>), dim3(nblocks), dim3(256), lds, st, arena, circs, passes, ops, mats,
+    hipLaunchKernelGGL((k_batch_round<R, M, FULL>), dim3(nblocks), dim3(256), lds, st, arena, circs, passes, ops, mats,
                        entries, nentries);
     return hipGetLastError();
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_serve_round(const ServeEntry* __restrict__ entries, int nentries)
 {
@@ -598,11 +966,11 @@ k_serve_round(const ServeEntry* __restrict__ entries, int nentries)
     const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
     tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
     __syncthreads();
-    tile_ops<R, M, MF>(tile, base, en.ops + bp.op0, bp.nops, en.mats);
+    tile_ops<R, M, FULL>(tile, base, en.ops + bp.op0, bp.nops, en.mats);
     tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_serve_whole(const ServeEntry* __restrict__ entries)
 {
@@ -616,15 +984,15 @@ k_serve_whole(const ServeEntry* __restrict__ entries)
         V v;
         v.x = (e == en.basis) ? (R)1 : (R)0;
         v.y = 0;
-        tile[e] = v;
+        tile[QS_SW(e)] = v;
     }
     if (threadIdx.x == 0) hoff[0] = 0;
     __syncthreads();
-    if (en.pass) tile_ops<R, M, MF>(tile, 0, en.ops + en.pass->op0, en.pass->nops, en.mats);
+    if (en.pass) tile_ops<R, M, FULL>(tile, 0, en.ops + en.pass->op0, en.pass->nops, en.mats);
     tile_store<R, M>((V*)en.psi, 0, M, hoff, tile, M >= 4 ? 1 : 0);
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 static hipError_t launch_serve_round_m(const ServeEntry* entries, int nentries, uint32_t nblocks, hipStream_t st)
 {
     const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
@@ -632,34 +1000,34 @@ static hipError_t launch_serve_round_m(const ServeEntry* entries, int nentries, 
     if (lds > 65536) {
         static bool set = false;
         if (!set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_serve_round<R, M, MF>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_serve_round<R, M, FULL>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_serve_round<R, M, MF>), dim3(nblocks), dim3(256), lds, st, entries, nentries);
+    hipLaunchKernelGGL((k_serve_round<R, M, FULL>), dim3(nblocks), dim3(256), lds, st, entries, nentries);
     return hipGetLastError();
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 static hipError_t launch_serve_whole_m(const ServeEntry* entries, int nentries, hipStream_t st)
 {
     const size_t lds = sizeof(typename CT<R>::V) * (1ull << M) + 16;
     if (lds > 65536) {
         static bool set = false;
         if (!set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_serve_whole<R, M, MF>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_serve_whole<R, M, FULL>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_serve_whole<R, M, MF>), dim3(nentries), dim3(256), lds, st, entries);
+    hipLaunchKernelGGL((k_serve_whole<R, M, FULL>), dim3(nentries), dim3(256), lds, st, entries);
     return hipGetLastError();
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 static hipError_t launch_whole_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                  const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
@@ -667,17 +1035,17 @@ static hipError_t launch_whole_m(char* arena, const BatchCirc* circs, const int3
     if (lds > 65536) {
         static bool set = false;
         if (!set) {
-            hipError_t e = hipFuncSetAttribute((const void*)k_batch_whole<R, M, MF>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_whole<R, M, FULL>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_batch_whole<R, M, MF>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops, mats);
+    hipLaunchKernelGGL((k_batch_whole<R, M, FULL>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops, mats);
     return hipGetLastError();
 }
 
-template <typename R, int M, bool MF>
+template <typename R, int M, bool FULL>
 static hipError_t launch_persist_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                    const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
@@ -686,7 +1054,7 @@ static hipError_t launch_persist_m(char* arena, const BatchCirc* circs, const in
         static bool set = false;
         if (!set) {
             const int lim = lds_max > 163840 ? 163840 : (int)lds_max;
-            hipError_t e = hipFuncSetAttribute((const void*)k_batch_persist<R, M, MF>,
+            hipError_t e = hipFuncSetAttribute((const void*)k_batch_persist<R, M, FULL>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, lim);
             if (e != hipSuccess) return e;
             set = true;
@@ -694,7 +1062,7 @@ static hipError_t launch_persist_m(char* arena, const BatchCirc* circs, const in
     }
     // LDS for the smallest L any pass may have
     const size_t lds = lds_max > 163840 ? 163840 : lds_max;
-    hipLaunchKernelGGL((k_batch_persist<R, M, MF>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops,
+    hipLaunchKernelGGL((k_batch_persist<R, M, FULL>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops,
                        mats);
     return hipGetLastError();
 }
@@ -735,11 +1103,9 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     const int line_bits = sizeof(R) == 8 ? 3 : 4;
     static int nt_env = env_int("QS_NT", 1);
     const int nt = (nt_env && pass.L >= line_bits) ? 1 : 0;
-    // the matrix-core variant only when the pass holds a fused block (its
-    // fragments would otherwise cost every pass registers)
-    bool mf = false;
-    for (const TileOp& t : pass.ops) mf |= t.kind == TK_MFMA;
-    if (mf)
+    // the full variant only when the pass needs it (k >= 3 ops, fused
+    // blocks or ops outside segments would otherwise cost every pass registers)
+    if (ops_need_full(pass.ops.data(), pass.ops.size(), pass.m))
         hipLaunchKernelGGL((k_tile<R, M, true>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
                            (int)pass.ops.size(), (const double*)dmats, nt);
     else
@@ -763,13 +1129,13 @@ hipError_t launch_r(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     }
 }
 
-template <typename R, bool MF>
+template <typename R, bool FULL>
 static hipError_t batch_whole_r(int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                 const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
     switch (M) {
 #define QS_WCASE(MM) \
-    case MM: return launch_whole_m<R, MM, MF>(arena, circs, list, count, passes, ops, mats, st);
+    case MM: return launch_whole_m<R, MM, FULL>(arena, circs, list, count, passes, ops, mats, st);
         QS_WCASE(1) QS_WCASE(2) QS_WCASE(3) QS_WCASE(4) QS_WCASE(5) QS_WCASE(6) QS_WCASE(7) QS_WCASE(8)
         QS_WCASE(9) QS_WCASE(10) QS_WCASE(11) QS_WCASE(12) QS_WCASE(13)
 #undef QS_WCASE
@@ -777,13 +1143,13 @@ static hipError_t batch_whole_r(int M, char* arena, const BatchCirc* circs, cons
     }
 }
 
-template <typename R, bool MF>
+template <typename R, bool FULL>
 static hipError_t batch_persist_r(int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                   const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
     switch (M) {
 #define QS_PCASE(MM) \
-    case MM: return launch_persist_m<R, MM, MF>(arena, circs, list, count, passes, ops, mats, st);
+    case MM: return launch_persist_m<R, MM, FULL>(arena, circs, list, count, passes, ops, mats, st);
         QS_PCASE(9) QS_PCASE(10) QS_PCASE(11) QS_PCASE(12) QS_PCASE(13)
 #undef QS_PCASE
     default: return hipErrorInvalidValue;
@@ -798,33 +1164,37 @@ size_t tile_lds_bytes(int dt, int m, int L)
 }
 
 hipError_t launch_batch_whole(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
-                              const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                              const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
                               hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (dt == QS_C128) return batch_whole_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
-    return mf ? batch_whole_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
+    if (dt == QS_C128)
+        return full ? batch_whole_r<double, true>(M, arena, circs, list, count, passes, ops, mats, st)
+                  : batch_whole_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
+    return full ? batch_whole_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
               : batch_whole_r<float, false>(M, arena, circs, list, count, passes, ops, mats, st);
 }
 
 hipError_t launch_batch_persist(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list,
-                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool mf,
+                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
                                 hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (dt == QS_C128) return batch_persist_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
-    return mf ? batch_persist_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
+    if (dt == QS_C128)
+        return full ? batch_persist_r<double, true>(M, arena, circs, list, count, passes, ops, mats, st)
+                  : batch_persist_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
+    return full ? batch_persist_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
               : batch_persist_r<float, false>(M, arena, circs, list, count, passes, ops, mats, st);
 }
 
-template <typename R, bool MF>
+template <typename R, bool FULL>
 static hipError_t batch_round_r(int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
                                 const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
                                 uint32_t nblocks, hipStream_t st)
 {
     switch (M) {
 #define QS_RCASE(MM) \
-    case MM: return launch_round_m<R, MM, MF>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+    case MM: return launch_round_m<R, MM, FULL>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
         QS_RCASE(9) QS_RCASE(10) QS_RCASE(11) QS_RCASE(12) QS_RCASE(13)
 #undef QS_RCASE
     default: return hipErrorInvalidValue;
@@ -833,12 +1203,13 @@ static hipError_t batch_round_r(int M, char* arena, const BatchCirc* circs, cons
 
 hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
                               const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
-                              uint32_t nblocks, bool mf, hipStream_t st)
+                              uint32_t nblocks, bool full, hipStream_t st)
 {
     if (nentries <= 0 || nblocks == 0) return hipSuccess;
     if (dt == QS_C128)
-        return batch_round_r<double, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
-    return mf ? batch_round_r<float, true>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st)
+        return full ? batch_round_r<double, true>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st)
+                  : batch_round_r<double, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+    return full ? batch_round_r<float, true>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st)
               : batch_round_r<float, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
 }
 
@@ -860,24 +1231,24 @@ hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCir
     return hipGetLastError();
 }
 
-template <typename R, bool MF>
+template <typename R, bool FULL>
 static hipError_t serve_round_r(int M, const ServeEntry* entries, int nentries, uint32_t nblocks, hipStream_t st)
 {
     switch (M) {
 #define QS_SRCASE(MM) \
-    case MM: return launch_serve_round_m<R, MM, MF>(entries, nentries, nblocks, st);
+    case MM: return launch_serve_round_m<R, MM, FULL>(entries, nentries, nblocks, st);
         QS_SRCASE(9) QS_SRCASE(10) QS_SRCASE(11) QS_SRCASE(12) QS_SRCASE(13)
 #undef QS_SRCASE
     default: return hipErrorInvalidValue;
     }
 }
 
-template <typename R, bool MF>
+template <typename R, bool FULL>
 static hipError_t serve_whole_r(int M, const ServeEntry* entries, int nentries, hipStream_t st)
 {
     switch (M) {
 #define QS_SWCASE(MM) \
-    case MM: return launch_serve_whole_m<R, MM, MF>(entries, nentries, st);
+    case MM: return launch_serve_whole_m<R, MM, FULL>(entries, nentries, st);
         QS_SWCASE(1) QS_SWCASE(2) QS_SWCASE(3) QS_SWCASE(4) QS_SWCASE(5) QS_SWCASE(6) QS_SWCASE(7)
         QS_SWCASE(8) QS_SWCASE(9) QS_SWCASE(10) QS_SWCASE(11) QS_SWCASE(12) QS_SWCASE(13)
 #undef QS_SWCASE
@@ -885,20 +1256,24 @@ static hipError_t serve_whole_r(int M, const ServeEntry* entries, int nentries, 
     }
 }
 
-hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool mf,
+hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool full,
                               hipStream_t st)
 {
     if (nentries <= 0 || nblocks == 0) return hipSuccess;
-    if (dt == QS_C128) return serve_round_r<double, false>(M, entries, nentries, nblocks, st);
-    return mf ? serve_round_r<float, true>(M, entries, nentries, nblocks, st)
+    if (dt == QS_C128)
+        return full ? serve_round_r<double, true>(M, entries, nentries, nblocks, st)
+                  : serve_round_r<double, false>(M, entries, nentries, nblocks, st);
+    return full ? serve_round_r<float, true>(M, entries, nentries, nblocks, st)
               : serve_round_r<float, false>(M, entries, nentries, nblocks, st);
 }
 
-hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool mf, hipStream_t st)
+hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool full, hipStream_t st)
 {
     if (nentries <= 0) return hipSuccess;
-    if (dt == QS_C128) return serve_whole_r<double, false>(M, entries, nentries, st);
-    return mf ? serve_whole_r<float, true>(M, entries, nentries, st)
+    if (dt == QS_C128)
+        return full ? serve_whole_r<double, true>(M, entries, nentries, st)
+                  : serve_whole_r<double, false>(M, entries, nentries, st);
+    return full ? serve_whole_r<float, true>(M, entries, nentries, st)
               : serve_whole_r<float, false>(M, entries, nentries, st);
 }
 

@@ -102,23 +102,25 @@ def test_planner_groups_gates(qs):
     # every gate inside the tile: one pass
     c = W.random_u3_cnot(10, 200, seed=2)
     ops, mats = c.arrays()
-    assert qs.qs_plan_circuit(10, qs.QS_C128, ops, mats, tile_qubits=10) == (1, len(ops))
+    npass, nops = qs.qs_plan_circuit(10, qs.QS_C128, ops, mats, tile_qubits=10)
+    assert npass == 1 and nops <= len(ops)  # register blocks absorb runs of gates
     # diagonal gates never force a new pass
     q = W.qft(24)
     ops, mats = q.arrays()
     npass, nops = qs.qs_plan_circuit(24, qs.QS_C128, ops, mats, tile_qubits=11)
-    assert nops == len(ops)
+    assert nops <= len(ops)
     n_dense = 24 + 12  # Hadamards and swaps
     assert npass < n_dense // 2
     # per-gate mode is not planned into tiles but validates the same way
     r = W.rqc_chain(32, 20, 5)
     ops, mats = r.arrays()
     npass, nops = qs.qs_plan_circuit(32, qs.QS_C64, ops, mats, tile_qubits=12)
-    assert nops == len(ops) and npass <= 20 * 6
+    assert nops <= len(ops) and npass <= 20 * 6
 
 
 def test_planner_fuses_blocks_for_c64(qs, monkeypatch):
     monkeypatch.setenv("QS_FUSE_MIN", "2")
+    monkeypatch.setenv("QS_REG_SEGMENTS", "0")  # compare matrix-core blocks with ops one by one
     r = W.rqc_chain(20, 10, 1)
     ops, mats = r.arrays()
     plain = qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, tile_qubits=12)

@@ -43,11 +43,12 @@ def _random_mixed(n, count, seed):
 
 def _circuits():
     return [W.random_u3_cnot(9, 150, seed=3), W.rqc_chain(10, 8, 4), W.qft(9, 300), W.grover(8, 77),
-            _random_mixed(9, 160, 5), _random_mixed(10, 200, 6)]
+            _random_mixed(9, 160, 5), _random_mixed(10, 200, 6), _random_mixed(12, 250, 7), W.rqc_chain(12, 10, 8),
+            W.rqc_chain(13, 2, 632), W.rqc_chain(12, 3, 2)]
 
 
-@pytest.mark.parametrize("tq,low", [(4, 2), (5, 3), (6, 0)])
-@pytest.mark.parametrize("ci", range(6))
+@pytest.mark.parametrize("tq,low", [(4, 2), (5, 3), (6, 0), (10, 3), (11, 5)])
+@pytest.mark.parametrize("ci", range(10))
 def test_planned_order_matches_oracle(qs, monkeypatch, ci, tq, low):
     monkeypatch.setenv("QS_TILE_LOW", str(low))
     c = _circuits()[ci]
@@ -102,3 +103,22 @@ def test_noncommuting_swap_is_detected():
             assert float(np.max(np.abs(got - ref))) > 1e-6
             return
     pytest.fail("no adjacent non-commuting pair in the sample circuit")
+
+
+@pytest.mark.parametrize("dt", [1, 2])
+@pytest.mark.parametrize("tq,low", [(10, 5), (11, 6), (12, 5), (13, 6), (0, 5)])
+@pytest.mark.parametrize("ci", range(10))
+def test_encoded_plan_matches_oracle(qs, monkeypatch, ci, tq, low, dt):
+    """The planner's encoded passes (segments, fused register blocks, the
+    diagonal forms), executed by a host model of the tile kernels, give the
+    oracle's state; tile sizes up to the whole state (tq = 0: tile = n)."""
+    from tests.tile_model import run_plan
+
+    monkeypatch.setenv("QS_TILE_LOW", str(low))
+    c = _circuits()[ci]
+    t = c.n if tq == 0 else tq
+    ops, mats = c.arrays()
+    passes, tops, pool = qs.qs_plan_export(c.n, dt, ops, mats, tile_qubits=t)
+    got = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis))
+    ref = oracle.run_circuit(c)
+    assert float(np.max(np.abs(got - ref))) <= 1e-12

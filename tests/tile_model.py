@@ -1,0 +1,156 @@
+"""A host model of what the tile kernels do with a planned pass (test
+infrastructure).  It executes the planner's encoded operations -- tile
+qubits, register segments, fused register blocks, diagonal forms -- on a
+complex128 state with numpy, so a CPU test can compare the result with the
+FP64 oracle and catch an encoding mistake without a GPU.  It follows the
+field meanings the kernels use; it does not model rounding, thread layout
+or the matrix-core blocks.
+"""
+import numpy as np
+
+TK_DENSE1, TK_DENSE2, TK_DENSEK, TK_DIAG, TK_MFMA, TK_SEG = range(6)
+SO_1Q, SO_2Q, SO_D0, SO_D1, SO_D2, SO_D1X, SO_D2X, SO_BLOCK, SO_DG = 0, 8, 20, 21, 25, 31, 39, 63, 64
+SD_GATHER = 7
+
+
+def _bit(x, pos):
+    return (x >> pos) & 1
+
+
+def _cmat(pool, moff, d):
+    v = pool[moff:moff + 2 * d * d]
+    return (v[0::2] + 1j * v[1::2]).reshape(d, d)
+
+
+def _cvec(pool, moff, d):
+    v = pool[moff:moff + 2 * d]
+    return v[0::2] + 1j * v[1::2]
+
+
+def _dense(T, tsel, esel, targets, U):
+    """Apply U (index bit j = targets[j]) to the tile elements of the
+    selected tiles whose group base passes esel (a mask over group bases)."""
+    k = len(targets)
+    E = T.shape[1]
+    e = np.arange(E)
+    tm = sum(1 << t for t in targets)
+    g0 = e[(e & tm) == 0]
+    g0 = g0[esel(g0)]
+    if g0.size == 0 or not tsel.any():
+        return
+    offs = np.array([sum(_bit(mi, j) << targets[j] for j in range(k)) for mi in range(1 << k)])
+    cols = g0[:, None] | offs[None, :]                 # (groups, D)
+    V = T[np.ix_(tsel, cols.ravel())].reshape(int(tsel.sum()), g0.size, 1 << k)
+    W = V @ U.T
+    T[np.ix_(tsel, cols.ravel())] = W.reshape(int(tsel.sum()), -1)
+
+
+def _diag(T, tsel, factor):
+    """Multiply the selected tiles elementwise by factor (ntiles x E)."""
+    T[tsel] *= factor[tsel]
+
+
+def _member(T, base, R, op, pool):
+    E = T.shape[1]
+    e = np.arange(E)
+    tsel = (base & int(op["gcm"])) == int(op["gcv"])
+    opc = int(op["rsv"]) >> 16
+    lcm, lcv = int(op["lcm"]), int(op["lcv"])
+    ctl = lambda g: (g & lcm) == lcv
+    if opc == SO_BLOCK:
+        _dense(T, tsel, lambda g: np.ones(g.size, bool), list(R), _cmat(pool, int(op["moff"]), 1 << len(R)))
+        return
+    if opc < SO_D0:
+        rb = int(op["rsv"]) & 0xFFFF
+        if opc < SO_2Q:
+            _dense(T, tsel, ctl, [R[rb & 255]], _cmat(pool, int(op["moff"]), 2))
+        else:
+            _dense(T, tsel, ctl, [R[rb & 255], R[(rb >> 8) & 255]], _cmat(pool, int(op["moff"]), 4))
+        return
+    k = int(op["k"])
+    tab = _cvec(pool, int(op["moff"]), 1 << k)
+    if opc == SO_DG:
+        idx = np.zeros((T.shape[0], E), dtype=np.int64)
+        for j in range(k):
+            q = int(op["lp"][j])
+            b = _bit(e, q)[None, :] if q >= 0 else _bit(base, int(op["p"][j]))[:, None]
+            idx |= b << j
+        f = np.where(((e & lcm) == lcv)[None, :], tab[idx], 1.0)
+        _diag(T, tsel, f)
+        return
+    kr, kt = int(op["dj"]) & 15, (int(op["dj"]) >> 4) & 15
+    ranks = [int(op["rsv"]) & 255, (int(op["rsv"]) >> 8) & 255]
+    idx = np.zeros((T.shape[0], E), dtype=np.int64)
+    for j in range(k):
+        if j < kr:
+            b = _bit(e, R[ranks[j]])[None, :]
+        elif j < kr + kt:
+            b = _bit(e, int(op["p"][j]))[None, :]
+        else:
+            b = _bit(base, int(op["p"][j]))[:, None]
+        idx |= b << j
+    f = tab[idx]
+    if SO_D1X <= opc < SO_D2X:
+        ri = (opc - SO_D1X) % 2
+        keep = _bit(e, R[ranks[0]]) == ri
+        f = np.where(keep[None, :], f, 1.0)
+    elif SO_D2X <= opc < SO_D2X + 24:
+        ri = (opc - SO_D2X) % 4
+        keep = (_bit(e, R[ranks[0]]) | (_bit(e, R[ranks[1]]) << 1)) == ri
+        f = np.where(keep[None, :], f, 1.0)
+    _diag(T, tsel, f)
+
+
+def _top(T, base, op, pool):
+    """An operation outside a segment, in the planner's original form."""
+    E = T.shape[1]
+    e = np.arange(E)
+    kind, k = int(op["kind"]), int(op["k"])
+    lcm, lcv = int(op["lcm"]), int(op["lcv"])
+    if kind == TK_DIAG:
+        tsel = (base & int(op["gcm"])) == int(op["gcv"])
+        tab = _cvec(pool, int(op["moff"]), 1 << k)
+        idx = np.zeros((T.shape[0], E), dtype=np.int64)
+        for j in range(k):
+            q = int(op["lp"][j])
+            b = _bit(e, q)[None, :] if q >= 0 else _bit(base, int(op["p"][j]))[:, None]
+            idx |= b << j
+        _diag(T, tsel, np.where(((e & lcm) == lcv)[None, :], tab[idx], 1.0))
+        return
+    if kind in (TK_DENSE1, TK_DENSE2, TK_DENSEK):
+        tsel = (base & int(op["gcm"])) == int(op["gcv"])
+        _dense(T, tsel, lambda g: (g & lcm) == lcv, [int(x) for x in op["p"][:k]], _cmat(pool, int(op["moff"]), 1 << k))
+        return
+    raise NotImplementedError(f"op kind {kind} is not modelled")
+
+
+def run_plan(n, passes, tops, pool, psi):
+    """Apply the planned passes to psi (complex128, 2^n); returns the result."""
+    psi = np.array(psi, dtype=np.complex128)
+    for P in passes:
+        m, Q = P["m"], P["Q"]
+        others = [q for q in range(n) if q not in Q]
+        e = np.arange(1 << m, dtype=np.int64)
+        local = np.zeros(1 << m, dtype=np.int64)
+        for j, q in enumerate(Q):
+            local |= _bit(e, j) << q
+        tau = np.arange(1 << (n - m), dtype=np.int64)
+        base = np.zeros(tau.size, dtype=np.int64)
+        for j, q in enumerate(others):
+            base |= _bit(tau, j) << q
+        idx = base[:, None] | local[None, :]
+        T = psi[idx]
+        ops = tops[P["op0"]:P["op0"] + P["nops"]]
+        i = 0
+        while i < len(ops):
+            op = ops[i]
+            if int(op["kind"]) == TK_SEG:
+                R = [int(x) for x in op["p"][:int(op["k"])]]
+                for mem in ops[i + 1:i + 1 + int(op["dj"])]:
+                    _member(T, base, R, mem, pool)
+                i += 1 + int(op["dj"])
+                continue
+            _top(T, base, op, pool)
+            i += 1
+        psi[idx] = T
+    return psi
