@@ -480,6 +480,96 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
         auto commute = [&](int x, int y) {
             return (nd[x] & (nd[y] | dq[y])) == 0 && (nd[y] & (nd[x] | dq[x])) == 0;
         };
+        // Consecutive diagonal ops (they commute) as one factor table: index
+        // bits = all r register bits (rank order), then the thread positions
+        // they use, then the positions outside the tile (targets or
+        // controls); at most 10 bits.  Each thread reads its 2^r factors
+        // as one contiguous slice.
+        auto diag_masks = [&](const int* gs, size_t cnt, uint32_t& tpm, uint64_t& gpm) {
+            tpm = 0;
+            gpm = 0;
+            for (size_t i = 0; i < cnt; ++i) {
+                const TileOp& t = P.ops[gs[i]];
+                for (int j = 0; j < t.k; ++j) {
+                    if (t.lp[j] >= 0) {
+                        if (!((R >> t.lp[j]) & 1)) tpm |= 1u << t.lp[j];
+                    } else {
+                        gpm |= 1ull << t.p[j];
+                    }
+                }
+                tpm |= (uint32_t)t.lcm & ~R;
+                gpm |= t.gcm;
+            }
+        };
+        auto diag_bits = [&](const int* gs, size_t cnt) {
+            uint32_t tpm;
+            uint64_t gpm;
+            diag_masks(gs, cnt, tpm, gpm);
+            return r + __builtin_popcount(tpm) + __builtin_popcountll(gpm);
+        };
+        auto diag_group = [&](const int* gs, size_t cnt) -> bool {
+            uint32_t tpm = 0;
+            uint64_t gpm = 0;
+            for (size_t i = 0; i < cnt; ++i) {
+                const TileOp& t = P.ops[gs[i]];
+                for (int j = 0; j < t.k; ++j) {
+                    if (t.lp[j] >= 0) {
+                        if (!((R >> t.lp[j]) & 1)) tpm |= 1u << t.lp[j];
+                    } else {
+                        gpm |= 1ull << t.p[j];
+                    }
+                }
+                tpm |= (uint32_t)t.lcm & ~R;
+                gpm |= t.gcm;
+            }
+            const int kt = __builtin_popcount(tpm), kg = __builtin_popcountll(gpm);
+            if (r + kt + kg > 10) return false;
+            int tpos[32], gpos[64];
+            for (int i = 0, q = 0; q < 32; ++q)
+                if ((tpm >> q) & 1) tpos[i++] = q;
+            for (int i = 0, q = 0; q < 64; ++q)
+                if ((gpm >> q) & 1) gpos[i++] = q;
+            const int K = r + kt + kg, D = 1 << K;
+            size_t off = pool.size();
+            if (off & 1) pool.push_back(0.0), ++off; // 16-byte aligned factors
+            pool.resize(off + 2 * (size_t)D);
+            for (int x = 0; x < D; ++x) {
+                uint32_t e = 0; // tile-local bits
+                uint64_t gb = 0; // bits outside the tile
+                for (int b = 0; b < r; ++b)
+                    if ((x >> b) & 1) e |= 1u << h.p[b];
+                for (int b = 0; b < kt; ++b)
+                    if ((x >> (r + b)) & 1) e |= 1u << tpos[b];
+                for (int b = 0; b < kg; ++b)
+                    if ((x >> (r + kt + b)) & 1) gb |= 1ull << gpos[b];
+                cd f = 1.0;
+                for (size_t i = 0; i < cnt; ++i) {
+                    const TileOp& t = P.ops[gs[i]];
+                    if ((e & (uint32_t)t.lcm) != (uint32_t)t.lcv || (gb & t.gcm) != t.gcv) continue;
+                    int idx = 0;
+                    for (int j = 0; j < t.k; ++j) {
+                        const int bit = t.lp[j] >= 0 ? (int)((e >> t.lp[j]) & 1) : (int)((gb >> t.p[j]) & 1);
+                        idx |= bit << j;
+                    }
+                    f *= cd(pool[t.moff + 2 * idx], pool[t.moff + 2 * idx + 1]);
+                }
+                pool[off + 2 * x] = f.real();
+                pool[off + 2 * x + 1] = f.imag();
+            }
+            TileOp t;
+            std::memset(&t, 0, sizeof t);
+            t.kind = TK_DIAG;
+            t.k = K;
+            t.lcm = tpm; // thread positions of the index
+            t.lcv = gpm; // positions outside the tile
+            t.moff = off;
+            t.dj = kt | (kg << 8);
+            t.rsv = SO_DGROUP << 16;
+            out.push_back(t);
+            osrc.push_back(-1);
+            for (size_t i = 0; i < cnt; ++i) ord.push_back(P.src[gs[i]]);
+            return true;
+        };
         auto op_cost = [&](int g) {
             const TileOp& t = P.ops[g];
             return t.kind == TK_DENSE1 ? 20.0 : (t.kind == TK_DENSE2 ? 40.0 : 8.0);
@@ -513,7 +603,20 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
             } else {
                 for (int g : run) emit_member(g);
             }
-            for (int g : pend) emit_member(g);
+            for (size_t i = 0; i < pend.size();) {
+                // the longest run of diagonal ops from i whose factor table
+                // fits (at most 10 index bits)
+                size_t j = i;
+                while (j < pend.size() && P.ops[pend[j]].kind == TK_DIAG && diag_bits(pend.data() + i, j + 1 - i) <= 10)
+                    ++j;
+                if (j - i >= 2) {
+                    diag_group(pend.data() + i, j - i);
+                    i = j;
+                    continue;
+                }
+                emit_member(pend[i]);
+                ++i;
+            }
             run.clear();
             pend.clear();
         };

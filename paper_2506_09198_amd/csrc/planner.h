@@ -44,6 +44,7 @@ enum {
     SO_D2X = 39,  // 24: 4 pair + ri
     SO_BLOCK = 63, // a fused 2^r x 2^r block on all register bits (row-major complex)
     SO_DG = 64,   // gather
+    SO_DGROUP = 65, // several diagonal ops as one factor table (see the planner)
 };
 static_assert(SO_D2X + 4 * 6 <= SO_BLOCK, "segment opcode ranges overlap");
 

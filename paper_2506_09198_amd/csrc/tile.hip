@@ -377,6 +377,25 @@ __device__ __forceinline__ void seg_op(double2 (&reg)[NR], const uint32_t (&roff
         diag_gather<NR>(reg, roff, rmask, eb, d, base, u);
         return;
     }
+    if (opc == SO_DGROUP) {
+        // factor table index: register bits, then the thread positions in
+        // lcm, then the positions outside the tile in lcv
+        const uint32_t tpm = (uint32_t)d.lcm;
+        const uint64_t gpm = d.lcv;
+        uint32_t ti = 0, gi = 0;
+        int b = 0;
+        for (uint32_t m = tpm; m; m &= m - 1) ti |= ((eb >> __builtin_ctz(m)) & 1) << b++;
+        b = 0;
+        for (uint64_t m = gpm; m; m &= m - 1) gi |= (uint32_t)((base >> __builtin_ctzll(m)) & 1) << b++;
+        const int kt = d.dj & 255;
+        const double2* f = (const double2*)u + ((((uint64_t)gi << kt) | ti) << RR);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const double2 fj = f[j];
+            reg[j] = cmul<double2, double>(fj.x, fj.y, reg[j]);
+        }
+        return;
+    }
     double2 F[4];
     diag_factors(F, d, base, eb, u);
     switch (opc) {

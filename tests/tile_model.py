@@ -9,7 +9,7 @@ or the matrix-core blocks.
 import numpy as np
 
 TK_DENSE1, TK_DENSE2, TK_DENSEK, TK_DIAG, TK_MFMA, TK_SEG = range(6)
-SO_1Q, SO_2Q, SO_D0, SO_D1, SO_D2, SO_D1X, SO_D2X, SO_BLOCK, SO_DG = 0, 8, 20, 21, 25, 31, 39, 63, 64
+SO_1Q, SO_2Q, SO_D0, SO_D1, SO_D2, SO_D1X, SO_D2X, SO_BLOCK, SO_DG, SO_DGROUP = 0, 8, 20, 21, 25, 31, 39, 63, 64, 65
 SD_GATHER = 7
 
 
@@ -69,6 +69,18 @@ def _member(T, base, R, op, pool):
         return
     k = int(op["k"])
     tab = _cvec(pool, int(op["moff"]), 1 << k)
+    if opc == SO_DGROUP:
+        tp = [q for q in range(32) if (int(op["lcm"]) >> q) & 1]
+        gp = [q for q in range(64) if (int(op["lcv"]) >> q) & 1]
+        idx = np.zeros((T.shape[0], E), dtype=np.int64)
+        for b, q in enumerate(R):
+            idx |= _bit(e, q)[None, :] << b
+        for b, q in enumerate(tp):
+            idx |= _bit(e, q)[None, :] << (len(R) + b)
+        for b, q in enumerate(gp):
+            idx |= _bit(base, q)[:, None] << (len(R) + len(tp) + b)
+        _diag(T, tsel, tab[idx])
+        return
     if opc == SO_DG:
         idx = np.zeros((T.shape[0], E), dtype=np.int64)
         for j in range(k):
