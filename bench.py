@@ -9,9 +9,10 @@ Workloads (``--workload``), each printing ONE JSON line:
   uncontrolled and once with one control: 118 gates, one launch each, state
   resident in HBM.  Value: amplitude-updates/s.
 - ``circuits``: 32-qubit random chain circuit (depth 20) and full QFT of a
-  random basis state, complex64 in tile passes with 5-qubit fused blocks on
-  matrix cores, beside complex128 tile passes and complex128 gate by gate.
-  Value: credited amplitude-updates/s of the fused complex64 runs.
+  random basis state, complex64 in tile passes (register segments with fused
+  register blocks), beside complex64 with 5-qubit fused blocks on matrix
+  cores, complex128 tile passes and complex128 gate by gate.  Value:
+  credited amplitude-updates/s of the complex64 tile passes.
 - ``batch``: 4096 circuits (n log-uniform in [10, 22]; random chain / QFT /
   Grover) in one batch: fused complex64 against plain per-gate complex128 on
   8 streams and on 1 stream.  Value: circuits/s of the fused complex64 batch.
@@ -54,6 +55,9 @@ def _args():
     p.add_argument("--no-baselines", action="store_true",
                    help="circuits/batch: skip the per-gate complex128 comparison runs")
     p.add_argument("--qps-sweep", action="store_true", help="serve: also run 0.3x, 0.5x and 1.0x of saturation")
+    p.add_argument("--big-blocks", type=int, default=256,
+                   help="serve: workgroup cap of the large circuit's passes (0 = library default), which "
+                        "leaves compute units to the request stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-n", type=int, default=0, help="qubits of the oracle sample (0 = workload default)")
     p.add_argument("--copy-calibration", action="store_true",
@@ -265,7 +269,8 @@ def run_circuits(a, qs, torch, W):
             "qft": W.qft(n, int(np.random.default_rng(6).integers(1 << n)))}
     arrs = {k: c.arrays() for k, c in work.items()}
     upd = {k: _updates(n, arrs[k][0]) for k in work}
-    variants = [("c64_fused5", qs.QS_C64, 0, 5, a.steps, a.warmup), ("c64_tiles", qs.QS_C64, 0, 0, 1, 1),
+    head = "c64_tiles"
+    variants = [(head, qs.QS_C64, 0, 0, a.steps, a.warmup), ("c64_mfma5", qs.QS_C64, 0, 5, 1, 1),
                 ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
     if not a.no_baselines:
         variants.append(("c128_pergate", qs.QS_C128, 1, 0, 1, 0))
@@ -281,7 +286,7 @@ def run_circuits(a, qs, torch, W):
                 s.init_basis(c.init_basis)
                 s.run(ops, mats, mode=mode, fuse_k=fk)
             s.sync()
-            if name == "c64_fused5":
+            if name == head:
                 qs.qs_trace_enable(s.h, True)
             t0 = time.perf_counter()
             for _ in range(steps):
@@ -289,23 +294,24 @@ def run_circuits(a, qs, torch, W):
                 s.run(ops, mats, mode=mode, fuse_k=fk)
             s.sync()
             el = (time.perf_counter() - t0) / steps
-            if name == "c64_fused5":
+            if name == head:
                 traces[k] = qs.qs_trace_read(s.h, 1 << 20)
                 qs.qs_trace_enable(s.h, False)
             s.close()
             res.setdefault(name, {})[k] = {"ms": el * 1e3, "amp_updates_per_s": upd[k] / el,
                                            "gates": len(ops), "passes": None if plan is None else plan[0]}
             _log(f"circuits {name} {k}: {el * 1e3:.1f} ms")
-            if name in ("c64_fused5", "c128_tiles"):
+            if name in (head, "c64_mfma5", "c128_tiles"):
                 states.setdefault(k, {})[name] = psi
             else:
                 del psi
         torch.cuda.synchronize()
         if name == "c128_tiles":  # both precisions of each circuit are resident: compare them
             for k in work:
-                f, dn, err = _fidelity(torch, states[k]["c128_tiles"], states[k]["c64_fused5"])
-                res["c64_fused5"][k].update({"fidelity_vs_c128": f, "norm2_minus_1": dn, "max_abs_err_vs_c128": err})
-                del states[k]["c64_fused5"]
+                for v in (head, "c64_mfma5"):
+                    f, dn, err = _fidelity(torch, states[k]["c128_tiles"], states[k][v])
+                    res[v][k].update({"fidelity_vs_c128": f, "norm2_minus_1": dn, "max_abs_err_vs_c128": err})
+                    del states[k][v]
             if work["qft"].name.startswith("qft"):  # c128 QFT against its closed form on samples
                 x, N = work["qft"].init_basis, 1 << n
                 y = np.random.default_rng(7).integers(0, N, size=1 << 16, dtype=np.int64)
@@ -315,18 +321,19 @@ def run_circuits(a, qs, torch, W):
             states.clear()
             torch.cuda.empty_cache()
     tot = sum(upd.values())
-    ms64 = sum(r["ms"] for r in res["c64_fused5"].values())
+    ms64 = sum(r["ms"] for r in res[head].values())
     kinds = _kinds(qs, np.concatenate(list(traces.values())))
-    out = _header(a, "amplitude-updates/s", tot / (ms64 * 1e-3), "amp-updates/s", ms64, "f32",
+    out = _header(a, "amplitude-updates/s", tot / (ms64 * 1e-3), "amp-updates/s", ms64, "f64",
                   "synthetic (seeded chain circuit of sqrt(X)/sqrt(Y)/sqrt(W) + CZ layers; QFT of a seeded basis "
                   "state)",
                   {"workload": f"n={n}: depth-20 chain circuit ({len(arrs['rqc_d20'][0])} gates) + QFT "
-                               f"({len(arrs['qft'][0])} gates); complex64 tile passes with 5-qubit fused blocks",
-                   "n": n, "state_bytes_c64": 8 << n, "state_bytes_c128": 16 << n})
+                               f"({len(arrs['qft'][0])} gates); complex64 state in tile passes with fused register "
+                               "blocks (FP64 arithmetic)",
+                   "n": n, "state": "c64", "state_bytes_c64": 8 << n, "state_bytes_c128": 16 << n})
     for name in res:
         ms = sum(r["ms"] for r in res[name].values())
         res[name]["total_ms"] = ms
-        res[name]["speedup_of_c64_fused5"] = ms / ms64
+        res[name]["time_vs_head"] = ms / ms64
     out.update({"variants": res, "roofline": _roofline(kinds),
                 "kernels": {k: {"launches": d["launches"], "avg_ms": round(d["avg_ms"], 4), "gbs": round(d["gbs"], 1)}
                             for k, d in kinds.items()}})
@@ -415,10 +422,11 @@ def run_batch(a, qs, torch, W):
                                                               res["c128_pergate_8streams"]["circuits_per_s"])
     v = res["c64_fused"]
     ns = np.array([c.n for c in circs])
-    out = _header(a, "batched circuits/s", v["circuits_per_s"], "circuits/s", v["end_to_end_ms"], "f32",
+    out = _header(a, "batched circuits/s", v["circuits_per_s"], "circuits/s", v["end_to_end_ms"], "f64",
                   "synthetic (seeded mix of chain circuits, QFTs and Grover searches)",
                   {"workload": f"{count} circuits, n log-uniform in [10,22] (mean {ns.mean():.1f}), one third each "
-                               "chain circuit (depth 20-200), QFT, Grover (<=200 gates); complex64 fused batch",
+                               "chain circuit (depth 20-200), QFT, Grover (<=200 gates); complex64 states, FP64 "
+                               "arithmetic, fused batch",
                    "circuits": count, "gates": int(sum(len(x[1]) for x in arrs))})
     # aggregate roofline: algorithmic bytes of every pass of every circuit over the batch's device time
     alg = 0
@@ -443,7 +451,7 @@ def _serve_stream(qs, circs, arrivals, dt, budget=0, hook=None):
     srv = qs.qs_server_create(dtype=dt, hbm_budget=budget)
     done, ids = {}, []
     try:
-        t0 = time.perf_counter()
+        t0 = t_log = time.perf_counter()
         i = 0
         while len(done) < len(circs):
             now = time.perf_counter() - t0
@@ -458,6 +466,9 @@ def _serve_stream(qs, circs, arrivals, dt, budget=0, hook=None):
             if i == len(circs) and time.perf_counter() - t0 > arrivals[-1] + 900:
                 raise RuntimeError("serving did not drain")
             time.sleep(0.0001)
+            if time.perf_counter() - t_log > 10:
+                t_log = time.perf_counter()
+                _log(f"serve: {len(done)}/{len(circs)} done, {i} submitted")
         st = qs.qs_server_get_stats(srv)
     finally:
         qs.qs_server_destroy(srv)
@@ -475,8 +486,8 @@ class _BigJob:
     run forward and then inverted (echo), and the cycle is enqueued again
     whenever the previous one has finished, until stop()."""
 
-    def __init__(self, qs, torch, W, n):
-        self.qs, self.torch, self.n = qs, torch, n
+    def __init__(self, qs, torch, W, n, fuse_k=0, max_blocks=0):
+        self.qs, self.torch, self.n, self.fuse_k, self.max_blocks = qs, torch, n, fuse_k, max_blocks
         c = W.rqc_chain(n, 24, 9)
         self.ops, self.mats = c.arrays()
         self.iops, self.imats = c.inverse().arrays()
@@ -491,9 +502,9 @@ class _BigJob:
     def enqueue(self):
         ev = [self.torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record(self.side)
-        self.s.run(self.ops, self.mats, mode=0, fuse_k=5)
+        self.s.run(self.ops, self.mats, mode=0, fuse_k=self.fuse_k, max_blocks=self.max_blocks)
         ev[1].record(self.side)
-        self.s.run(self.iops, self.imats, mode=0, fuse_k=5)
+        self.s.run(self.iops, self.imats, mode=0, fuse_k=self.fuse_k, max_blocks=self.max_blocks)
         ev[2].record(self.side)
         self.cycles.append(ev)
 
@@ -509,7 +520,8 @@ class _BigJob:
         ec = [c[1].elapsed_time(c[2]) for c in self.cycles]
         out = {"n": self.n, "dtype": "c64", "gates": len(self.ops), "cycles": len(self.cycles),
                "forward_ms": fw, "echo_ms": ec, "echo_prob_0": abs(a0) ** 2, "norm2_minus_1": self.s.norm() - 1.0,
-               "passes": qs.qs_plan_circuit(self.n, qs.QS_C64, self.ops, self.mats, mode=0, fuse_k=5)[0]}
+               "fuse_k": self.fuse_k, "max_blocks": self.max_blocks,
+               "passes": qs.qs_plan_circuit(self.n, qs.QS_C64, self.ops, self.mats, mode=0, fuse_k=self.fuse_k)[0]}
         out["pass_gbs_algorithmic"] = out["passes"] * (16 << self.n) / (float(np.median(fw)) * 1e-3) / 1e9
         self.s.close()
         del self.psi
@@ -519,17 +531,17 @@ class _BigJob:
 
 def run_serve(a, qs, torch, W):
     nb = 34 if a.n == 0 else a.n
-    count = a.count or 200
+    count = a.count or 120
     circs = W.circuit_mix(count, 8, n_lo=8, n_hi=28)
     _log(f"serve: {count} requests, {sum(len(c) for c in circs)} gates")
     dt = qs.QS_C64
-    sat_n = min(count, 100)
+    sat_n = min(count, 60)
     # saturated throughput with nothing alongside: the first requests all at once
     alone = _serve_stream(qs, circs[:sat_n], np.zeros(sat_n), dt)
     _log(f"serve saturated, alone: {alone['circuits_per_s']:.1f} circuits/s")
     big, hook, sat = None, None, alone
     if nb > 0:
-        big = _BigJob(qs, torch, W, nb)
+        big = _BigJob(qs, torch, W, nb, max_blocks=a.big_blocks)
         hook = big.hook
         sat = _serve_stream(qs, circs[:sat_n], np.zeros(sat_n), dt, hook=hook)
         _log(f"serve saturated, beside n={nb}: {sat['circuits_per_s']:.1f} circuits/s")
@@ -545,12 +557,12 @@ def run_serve(a, qs, torch, W):
     if big is not None:
         big = big.stop()
     ns = np.array([c.n for c in circs])
-    out = _header(a, "served circuits/s", main["circuits_per_s"], "circuits/s", None, "f32",
+    out = _header(a, "served circuits/s", main["circuits_per_s"], "circuits/s", None, "f64",
                   "synthetic (seeded Poisson arrivals; seeded mix of chain circuits, QFTs and Grover searches)",
                   {"workload": f"{count} requests, n log-uniform in [8,28] (mean {ns.mean():.1f}), complex64, "
                                f"Poisson at 0.7x the saturated rate" +
-                               (f", beside an n={nb} complex64 depth-24 chain circuit with 5-qubit fused blocks "
-                                "run forward and back for the whole stream" if nb else ""),
+                               (f", beside an n={nb} complex64 depth-24 chain circuit in tile passes with fused "
+                                "register blocks, run forward and back for the whole stream" if nb else ""),
                    "requests": count, "qps": qps})
     out.update({"latency_ms": {"p50": main["p50_ms"], "p99": main["p99_ms"]}, "stream": main,
                 "saturated": sat, "saturated_alone": alone, "big_circuit": big, "qps_sweep": sweep or None})

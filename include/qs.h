@@ -150,7 +150,11 @@ typedef struct {
     int32_t mode;        /* 0 = auto (fused tile passes), 1 = one launch per gate */
     int32_t fuse_k;      /* max qubits of a fused dense block; 0 = default */
     int32_t tile_qubits; /* qubits held in LDS per tile; 0 = default */
-    int32_t rsv[5];
+    int32_t max_blocks;  /* cap on the workgroups of each tile-pass launch (they stride over
+                            the tiles); 0 = default (2048).  A lower cap leaves compute units
+                            to other streams, e.g. a serving loop beside a long run, at the
+                            cost of this run's speed */
+    int32_t rsv[4];
 } qs_run_opts;
 
 /* Apply a whole circuit (ops[0..n_ops), matrices in mats[0..n_mats)) in

@@ -72,7 +72,7 @@ class _ServerStats(ctypes.Structure):
 
 class _RunOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
-                ("rsv", ctypes.c_int32 * 5)]
+                ("max_blocks", ctypes.c_int32), ("rsv", ctypes.c_int32 * 4)]
 
 
 def _load():
@@ -254,12 +254,12 @@ def qs_apply_fused(s: int, targets, U, ctrl_mask=0, ctrl_vals=None):
 
 
 def qs_run_circuit(s: int, ops: np.ndarray, mats: np.ndarray, mode: int = 0, fuse_k: int = 0,
-                   tile_qubits: int = 0):
+                   tile_qubits: int = 0, max_blocks: int = 0):
     ops = np.ascontiguousarray(ops)
     if ops.dtype.itemsize != 64:
         raise ValueError("ops must be 64-byte records (workloads.OP_DTYPE)")
     mats = np.ascontiguousarray(mats, dtype=np.float64)
-    o = _RunOpts(mode, fuse_k, tile_qubits)
+    o = _RunOpts(mode, fuse_k, tile_qubits, max_blocks)
     _check(lib.qs_run_circuit(ctypes.c_void_p(s), ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
                               mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o)))
 

@@ -161,6 +161,9 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     std::vector<TileOp> bops;
     std::vector<double> bmats;
     int persist_m = 0, stream_m = 0;
+    // classes and tile sizes first (the first circuit of a class fixes its
+    // tile size), then the plans on host threads, then one concatenation
+    std::vector<PlanOpts> popts(count);
     for (int i = 0; i < count; ++i) {
         const qs_circuit& c = circuits[i];
         std::memset(&bc[i], 0, sizeof(BatchCirc));
@@ -168,7 +171,7 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         bc[i].basis = c.init_basis;
         bc[i].n = c.n;
         if (b->mode == 1) continue;
-        PlanOpts po;
+        PlanOpts& po = popts[i];
         st = plan_opts_for(b->dt, c.ops, c.n_ops, o.fuse_k, o.tile_qubits, po);
         if (st != QS_OK) {
             release(b);
@@ -185,9 +188,17 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
             if (stream_m == 0) stream_m = std::min(po.m, 13);
             po.m = stream_m;
         }
-        std::vector<PlanPass> passes;
-        std::vector<double> pool;
-        if (c.n_ops > 0) plan_circuit(c.n, c.ops, c.n_ops, c.mats, po, passes, pool);
+    }
+    std::vector<std::vector<PlanPass>> plans(b->mode == 0 ? count : 0);
+    std::vector<std::vector<double>> pools(b->mode == 0 ? count : 0);
+    if (b->mode == 0)
+        parallel_for(count, [&](int i) {
+            const qs_circuit& c = circuits[i];
+            if (c.n_ops > 0) plan_circuit(c.n, c.ops, c.n_ops, c.mats, popts[i], plans[i], pools[i]);
+        });
+    for (int i = 0; i < count && b->mode == 0; ++i) {
+        std::vector<PlanPass>& passes = plans[i];
+        std::vector<double>& pool = pools[i];
         const size_t pool_base = bmats.size() + (bmats.size() & 1); // keep 16-byte alignment
         bmats.resize(pool_base);
         bmats.insert(bmats.end(), pool.begin(), pool.end());
@@ -213,6 +224,8 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
             bpass.push_back(d);
             b->stats.passes += 1;
         }
+        std::vector<PlanPass>().swap(passes);
+        std::vector<double>().swap(pool);
     }
     // per-gate mode: stage every circuit's matrices (dense k > 2 gates read them)
     std::vector<size_t> gate_pool_base(count, 0);

@@ -63,6 +63,7 @@ extern "C" qs_status qs_run_circuit(qs_state s, const qs_op* ops, int64_t n_ops,
     qs_run_opts o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
+    if (o.max_blocks < 0) return set_err(QS_ERR_ARG, "max_blocks=%d < 0", o.max_blocks);
     if (o.mode == 1) return run_per_gate(s, ops, n_ops, mats, n_mats);
     if (o.mode != 0) return set_err(QS_ERR_ARG, "unknown run mode %d", o.mode);
     return run_planned(s, ops, n_ops, mats, n_mats, o);

@@ -47,8 +47,9 @@ static bool op_local_bits(const TileOp& t, uint32_t* bits)
     return true;
 }
 
-// Full 2^K x 2^K matrix (column-major product order: G = op * G) of one op in
-// the block whose qubits are the local positions bq[0..K).
+// G = op * G for a 2^K x 2^K matrix G (row-major) on the block whose qubits
+// are the tile positions bq[0..K): the op's matrix acts on each column of G
+// directly, so a k-qubit op costs 2^K * 2^K * 2^k multiply-adds.
 static void embed_op(const TileOp& t, const std::vector<double>& pool, const int* bq, int K, std::vector<cd>& G)
 {
     const int D = 1 << K;
@@ -61,41 +62,50 @@ static void embed_op(const TileOp& t, const std::vector<double>& pool, const int
             cbm |= 1u << bidx[q];
             if ((t.lcv >> q) & 1) cbv |= 1u << bidx[q];
         }
-    int tb[6];
     const bool diag = t.kind == TK_DIAG;
-    for (int j = 0; j < t.k; ++j) tb[j] = bidx[diag ? t.lp[j] : t.p[j]];
+    int tb[6];
+    uint32_t tmask = 0;
+    for (int j = 0; j < t.k; ++j) {
+        tb[j] = bidx[diag ? t.lp[j] : t.p[j]];
+        tmask |= 1u << tb[j];
+    }
     const int dk = 1 << t.k;
     const double* U = pool.data() + t.moff;
-    std::vector<cd> H((size_t)D * D, cd(0, 0));
-    for (int c = 0; c < D; ++c) {
-        if (((uint32_t)c & cbm) != cbv) {
-            H[(size_t)c * D + c] = 1.0;
-            continue;
+    auto row_of = [&](uint32_t r0, int m) {
+        uint32_t r = r0;
+        for (int j = 0; j < t.k; ++j)
+            if ((m >> j) & 1) r |= 1u << tb[j];
+        return r;
+    };
+    if (diag) {
+        for (int r = 0; r < D; ++r) {
+            if (((uint32_t)r & cbm) != cbv) continue;
+            int mi = 0;
+            for (int j = 0; j < t.k; ++j) mi |= (int)((r >> tb[j]) & 1) << j;
+            const cd f(U[2 * mi], U[2 * mi + 1]);
+            cd* row = G.data() + (size_t)r * D;
+            for (int c = 0; c < D; ++c) row[c] *= f;
         }
-        int mi = 0, base = c;
-        for (int j = 0; j < t.k; ++j) {
-            mi |= ((c >> tb[j]) & 1) << j;
-            base &= ~(1 << tb[j]);
-        }
-        if (diag) {
-            H[(size_t)c * D + c] = cd(U[2 * mi], U[2 * mi + 1]);
-            continue;
-        }
-        for (int r = 0; r < dk; ++r) {
-            int row = base;
-            for (int j = 0; j < t.k; ++j)
-                if ((r >> j) & 1) row |= 1 << tb[j];
-            H[(size_t)row * D + c] = cd(U[2 * (r * dk + mi)], U[2 * (r * dk + mi) + 1]);
+        return;
+    }
+    thread_local std::vector<cd> u;
+    u.resize((size_t)dk * dk);
+    for (int i = 0; i < dk * dk; ++i) u[i] = cd(U[2 * i], U[2 * i + 1]);
+    cd v[64], w[64];
+    for (uint32_t r0 = 0; r0 < (uint32_t)D; ++r0) {
+        if ((r0 & tmask) != 0 || (r0 & cbm) != cbv) continue;
+        uint32_t rows[64];
+        for (int m = 0; m < dk; ++m) rows[m] = row_of(r0, m);
+        for (int c = 0; c < D; ++c) {
+            for (int m = 0; m < dk; ++m) v[m] = G[(size_t)rows[m] * D + c];
+            for (int m = 0; m < dk; ++m) {
+                cd acc = 0;
+                for (int q = 0; q < dk; ++q) acc += u[m * dk + q] * v[q];
+                w[m] = acc;
+            }
+            for (int m = 0; m < dk; ++m) G[(size_t)rows[m] * D + c] = w[m];
         }
     }
-    std::vector<cd> out((size_t)D * D, cd(0, 0));
-    for (int r = 0; r < D; ++r)
-        for (int k2 = 0; k2 < D; ++k2) {
-            const cd h = H[(size_t)r * D + k2];
-            if (h == cd(0, 0)) continue;
-            for (int c = 0; c < D; ++c) out[(size_t)r * D + c] += h * G[(size_t)k2 * D + c];
-        }
-    G.swap(out);
 }
 
 static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_dense)
@@ -533,28 +543,52 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
             size_t off = pool.size();
             if (off & 1) pool.push_back(0.0), ++off; // 16-byte aligned factors
             pool.resize(off + 2 * (size_t)D);
-            for (int x = 0; x < D; ++x) {
-                uint32_t e = 0; // tile-local bits
-                uint64_t gb = 0; // bits outside the tile
-                for (int b = 0; b < r; ++b)
-                    if ((x >> b) & 1) e |= 1u << h.p[b];
-                for (int b = 0; b < kt; ++b)
-                    if ((x >> (r + b)) & 1) e |= 1u << tpos[b];
-                for (int b = 0; b < kg; ++b)
-                    if ((x >> (r + kt + b)) & 1) gb |= 1ull << gpos[b];
-                cd f = 1.0;
-                for (size_t i = 0; i < cnt; ++i) {
-                    const TileOp& t = P.ops[gs[i]];
-                    if ((e & (uint32_t)t.lcm) != (uint32_t)t.lcv || (gb & t.gcm) != t.gcv) continue;
-                    int idx = 0;
-                    for (int j = 0; j < t.k; ++j) {
-                        const int bit = t.lp[j] >= 0 ? (int)((e >> t.lp[j]) & 1) : (int)((gb >> t.p[j]) & 1);
-                        idx |= bit << j;
+            // each op's targets and controls as bit positions of the index x
+            struct Xop {
+                int tb[6];
+                int k;
+                uint32_t cm, cv;
+                const double* T;
+            };
+            std::vector<Xop> xo(cnt);
+            int xbit_local[32], xbit_glob[64];
+            for (int q = 0; q < 32; ++q) xbit_local[q] = -1;
+            for (int q = 0; q < 64; ++q) xbit_glob[q] = -1;
+            for (int b = 0; b < r; ++b) xbit_local[h.p[b]] = b;
+            for (int b = 0; b < kt; ++b) xbit_local[tpos[b]] = r + b;
+            for (int b = 0; b < kg; ++b) xbit_glob[gpos[b]] = r + kt + b;
+            for (size_t i = 0; i < cnt; ++i) {
+                const TileOp& t = P.ops[gs[i]];
+                Xop& x = xo[i];
+                x.k = t.k;
+                x.cm = x.cv = 0;
+                for (int j = 0; j < t.k; ++j) x.tb[j] = t.lp[j] >= 0 ? xbit_local[t.lp[j]] : xbit_glob[t.p[j]];
+                for (int q = 0; q < 32; ++q)
+                    if (((uint32_t)t.lcm >> q) & 1) {
+                        x.cm |= 1u << xbit_local[q];
+                        if (((uint32_t)t.lcv >> q) & 1) x.cv |= 1u << xbit_local[q];
                     }
-                    f *= cd(pool[t.moff + 2 * idx], pool[t.moff + 2 * idx + 1]);
+                for (int q = 0; q < 64; ++q)
+                    if ((t.gcm >> q) & 1) {
+                        x.cm |= 1u << xbit_glob[q];
+                        if ((t.gcv >> q) & 1) x.cv |= 1u << xbit_glob[q];
+                    }
+                x.T = nullptr;
+            }
+            for (int x = 0; x < D; ++x) {
+                double fr = 1.0, fi = 0.0;
+                for (size_t i = 0; i < cnt; ++i) {
+                    const Xop& o = xo[i];
+                    if (((uint32_t)x & o.cm) != o.cv) continue;
+                    int idx = 0;
+                    for (int j = 0; j < o.k; ++j) idx |= ((x >> o.tb[j]) & 1) << j;
+                    const double* T = pool.data() + P.ops[gs[i]].moff + 2 * idx;
+                    const double nr = fr * T[0] - fi * T[1], ni = fr * T[1] + fi * T[0];
+                    fr = nr;
+                    fi = ni;
                 }
-                pool[off + 2 * x] = f.real();
-                pool[off + 2 * x + 1] = f.imag();
+                pool[off + 2 * x] = fr;
+                pool[off + 2 * x + 1] = fi;
             }
             TileOp t;
             std::memset(&t, 0, sizeof t);
@@ -607,8 +641,17 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 // the longest run of diagonal ops from i whose factor table
                 // fits (at most 10 index bits)
                 size_t j = i;
-                while (j < pend.size() && P.ops[pend[j]].kind == TK_DIAG && diag_bits(pend.data() + i, j + 1 - i) <= 10)
+                uint32_t tpm = 0;
+                uint64_t gpm = 0;
+                while (j < pend.size() && P.ops[pend[j]].kind == TK_DIAG) {
+                    uint32_t t2;
+                    uint64_t g2;
+                    diag_masks(pend.data() + j, 1, t2, g2);
+                    if (r + __builtin_popcount(tpm | t2) + __builtin_popcountll(gpm | g2) > 10) break;
+                    tpm |= t2;
+                    gpm |= g2;
                     ++j;
+                }
                 if (j - i >= 2) {
                     diag_group(pend.data() + i, j - i);
                     i = j;
@@ -914,7 +957,7 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
             s, rec,
             [&](int* kind) {
                 *kind = QS_K_TILE;
-                return launch_tile_pass(s->d, s->dt, s->n, p, pd, dmats, s->st);
+                return launch_tile_pass(s->d, s->dt, s->n, p, pd, dmats, o.max_blocks, s->st);
             },
             "tile pass launch");
         if (st != QS_OK) return st;

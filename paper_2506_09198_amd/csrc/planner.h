@@ -2,7 +2,10 @@
 // one write of the state per pass).  Not part of the public ABI.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -120,6 +123,26 @@ struct PlanOpts {
 void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po,
                   std::vector<PlanPass>& passes, std::vector<double>& mats_out);
 
+// Run fn(i) for i in [0, n) on up to 16 host threads (independent items,
+// e.g. the circuits of a batch, which are planned one per call).
+template <typename F>
+void parallel_for(int n, F fn)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int nt = (int)std::min<unsigned>(std::min(hw, 16u), (unsigned)std::max(1, n / 4));
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&]() {
+            for (int i; (i = next.fetch_add(1)) < n;) fn(i);
+        });
+    for (auto& x : th) x.join();
+}
+
 // ---------------------------------------------------------------- batches
 
 // Pass descriptor in device memory (persistent batch kernels read it there).
@@ -195,8 +218,10 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
                       const qs_run_opts& o);
 
 // Tile pass launcher (tile.hip).  `dops` and `dmats` are device copies.
+// max_blocks caps the launch's grid (0: the default cap); the blocks stride
+// over the tiles.
 hipError_t launch_tile_pass(void* psi, int dt, int n, const PlanPass& pass, const TileOp* dops,
-                            const void* dmats, hipStream_t st);
+                            const void* dmats, int max_blocks, hipStream_t st);
 size_t tile_lds_bytes(int dt, int m, int L);
 
 } // namespace qs

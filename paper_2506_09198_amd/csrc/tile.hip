@@ -1088,7 +1088,7 @@ static hipError_t launch_persist_m(char* arena, const BatchCirc* circs, const in
 
 template <typename R, int M>
 hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, const void* dmats,
-                    hipStream_t st)
+                    int max_blocks, hipStream_t st)
 {
     using V = typename CT<R>::V;
     QList ql;
@@ -1116,8 +1116,9 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
         attr_set = true;
     }
     if (lds > 163840) return hipErrorInvalidValue;
-    static int cap = env_int("QS_TILE_GRID_CAP", 256 * 8);
-    const unsigned g = (unsigned)(ntiles < (uint64_t)cap ? ntiles : (uint64_t)cap);
+    static int cap_env = env_int("QS_TILE_GRID_CAP", 256 * 8);
+    const uint64_t cap = max_blocks > 0 ? (uint64_t)max_blocks : (uint64_t)cap_env;
+    const unsigned g = (unsigned)(ntiles < cap ? ntiles : cap);
     // non-temporal when each contiguous run covers whole 128-byte lines
     const int line_bits = sizeof(R) == 8 ? 3 : 4;
     static int nt_env = env_int("QS_NT", 1);
@@ -1135,11 +1136,11 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
 
 template <typename R>
 hipError_t launch_r(void* psi, int n, const PlanPass& pass, const TileOp* dops, const void* dmats,
-                    hipStream_t st)
+                    int max_blocks, hipStream_t st)
 {
     switch (pass.m) {
 #define QS_TILE_CASE(MM) \
-    case MM: return launch_m<R, MM>(psi, n, pass, dops, dmats, st);
+    case MM: return launch_m<R, MM>(psi, n, pass, dops, dmats, max_blocks, st);
         QS_TILE_CASE(1) QS_TILE_CASE(2) QS_TILE_CASE(3) QS_TILE_CASE(4) QS_TILE_CASE(5) QS_TILE_CASE(6)
         QS_TILE_CASE(7) QS_TILE_CASE(8) QS_TILE_CASE(9) QS_TILE_CASE(10) QS_TILE_CASE(11) QS_TILE_CASE(12)
         QS_TILE_CASE(13)
@@ -1297,11 +1298,11 @@ hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nent
 }
 
 hipError_t launch_tile_pass(void* psi, int dt, int n, const PlanPass& pass, const TileOp* dops,
-                            const void* dmats, hipStream_t st)
+                            const void* dmats, int max_blocks, hipStream_t st)
 {
     if (pass.m < 1 || pass.m > 13 || pass.m > n || pass.L > pass.m) return hipErrorInvalidValue;
-    return dt == QS_C128 ? launch_r<double>(psi, n, pass, dops, dmats, st)
-                         : launch_r<float>(psi, n, pass, dops, dmats, st);
+    return dt == QS_C128 ? launch_r<double>(psi, n, pass, dops, dmats, max_blocks, st)
+                         : launch_r<float>(psi, n, pass, dops, dmats, max_blocks, st);
 }
 
 } // namespace qs
