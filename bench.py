@@ -54,6 +54,8 @@ def _args():
     p.add_argument("--count", type=int, default=0, help="circuits of the batch / requests of the stream")
     p.add_argument("--no-baselines", action="store_true",
                    help="circuits/batch: skip the per-gate complex128 comparison runs")
+    p.add_argument("--only-head", action="store_true",
+                   help="circuits: run only the complex64 tile-pass variant (no comparisons, e.g. under a profiler)")
     p.add_argument("--qps-sweep", action="store_true", help="serve: also run 0.3x, 0.5x and 1.0x of saturation")
     p.add_argument("--big-blocks", type=int, default=256,
                    help="serve: workgroup cap of the large circuit's passes (0 = library default), which "
@@ -270,9 +272,10 @@ def run_circuits(a, qs, torch, W):
     arrs = {k: c.arrays() for k, c in work.items()}
     upd = {k: _updates(n, arrs[k][0]) for k in work}
     head = "c64_tiles"
-    variants = [(head, qs.QS_C64, 0, 0, a.steps, a.warmup), ("c64_mfma5", qs.QS_C64, 0, 5, 1, 1),
-                ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
-    if not a.no_baselines:
+    variants = [(head, qs.QS_C64, 0, 0, a.steps, a.warmup)]
+    if not a.only_head:
+        variants += [("c64_mfma5", qs.QS_C64, 0, 5, 1, 1), ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
+    if not a.no_baselines and not a.only_head:
         variants.append(("c128_pergate", qs.QS_C128, 1, 0, 1, 0))
     res, traces, states = {}, {}, {}
     for name, dt, mode, fk, steps, warm in variants:
@@ -301,7 +304,7 @@ def run_circuits(a, qs, torch, W):
             res.setdefault(name, {})[k] = {"ms": el * 1e3, "amp_updates_per_s": upd[k] / el,
                                            "gates": len(ops), "passes": None if plan is None else plan[0]}
             _log(f"circuits {name} {k}: {el * 1e3:.1f} ms")
-            if name in (head, "c64_mfma5", "c128_tiles"):
+            if name in (head, "c64_mfma5", "c128_tiles") and not a.only_head:
                 states.setdefault(k, {})[name] = psi
             else:
                 del psi
