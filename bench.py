@@ -54,6 +54,7 @@ def _args():
     p.add_argument("--count", type=int, default=0, help="circuits of the batch / requests of the stream")
     p.add_argument("--no-baselines", action="store_true",
                    help="circuits/batch: skip the per-gate complex128 comparison runs")
+    p.add_argument("--no-tune", action="store_true", help="batch: skip the autotuner (library defaults)")
     p.add_argument("--only-head", action="store_true",
                    help="circuits: run only the complex64 tile-pass variant (no comparisons, e.g. under a profiler)")
     p.add_argument("--qps-sweep", action="store_true", help="serve: also run 0.3x, 0.5x and 1.0x of saturation")
@@ -371,15 +372,24 @@ def run_batch(a, qs, torch, W):
     _log(f"batch: generated {count} circuits in {time.perf_counter() - t0:.1f} s")
     upd_total = sum(_updates(c.n, x[1]) for c, x in zip(circs, arrs))
 
-    def one(dt, mode, streams, steps, warm):
+    tuned, tune_rows, tune_s = {}, None, None
+    if not a.no_tune:
+        rng = np.random.default_rng(11)
+        sample = [arrs[i] for i in rng.permutation(count)[:min(256, count)]]
+        t0 = time.perf_counter()
+        tuned, tune_rows = qs.qs_batch_tune(sample, dtype=qs.QS_C64)
+        tune_s = time.perf_counter() - t0
+        _log(f"batch tuned on {len(sample)} circuits in {tune_s:.1f} s: {tuned}")
+
+    def one(dt, mode, streams, steps, warm, **kw):
         for _ in range(warm):
-            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams)
+            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams, **kw)
             qs.qs_batch_wait(b)
             qs.qs_batch_release(b)
         e2e, dev, keep = [], [], None
         for i in range(steps):
             t0 = time.perf_counter()
-            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams)
+            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams, **kw)
             t1 = time.perf_counter()
             qs.qs_batch_wait(b)
             t2 = time.perf_counter()
@@ -397,7 +407,8 @@ def run_batch(a, qs, torch, W):
         return r, keep
 
     res = {}
-    r, b64 = one(qs.QS_C64, 0, 0, a.steps, a.warmup)
+    r, b64 = one(qs.QS_C64, 0, 0, a.steps, a.warmup, **tuned)
+    r["options"] = dict(tuned) or "library defaults"
     res["c64_fused"] = r
     _log(f"batch c64 fused: {r['circuits_per_s']:.0f} circuits/s")
     # closed-form check of sampled QFT / Grover circuits of the fused complex64 batch
@@ -411,6 +422,20 @@ def run_batch(a, qs, torch, W):
         emax = max(emax, float(np.max(np.abs(got - want))))
     r["closed_form_check"] = {"circuits": len(pick), "min_fidelity": fmin, "max_abs_err": emax}
     qs.qs_batch_release(b64)
+    # the same batch replayed from its HIP graph: device work only (planned and uploaded once)
+    b = qs.qs_batch_submit(arrs, dtype=qs.QS_C64, mode=0, graph=1, **tuned)
+    qs.qs_batch_wait(b)
+    rt = []
+    for _ in range(max(a.steps, 2)):
+        t0 = time.perf_counter()
+        qs.qs_batch_replay(b)
+        qs.qs_batch_wait(b)
+        rt.append(time.perf_counter() - t0)
+    dev = qs.qs_batch_get_stats(b)["device_ms"]
+    qs.qs_batch_release(b)
+    res["c64_graph_replay"] = {"circuits_per_s": count / float(np.median(rt)), "wall_ms": 1e3 * float(np.median(rt)),
+                               "device_ms": dev, "note": "same batch replayed from its captured HIP graph"}
+    _log(f"batch c64 graph replay: {res['c64_graph_replay']['circuits_per_s']:.0f} circuits/s")
     r, b = one(qs.QS_C128, 0, 0, 1, 1)
     qs.qs_batch_release(b)
     res["c128_fused"] = r
@@ -439,7 +464,8 @@ def run_batch(a, qs, torch, W):
         else:
             alg += qs.qs_plan_circuit(c.n, qs.QS_C64, x[1], x[2], mode=0)[0] * (16 << c.n)
     ach = alg / (v["device_ms"] * 1e-3) / 1e9
-    out.update({"variants": res, "roofline": {
+    out.update({"tuning": {"sample": 256, "seconds": tune_s, "chosen": tuned, "candidates": tune_rows},
+                "variants": res, "roofline": {
         "bound": "hbm", "kernel": "all batch launches (aggregate)", "achieved": ach, "peak": PEAK_HBM_GBS,
         "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
         "note": "states of n<=22 (<=32 MiB) stay in L2/Infinity Cache, so HBM is a loose roof here"}})

@@ -237,7 +237,9 @@ typedef struct {
     int32_t streams;     /* HIP streams the batch spreads over (0 = 8) */
     int32_t fuse_k;      /* as in qs_run_opts */
     int32_t tile_qubits; /* as in qs_run_opts */
-    int32_t rsv[3];
+    int32_t graph;       /* mode 0: 1 = capture the device work in a HIP graph (launched now and
+                            by every qs_batch_replay) */
+    int32_t rsv[2];
 } qs_batch_opts;
 
 typedef struct {
@@ -272,6 +274,31 @@ qs_status qs_batch_state(qs_batch b, int i, void** dev_ptr, int* n);
 qs_status qs_batch_download(qs_batch b, int i, void* host);
 
 qs_status qs_batch_get_stats(qs_batch b, qs_batch_stats* out);
+
+/* Run a fused (mode 0) batch again: the same circuits and plans, states
+ * recomputed from their initial basis states, with no host planning or
+ * upload (replaying the HIP graph if the batch was submitted with graph = 1).
+ * Waits for the previous run first; returns without waiting for this one.
+ * Results are bitwise those of the first run.  QS_ERR_UNSUPPORTED for
+ * mode 1 batches. */
+qs_status qs_batch_replay(qs_batch b);
+
+/* One candidate configuration timed by qs_batch_tune. */
+typedef struct {
+    int32_t tile_qubits;
+    int32_t fuse_k;
+    double device_ms; /* best device time of two replays of the sample */
+} qs_tune_entry;
+
+/* Autotune a batch configuration on a sample of circuits (survey batching
+ * item): every candidate tile size (10..12) and, for complex64, fused
+ * matrix-core width (0, 4, 5) is planned, run, and replayed twice on the
+ * device; *opts (dtype and mode as given, mode 0 only) gets the fastest
+ * tile_qubits and fuse_k.  out[0..max_out) receives the timings (NULL
+ * allowed), *n_out their number.  Allocates and frees device memory for the
+ * sample's states. */
+qs_status qs_batch_tune(const qs_circuit* sample, int count, qs_batch_opts* opts, qs_tune_entry* out, int max_out,
+                        int* n_out);
 
 /* Wait for outstanding work and free the batch (NULL accepted). */
 qs_status qs_batch_release(qs_batch b);

@@ -45,7 +45,12 @@ class _Circuit(ctypes.Structure):
 
 class _BatchOpts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("mode", ctypes.c_int32), ("streams", ctypes.c_int32),
-                ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32), ("rsv", ctypes.c_int32 * 3)]
+                ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("rsv", ctypes.c_int32 * 2)]
+
+
+class _TuneEntry(ctypes.Structure):
+    _fields_ = [("tile_qubits", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("device_ms", ctypes.c_double)]
 
 
 class _BatchStats(ctypes.Structure):
@@ -111,6 +116,9 @@ def _load():
         "qs_plan_export": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
                             ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64), vp, ctypes.POINTER(ctypes.c_int64),
                             dp, ctypes.POINTER(ctypes.c_int64)], i32),
+        "qs_batch_replay": ([vp], i32),
+        "qs_batch_tune": ([ctypes.POINTER(_Circuit), i32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_TuneEntry), i32,
+                           ctypes.POINTER(i32)], i32),
         "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
         "qs_norm": ([vp, dp], i32),
         "qs_sync": ([vp], i32),
@@ -340,9 +348,7 @@ def qs_sync(s: int):
     _check(lib.qs_sync(ctypes.c_void_p(s)))
 
 
-def qs_batch_submit(circuits, dtype: int = QS_C128, mode: int = 0, streams: int = 0, fuse_k: int = 0,
-                    tile_qubits: int = 0) -> int:
-    """circuits: iterable of (n, ops, mats, init_basis) or objects with .n/.arrays()/.init_basis."""
+def _circuit_array(circuits):
     keep, arr = [], (_Circuit * max(1, len(circuits)))()
     for i, c in enumerate(circuits):
         if hasattr(c, "arrays"):
@@ -354,10 +360,32 @@ def qs_batch_submit(circuits, dtype: int = QS_C128, mode: int = 0, streams: int 
         keep.append((ops, mats))
         arr[i] = _Circuit(n, 0, int(basis), ops.ctypes.data if len(ops) else 0, len(ops),
                           mats.ctypes.data if mats.size else 0, mats.size)
-    o = _BatchOpts(dtype, mode, streams, fuse_k, tile_qubits)
+    return keep, arr
+
+
+def qs_batch_submit(circuits, dtype: int = QS_C128, mode: int = 0, streams: int = 0, fuse_k: int = 0,
+                    tile_qubits: int = 0, graph: int = 0) -> int:
+    """circuits: iterable of (n, ops, mats, init_basis) or objects with .n/.arrays()/.init_basis."""
+    keep, arr = _circuit_array(circuits)
+    o = _BatchOpts(dtype, mode, streams, fuse_k, tile_qubits, graph)
     h = ctypes.c_void_p()
     _check(lib.qs_batch_submit(arr, len(circuits), ctypes.byref(o), ctypes.byref(h)))
     return h.value
+
+
+def qs_batch_replay(b: int):
+    _check(lib.qs_batch_replay(ctypes.c_void_p(b)))
+
+
+def qs_batch_tune(sample, dtype: int = QS_C128, streams: int = 0):
+    """Time candidate (tile_qubits, fuse_k) on a sample; returns (best dict, all timings)."""
+    keep, arr = _circuit_array(sample)
+    o = _BatchOpts(dtype, 0, streams, 0, 0, 0)
+    out = (_TuneEntry * 16)()
+    k = ctypes.c_int()
+    _check(lib.qs_batch_tune(arr, len(sample), ctypes.byref(o), out, 16, ctypes.byref(k)))
+    rows = [{"tile_qubits": e.tile_qubits, "fuse_k": e.fuse_k, "device_ms": e.device_ms} for e in out[:k.value]]
+    return {"tile_qubits": o.tile_qubits, "fuse_k": o.fuse_k}, rows
 
 
 def qs_batch_wait(b: int, timeout_ms: int = -1):

@@ -40,6 +40,22 @@ struct qs_batch_s {
     hipEvent_t cls_done[3] = {nullptr, nullptr, nullptr};
     bool failed = false;
     qs_batch_stats stats;
+    // the fused launch schedule, kept for qs_batch_replay (device data in dbuf)
+    struct Sched {
+        std::vector<std::pair<int, std::pair<size_t, int>>> whole_groups; // (n, (list offset, count))
+        size_t persist_l0 = 0, stream_l0 = 0;
+        int persist_count = 0, stream_count = 0, persist_m = 0, stream_m = 0;
+        std::vector<std::pair<size_t, std::pair<int, uint32_t>>> rounds; // (entry offset, (count, blocks))
+        bool any_full = false;
+        const BatchCirc* dcirc = nullptr;
+        const BatchPass* dpass = nullptr;
+        const TileOp* dops = nullptr;
+        const int32_t* dlist = nullptr;
+        const RoundEntry* dents = nullptr;
+        const double* dmats = nullptr;
+    } sched;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -55,6 +71,8 @@ void release(qs_batch b)
 {
     if (!b) return;
     for (hipStream_t s : b->st) (void)hipStreamSynchronize(s);
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
     if (b->t0) (void)hipEventDestroy(b->t0);
     for (hipEvent_t e : b->cls_done)
@@ -65,6 +83,101 @@ void release(qs_batch b)
     if (b->hbuf) (void)hipHostFree(b->hbuf);
     (void)hipGetLastError();
     delete b;
+}
+
+// Enqueue the fused batch's device work from its kept schedule: arena
+// init, whole circuits (stream 0), persistent circuits (stream 1), pass-major
+// rounds (stream 2).  The streams must already be ordered after the upload.
+// mark: record the per-class completion events (not inside a graph capture).
+qs_status enqueue_fused(qs_batch b, bool mark)
+{
+    const qs_batch_s::Sched& S = b->sched;
+    const int NS = (int)b->st.size();
+    hipStream_t s0 = b->st[0], s1 = b->st[NS > 1 ? 1 : 0], sr = b->st[NS > 2 ? 2 : 0];
+    auto launched = [&](hipError_t err, const char* what) -> qs_status {
+        b->stats.launches += 1;
+        if (err != hipSuccess) return bfail(b, err, what);
+        return QS_OK;
+    };
+    auto mk = [&](int k, hipStream_t s) {
+        if (!mark) return;
+        if (!b->cls_done[k] && hipEventCreate(&b->cls_done[k]) != hipSuccess) return;
+        (void)hipEventRecord(b->cls_done[k], s);
+    };
+    qs_status st = QS_OK;
+    if (S.stream_count > 0) {
+        // zero the arena and set the streamed circuits' basis amplitudes before
+        // any other stream writes a state into it
+        hipError_t e = launch_batch_init(b->dt, b->arena, b->arena_bytes, S.dcirc, S.dlist + S.stream_l0,
+                                         S.stream_count, s0);
+        b->stats.launches += 2;
+        if (e != hipSuccess) return bfail(b, e, "batch init launch");
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) == hipSuccess) {
+            (void)hipEventRecord(ev, s0);
+            (void)hipStreamWaitEvent(s1, ev, 0);
+            (void)hipStreamWaitEvent(sr, ev, 0);
+            (void)hipEventDestroy(ev);
+        }
+    }
+    for (auto& g : S.whole_groups) {
+        st = launched(launch_batch_whole(b->dt, g.first, b->arena, S.dcirc, S.dlist + g.second.first, g.second.second,
+                                         S.dpass, S.dops, S.dmats, S.any_full, s0),
+                      "batch whole launch");
+        if (st != QS_OK) return st;
+    }
+    if (!S.whole_groups.empty()) mk(0, s0);
+    if (S.persist_count > 0) {
+        st = launched(launch_batch_persist(b->dt, S.persist_m, b->arena, S.dcirc, S.dlist + S.persist_l0,
+                                           S.persist_count, S.dpass, S.dops, S.dmats, S.any_full, s1),
+                      "batch persistent launch");
+        if (st != QS_OK) return st;
+        mk(1, s1);
+    }
+    for (size_t r = 0; r < S.rounds.size(); ++r) {
+        st = launched(launch_batch_round(b->dt, S.stream_m, b->arena, S.dcirc, S.dpass, S.dops, S.dmats,
+                                         S.dents + S.rounds[r].first, S.rounds[r].second.first,
+                                         S.rounds[r].second.second, S.any_full, sr),
+                      "batch round launch");
+        if (st != QS_OK) return st;
+    }
+    if (!S.rounds.empty()) mk(2, sr);
+    return QS_OK;
+}
+
+// Capture enqueue_fused into a HIP graph (streams forked from and joined
+// back to stream 0), keep it for replays, and launch it once.
+qs_status capture_fused(qs_batch b)
+{
+    hipStream_t s0 = b->st[0];
+    const int NS = (int)b->st.size();
+    const int used = NS < 3 ? NS : 3;
+    hipError_t e = hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, e, "hipStreamBeginCapture");
+    std::vector<hipEvent_t> evs;
+    auto ev = [&]() {
+        hipEvent_t x = nullptr;
+        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) == hipSuccess) evs.push_back(x);
+        return x;
+    };
+    hipEvent_t fork = ev();
+    (void)hipEventRecord(fork, s0);
+    for (int i = 1; i < used; ++i) (void)hipStreamWaitEvent(b->st[i], fork, 0);
+    qs_status st = enqueue_fused(b, false);
+    for (int i = 1; i < used; ++i) {
+        hipEvent_t j = ev();
+        (void)hipEventRecord(j, b->st[i]);
+        (void)hipStreamWaitEvent(s0, j, 0);
+    }
+    e = hipStreamEndCapture(s0, &b->graph);
+    for (hipEvent_t x : evs) (void)hipEventDestroy(x);
+    if (st != QS_OK) return st;
+    if (e != hipSuccess) return bfail(b, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bfail(b, e, "hipGraphInstantiate");
+    e = hipGraphLaunch(b->gexec, s0);
+    if (e != hipSuccess) return bfail(b, e, "hipGraphLaunch");
+    return QS_OK;
 }
 
 int whole_max(int dt)
@@ -313,17 +426,6 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     const int32_t* dlist = (const int32_t*)(b->dbuf + o_list);
     const RoundEntry* dents = (const RoundEntry*)(b->dbuf + o_ents);
     const double* dmats = (const double*)(b->dbuf + o_mats);
-    if (b->mode == 0 && stream_count > 0) {
-        // zero the arena and set the streamed circuits' basis amplitudes before
-        // any other stream writes a state into it
-        e = launch_batch_init(b->dt, b->arena, b->arena_bytes, dcirc, dlist + stream_l0, stream_count, s0);
-        b->stats.launches += 2;
-        if (e != hipSuccess) {
-            qs_status r = bfail(b, e, "batch init launch");
-            release(b);
-            return r;
-        }
-    }
     hipEvent_t up;
     (void)hipEventCreate(&up);
     (void)hipEventRecord(up, s0);
@@ -337,35 +439,26 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         return QS_OK;
     };
     const int NS = (int)b->st.size();
-    bool any_full = false; // any pass needs the full tile kernel
-    for (const BatchPass& d : bpass) any_full |= ops_need_full(bops.data() + d.op0, (size_t)d.nops, d.m);
     if (b->mode == 0) {
-        // whole circuits on stream 0, persistent ones on stream 1 (if any), the
-        // rest round-robin over the remaining streams
-        auto mark = [&](int k, hipStream_t s) {
-            if (hipEventCreate(&b->cls_done[k]) == hipSuccess) (void)hipEventRecord(b->cls_done[k], s);
-        };
+        qs_batch_s::Sched& S = b->sched;
+        S.whole_groups = whole_groups;
+        S.persist_l0 = persist_l0;
+        S.persist_count = persist_count;
+        S.persist_m = persist_m;
+        S.stream_l0 = stream_l0;
+        S.stream_count = stream_count;
+        S.stream_m = stream_m;
+        S.rounds = rounds;
+        S.any_full = false; // any pass needs the full tile kernel
+        for (const BatchPass& d : bpass) S.any_full |= ops_need_full(bops.data() + d.op0, (size_t)d.nops, d.m);
+        S.dcirc = dcirc;
+        S.dpass = dpass;
+        S.dops = dops;
+        S.dlist = dlist;
+        S.dents = dents;
+        S.dmats = dmats;
         for (int i = 0; i < count; ++i) b->stats.class_circuits[cls[i]] += 1;
-        for (auto& g : whole_groups) {
-            st = launched(launch_batch_whole(b->dt, g.first, b->arena, dcirc, dlist + g.second.first,
-                                             g.second.second, dpass, dops, dmats, any_full, s0),
-                          "batch whole launch");
-            if (st != QS_OK) break;
-        }
-        if (!whole_groups.empty()) mark(0, s0);
-        if (st == QS_OK && persist_count > 0) {
-            st = launched(launch_batch_persist(b->dt, persist_m, b->arena, dcirc, dlist + persist_l0, persist_count,
-                                               dpass, dops, dmats, any_full, b->st[NS > 1 ? 1 : 0]),
-                          "batch persistent launch");
-            mark(1, b->st[NS > 1 ? 1 : 0]);
-        }
-        hipStream_t sr = b->st[NS > 2 ? 2 : 0];
-        for (size_t r = 0; r < rounds.size() && st == QS_OK; ++r)
-            st = launched(launch_batch_round(b->dt, stream_m, b->arena, dcirc, dpass, dops, dmats,
-                                             dents + rounds[r].first, rounds[r].second.first,
-                                             rounds[r].second.second, any_full, sr),
-                          "batch round launch");
-        if (!rounds.empty()) mark(2, sr);
+        st = o.graph ? capture_fused(b) : enqueue_fused(b, true);
     } else {
         for (int i = 0; i < count && st == QS_OK; ++i) {
             const qs_circuit& c = circuits[i];
@@ -465,3 +558,72 @@ qs_status qs_batch_release(qs_batch b)
 }
 
 } // extern "C"
+
+qs_status qs_batch_replay(qs_batch b)
+{
+    if (!b) return set_err(QS_ERR_ARG, "null batch handle");
+    if (b->mode != 0) return set_err(QS_ERR_UNSUPPORTED, "replay needs a fused (mode 0) batch");
+    qs_status st = qs_batch_wait(b, -1);
+    if (st != QS_OK) return st;
+    hipStream_t s0 = b->st[0];
+    hipError_t e = hipEventRecord(b->t0, s0);
+    if (e != hipSuccess) return bfail(b, e, "hipEventRecord");
+    for (size_t i = 1; i < b->st.size(); ++i) (void)hipStreamWaitEvent(b->st[i], b->t0, 0);
+    if (b->gexec) {
+        e = hipGraphLaunch(b->gexec, s0);
+        if (e != hipSuccess) return bfail(b, e, "hipGraphLaunch");
+    } else if ((st = enqueue_fused(b, true)) != QS_OK) {
+        return st;
+    }
+    for (size_t i = 0; i < b->st.size(); ++i) {
+        e = hipEventRecord(b->done[i], b->st[i]);
+        if (e != hipSuccess) return bfail(b, e, "hipEventRecord");
+    }
+    return QS_OK;
+}
+
+qs_status qs_batch_tune(const qs_circuit* sample, int count, qs_batch_opts* opts, qs_tune_entry* out, int max_out,
+                        int* n_out)
+{
+    if (!sample || count <= 0 || !opts) return set_err(QS_ERR_ARG, "empty sample or null options");
+    if (opts->mode != 0) return set_err(QS_ERR_ARG, "tuning needs mode 0 (fused)");
+    const int dt = opts->dtype == 0 ? QS_C128 : opts->dtype;
+    std::vector<std::pair<int, int>> cand;
+    for (int m = 10; m <= 12; ++m) {
+        cand.push_back({m, 0});
+        if (dt == QS_C64) {
+            cand.push_back({m, 4});
+            cand.push_back({m, 5});
+        }
+    }
+    double best = -1.0;
+    int bm = 0, bf = 0, k = 0;
+    for (auto& c : cand) {
+        qs_batch_opts o = *opts;
+        o.tile_qubits = c.first;
+        o.fuse_k = c.second;
+        o.graph = 0;
+        qs_batch b = nullptr;
+        qs_status st = qs_batch_submit(sample, count, &o, &b);
+        if (st != QS_OK) return st;
+        double t = -1.0;
+        for (int rep = 0; rep < 3 && st == QS_OK; ++rep) {
+            if (rep > 0) st = qs_batch_replay(b);
+            if (st == QS_OK) st = qs_batch_wait(b, -1);
+            if (st == QS_OK && rep > 0 && (t < 0 || b->stats.device_ms < t)) t = b->stats.device_ms;
+        }
+        qs_batch_release(b);
+        if (st != QS_OK) return st;
+        if (out && k < max_out) out[k] = qs_tune_entry{c.first, c.second, t};
+        ++k;
+        if (best < 0 || t < best) {
+            best = t;
+            bm = c.first;
+            bf = c.second;
+        }
+    }
+    opts->tile_qubits = bm;
+    opts->fuse_k = bf;
+    if (n_out) *n_out = k;
+    return QS_OK;
+}

@@ -511,12 +511,6 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 gpm |= t.gcm;
             }
         };
-        auto diag_bits = [&](const int* gs, size_t cnt) {
-            uint32_t tpm;
-            uint64_t gpm;
-            diag_masks(gs, cnt, tpm, gpm);
-            return r + __builtin_popcount(tpm) + __builtin_popcountll(gpm);
-        };
         auto diag_group = [&](const int* gs, size_t cnt) -> bool {
             uint32_t tpm = 0;
             uint64_t gpm = 0;

@@ -359,3 +359,74 @@ def test_batch_rejects_invalid_circuit_before_any_work(qs):
     with pytest.raises(qs.QSError) as e:
         qs.qs_batch_submit([good, bad])
     assert e.value.status == qs.QS_ERR_ARG and "circuit 1" in str(e.value)
+
+
+@pytest.mark.parametrize("dt", [1, 2])
+@pytest.mark.parametrize("graph", [0, 1])
+def test_batch_replay_bitwise(qs, dt, graph):
+    """A fused batch replayed (from its HIP graph or by re-enqueueing) gives
+    bitwise the first run's states, every time, with eager device work and
+    synchronisations between the replays; the first run matches the oracle."""
+    import torch
+
+    circs = [W.qft(n, 5 * n + 1) for n in (9, 12, 14, 17)] + [W.rqc_chain(n, 6, n) for n in (10, 13, 15, 16, 18)] + \
+            [W.grover(n, 3 * n) for n in (11, 15)]
+    b = qs.qs_batch_submit(circs, dtype=dt, mode=0, graph=graph)
+    try:
+        qs.qs_batch_wait(b)
+        first = [qs.qs_batch_download(b, i, dt) for i in range(len(circs))]
+        for i, c in enumerate(circs):
+            want = oracle.run_circuit(c)
+            got = first[i].astype(np.complex128)
+            if dt == 2:
+                assert float(np.max(np.abs(got - want))) <= 1e-12, c.name
+            else:
+                assert abs(np.vdot(want, got)) ** 2 >= 1 - 1e-6, c.name
+        x = torch.randn(1 << 20, device="cuda")
+        for rep in range(3):
+            y = (x * (rep + 1)).sum()  # the program's own eager work between replays
+            torch.cuda.synchronize()
+            qs.qs_batch_replay(b)
+            qs.qs_batch_wait(b)
+            for i in range(len(circs)):
+                assert qs.qs_batch_download(b, i, dt).tobytes() == first[i].tobytes(), (rep, circs[i].name)
+            assert float(y.item()) == float(y.item())
+        st = qs.qs_batch_get_stats(b)
+        assert st["device_ms"] > 0
+    finally:
+        qs.qs_batch_release(b)
+
+
+def test_batch_replay_rejects_per_gate(qs):
+    b = qs.qs_batch_submit([W.qft(8, 3)], dtype=2, mode=1)
+    try:
+        qs.qs_batch_wait(b)
+        with pytest.raises(qs.QSError) as e:
+            qs.qs_batch_replay(b)
+        assert e.value.status == qs.QS_ERR_UNSUPPORTED
+    finally:
+        qs.qs_batch_release(b)
+
+
+@pytest.mark.parametrize("dt", [1, 2])
+def test_batch_tune(qs, dt):
+    """The autotuner times every candidate on a sample and returns one of them;
+    a batch with the tuned options matches the oracle."""
+    sample = [W.rqc_chain(n, 8, 100 + n) for n in (14, 15, 16, 17, 18)] + [W.qft(n, n) for n in (15, 17)]
+    best, rows = qs.qs_batch_tune(sample, dtype=dt)
+    expect = 9 if dt == 1 else 3
+    assert len(rows) == expect and all(r["device_ms"] > 0 for r in rows)
+    assert (best["tile_qubits"], best["fuse_k"]) in [(r["tile_qubits"], r["fuse_k"]) for r in rows]
+    assert min(rows, key=lambda r: r["device_ms"])["tile_qubits"] == best["tile_qubits"]
+    b = qs.qs_batch_submit(sample, dtype=dt, mode=0, **best)
+    try:
+        qs.qs_batch_wait(b)
+        for i, c in enumerate(sample):
+            got = qs.qs_batch_download(b, i, dt).astype(np.complex128)
+            want = oracle.run_circuit(c)
+            if dt == 2:
+                assert float(np.max(np.abs(got - want))) <= 1e-12, c.name
+            else:
+                assert abs(np.vdot(want, got)) ** 2 >= 1 - 1e-6, c.name
+    finally:
+        qs.qs_batch_release(b)
