@@ -4,6 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
 bench's ``cpu_baseline`` leg, never by the product package.  It shares no code
 with the GPU path; both sides read the same circuit IR (``workloads``).
 
+* ``expect_pauli`` and ``sample`` (Pauli-string expectation values; sampling
+  by inverting the cumulative distribution at caller-given uniforms).
 * ``run``/``apply_op``/``probabilities``/``norm2`` call ``qs_oracle.c``: plain
   FP64 loops that apply each gate operator in order (the pair update of Alg. 1
   generalised to any 2x2 / 2^k x 2^k matrix, controls as in Fig. control6q2).
@@ -56,6 +58,8 @@ def lib():
             L.orc_norm2.argtypes = [ctypes.c_int, dp]
             L.orc_norm2.restype = ctypes.c_double
             L.orc_num_threads.restype = ctypes.c_int
+            L.orc_expect_pauli.argtypes = [ctypes.c_int, dp, ctypes.c_uint64, ctypes.c_uint64, dp]
+            L.orc_sample.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_void_p]
             assert L.orc_op_size() == 64
             _lib = L
     return _lib
@@ -121,6 +125,23 @@ def probabilities(n: int, psi: np.ndarray, qubits) -> np.ndarray:
 def norm2(n: int, psi: np.ndarray) -> float:
     psi = np.ascontiguousarray(psi, dtype=np.complex128)
     return float(lib().orc_norm2(n, _dp(psi)))
+
+
+def expect_pauli(n: int, psi: np.ndarray, x: int, z: int) -> complex:
+    """<psi|P|psi> for P = i^|x&z| X^x Z^z (Y where a bit is in both masks)."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.zeros(2, dtype=np.float64)
+    lib().orc_expect_pauli(n, _dp(psi), int(x), int(z), _dp(out))
+    return complex(out[0], out[1])
+
+
+def sample(n: int, psi: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Indices drawn by inverting the cumulative |psi|^2 at the given uniforms."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(u.size, dtype=np.uint64)
+    lib().orc_sample(n, _dp(psi), _dp(u), u.size, out.ctypes.data)
+    return out
 
 
 def outputs_at(idx: np.ndarray, targets, U: np.ndarray, cmask: int, cvals: int, fetch):

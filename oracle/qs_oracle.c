@@ -168,3 +168,68 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Expectation value of a Pauli string.  P = i^w X^x Z^z with w = |x & z|
+ * (X on the bits of x, Z on the bits of z, Y = iXZ on bits in both), so
+ * P|k> = i^w (-1)^{|k & z|} |k ^ x> and
+ *   <psi|P|psi> = i^w * sum_k conj(psi_{k^x}) psi_k (-1)^{|k & z|}.
+ * Serial, compensated sums of the real and imaginary parts; out = (re, im). */
+void orc_expect_pauli(int n, const double* psi, uint64_t x, uint64_t z, double* out)
+{
+    const int64_t N = (int64_t)1 << n;
+    double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    for (int64_t k = 0; k < N; ++k) {
+        const int64_t j = k ^ (int64_t)x;
+        const double ar = psi[2 * j], ai = -psi[2 * j + 1]; /* conj(psi_j) */
+        const double br = psi[2 * k], bi = psi[2 * k + 1];
+        double pr = ar * br - ai * bi, pi = ar * bi + ai * br;
+        if (__builtin_popcountll((uint64_t)k & z) & 1) {
+            pr = -pr;
+            pi = -pi;
+        }
+        nsum(&sr, &cr, pr);
+        nsum(&si, &ci, pi);
+    }
+    double re = sr + cr, im = si + ci;
+    /* multiply by i^w */
+    for (int w = __builtin_popcountll(x & z) & 3; w > 0; --w) {
+        const double t = re;
+        re = -im;
+        im = t;
+    }
+    out[0] = re;
+    out[1] = im;
+}
+
+/* Sampling by inversion of the cumulative distribution: for each uniform
+ * u[s] in [0, 1), out[s] is the smallest index i with
+ *   sum_{j <= i} |psi_j|^2 > u[s] * sum_j |psi_j|^2
+ * (cumulative sums in FP64 in index order, compensated); a target at or
+ * above the total gives the last index with nonzero probability. */
+void orc_sample(int n, const double* psi, const double* u, int64_t shots, uint64_t* out)
+{
+    const int64_t N = (int64_t)1 << n;
+    double* C = (double*)malloc((size_t)N * sizeof(double));
+    double s = 0.0, c = 0.0;
+    int64_t last = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        const double p = psi[2 * i] * psi[2 * i] + psi[2 * i + 1] * psi[2 * i + 1];
+        nsum(&s, &c, p);
+        C[i] = s + c;
+        if (p > 0.0) last = i;
+    }
+    const double total = C[N - 1];
+    for (int64_t k = 0; k < shots; ++k) {
+        const double t = u[k] * total;
+        int64_t lo = 0, hi = N; /* first i with C[i] > t */
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (C[mid] > t)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        out[k] = (uint64_t)(lo < N ? lo : last);
+    }
+    free(C);
+}

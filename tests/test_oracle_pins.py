@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+import oracle
 from oracle import dense
 from tests.conftest import golden
 
@@ -327,3 +328,76 @@ def test_generators_deterministic():
     m1 = W.circuit_mix(16, 7)
     m2 = W.circuit_mix(16, 7)
     assert [x.name for x in m1] == [x.name for x in m2]
+
+
+# ---------------------------------------------------------------- Pauli expectations and sampling
+
+_PAULI = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]], complex), "Y": np.array([[0, -1j], [1j, 0]]),
+          "Z": np.diag([1.0, -1.0]).astype(complex)}
+
+
+def _pauli_dense(n, x, z):
+    """Kronecker product of single-qubit Paulis, qubit 0 the rightmost factor."""
+    M = np.eye(1, dtype=complex)
+    for q in reversed(range(n)):
+        xb, zb = (x >> q) & 1, (z >> q) & 1
+        M = np.kron(M, _PAULI["Y" if xb and zb else ("X" if xb else ("Z" if zb else "I"))])
+    return M
+
+
+def test_expect_pauli_matches_dense_operator():
+    rng = np.random.default_rng(21)
+    for n in (1, 2, 4, 6):
+        psi = W.random_state(n, 30 + n)
+        for _ in range(12):
+            x, z = int(rng.integers(1 << n)), int(rng.integers(1 << n))
+            want = np.vdot(psi, _pauli_dense(n, x, z) @ psi)
+            got = oracle.expect_pauli(n, psi, x, z)
+            assert abs(got - want) <= 1e-13, (n, x, z)
+            assert abs(got.imag) <= 1e-13  # Hermitian
+
+
+def test_expect_pauli_closed_forms():
+    n = 5
+    for xb in (0, 7, 19, 31):  # basis states: <Z^z> = (-1)^|x & z|, <X on any bit> = 0
+        psi = oracle.basis(n, xb)
+        for z in (1, 6, 31):
+            assert oracle.expect_pauli(n, psi, 0, z) == (-1) ** bin(xb & z).count("1")
+        assert oracle.expect_pauli(n, psi, 4, 0) == 0
+    ghz = np.zeros(1 << n, complex)
+    ghz[0] = ghz[-1] = 2 ** -0.5
+    assert abs(oracle.expect_pauli(n, ghz, (1 << n) - 1, 0) - 1) < 1e-15   # <X...X> = 1
+    assert abs(oracle.expect_pauli(n, ghz, 0, 3) - 1) < 1e-15              # <Z0 Z1> = 1
+    assert abs(oracle.expect_pauli(n, ghz, 0, 1)) < 1e-15                  # <Z0> = 0
+    plus_i = np.array([1, 1j]) / 2 ** 0.5                                   # Y eigenstate
+    assert abs(oracle.expect_pauli(1, plus_i, 1, 1) - 1) < 1e-15
+
+
+def test_sample_closed_forms_and_brute_force():
+    n = 6
+    u = np.random.default_rng(5).random(400)
+    assert np.all(oracle.sample(n, oracle.basis(n, 37), u) == 37)
+    uni = np.full(1 << n, 2 ** (-n / 2), complex)                           # H^n|0>: index = floor(u 2^n)
+    away = np.abs(u * (1 << n) - np.round(u * (1 << n))) > 1e-9
+    assert np.array_equal(oracle.sample(n, uni, u)[away], np.floor(u * (1 << n))[away].astype(np.uint64))
+    ghz = np.zeros(1 << n, complex)
+    ghz[0] = ghz[-1] = 2 ** -0.5
+    assert np.array_equal(oracle.sample(n, ghz, u), np.where(u < 0.5, 0, (1 << n) - 1).astype(np.uint64))
+    for seed in range(5):                                                   # plain numpy inversion
+        psi = W.random_state(n, 40 + seed)
+        C = np.cumsum(np.abs(psi) ** 2)
+        want = np.searchsorted(C, u * C[-1], side="right")
+        assert np.array_equal(oracle.sample(n, psi, u), want.astype(np.uint64))
+
+
+def test_sample_and_expectation_detect_slips():
+    """A conjugation slip or a dropped sign breaks the dense comparison; a
+    cumulative distribution taken in reverse order breaks the inversion."""
+    n = 3
+    psi = W.random_state(n, 77)
+    want = np.vdot(psi, _pauli_dense(n, 5, 3) @ psi)
+    assert abs(np.vdot(psi.conj(), _pauli_dense(n, 5, 3) @ psi.conj()) - want) > 1e-3
+    assert abs(oracle.expect_pauli(n, psi, 5, 3) + want) > 1e-3
+    u = np.random.default_rng(1).random(200)
+    rev = (1 << n) - 1 - oracle.sample(n, psi[::-1].copy(), u).astype(np.int64)
+    assert not np.array_equal(rev, oracle.sample(n, psi, u).astype(np.int64))
