@@ -212,6 +212,25 @@ qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out);
 /* Squared norm sum |psi_i|^2 in FP64 (the m = 0 case).  Blocking. */
 qs_status qs_norm(qs_state s, double* out);
 
+/* Expectation value <psi|P|psi> of the Pauli string P = i^w X^x Z^z with
+ * w = popcount(x_mask & z_mask): X on the qubits of x_mask, Z on those of
+ * z_mask, Y = iXZ on qubits in both.  Summed in FP64 in a fixed order as
+ * i^w * sum_k conj(psi_{k ^ x}) psi_k (-1)^popcount(k & z); out[0] = real
+ * part, out[1] = imaginary part (0 up to rounding, P being Hermitian).  The
+ * state is not normalised first.  Blocking (NEXT item: measurement on top of
+ * the reductions).  QS_ERR_ARG for mask bits at or above n. */
+qs_status qs_expect_pauli(qs_state s, uint64_t x_mask, uint64_t z_mask, double* out);
+
+/* Sample basis-state indices from |psi_i|^2 / sum_j |psi_j|^2 by inverting
+ * the cumulative distribution at the caller's uniforms u[0..shots), each in
+ * [0, 1): out[k] is the smallest index whose cumulative probability exceeds
+ * u[k] (FP64 chunk sums over min(4096, 2^n) amplitudes with a compensated
+ * prefix, then a walk inside the chunk; results may differ from an exact
+ * inversion only when u[k] lies within rounding of a boundary).  u and out
+ * are host arrays of shots elements, owned by the caller.  Blocking.
+ * QS_ERR_ARG for shots < 0 or a uniform outside [0, 1). */
+qs_status qs_sample(qs_state s, const double* u, int64_t shots, uint64_t* out);
+
 /* Wait for all work enqueued on the state. */
 qs_status qs_sync(qs_state s);
 

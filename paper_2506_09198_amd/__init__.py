@@ -119,6 +119,8 @@ def _load():
         "qs_batch_replay": ([vp], i32),
         "qs_batch_tune": ([ctypes.POINTER(_Circuit), i32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(_TuneEntry), i32,
                            ctypes.POINTER(i32)], i32),
+        "qs_expect_pauli": ([vp, u64, u64, dp], i32),
+        "qs_sample": ([vp, dp, ctypes.c_int64, ctypes.c_void_p], i32),
         "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
         "qs_norm": ([vp, dp], i32),
         "qs_sync": ([vp], i32),
@@ -328,6 +330,21 @@ def qs_plan_export(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_q
     passes = [{"m": int(d[0]), "L": int(d[1]), "op0": int(d[2]), "nops": int(d[3]),
                "Q": [int(q) for q in d[4:4 + d[0]]]} for d in desc[:np_.value]]
     return passes, tops[:nt.value], pool[:npool.value]
+
+
+def qs_expect_pauli(s: int, x_mask: int, z_mask: int) -> complex:
+    out = np.zeros(2, dtype=np.float64)
+    _check(lib.qs_expect_pauli(ctypes.c_void_p(s), int(x_mask), int(z_mask),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return complex(out[0], out[1])
+
+
+def qs_sample(s: int, u: np.ndarray) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros(u.size, dtype=np.uint64)
+    _check(lib.qs_sample(ctypes.c_void_p(s), u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), u.size,
+                         ctypes.c_void_p(out.ctypes.data)))
+    return out
 
 
 def qs_probabilities(s: int, qubits) -> np.ndarray:

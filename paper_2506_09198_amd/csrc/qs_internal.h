@@ -43,6 +43,19 @@ hipError_t launch_apply_kq_dev(void* psi, int dt, int n, const int* targets, int
 
 // Reductions.  `part` is device scratch of at least reduce_scratch_doubles()
 // doubles.  Results land in `dev_out` (device, 2^m doubles).
+// Pauli-string expectation: part needs pauli_scratch_doubles(n); dev_out
+// receives (sum re, sum im) before the factor i^|x & z|.
+uint64_t pauli_scratch_doubles(int n);
+hipError_t launch_pauli_expect(const void* psi, int dt, int n, uint64_t x, uint64_t z, double* part,
+                               double* dev_out, hipStream_t st);
+// Sampling within chunks of min(4096, 2^n) amplitudes (the chunk sums come
+// from launch_probabilities with m = 0, whose partials are per such chunk).
+struct SampleReq {
+    uint64_t chunk;
+    double residual;
+};
+hipError_t launch_sample_chunks(const void* psi, int dt, int n, const SampleReq* req, int64_t shots, uint64_t* out,
+                                hipStream_t st);
 uint64_t reduce_scratch_doubles(int n, int m);
 hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m,
                                 double* part, double* dev_out, hipStream_t st);

@@ -71,7 +71,143 @@ k_prob_final(const double* __restrict__ part, uint64_t nch, double* __restrict__
     if (threadIdx.x == 0) out[o] = s;
 }
 
+// Pauli-string expectation, pass 1.  Terms (x != 0): pairs (k0, k1 = k0 ^ x)
+// with bit b = lowest bit of x clear in k0, term = conj(psi_k1) psi_k0 s(k0)
+// + conj(psi_k0) psi_k1 s(k1), s(k) = (-1)^{|k & z|}; (x == 0): |psi_k|^2 s(k).
+// Chunks of CH consecutive terms per block, fixed lane order and tree;
+// part[chunk] = real sum, part[nch + chunk] = imaginary sum.
+template <typename V>
+__global__ void __launch_bounds__(kRT)
+k_pauli_chunks(const V* __restrict__ psi, uint64_t nterms, uint64_t ch, uint64_t nch, uint64_t x, uint64_t z,
+               int b, double* __restrict__ part)
+{
+    __shared__ double sh[kRT];
+    const uint64_t chunk = blockIdx.x;
+    const uint64_t lowm = (1ull << b) - 1;
+    double ar = 0.0, ai = 0.0;
+    for (uint64_t r = threadIdx.x; r < ch; r += kRT) {
+        const uint64_t t = chunk * ch + r;
+        if (t >= nterms) continue;
+        if (x == 0) {
+            const V a = psi[t];
+            const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+            ar += (__popcll(t & z) & 1) ? -p : p;
+        } else {
+            const uint64_t k0 = ((t >> b) << (b + 1)) | (t & lowm), k1 = k0 ^ x;
+            const V a0 = psi[k0], a1 = psi[k1];
+            const double x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
+            // conj(a1) a0 and conj(a0) a1 = conj of the first
+            const double pr = x1 * x0 + y1 * y0, pi = x1 * y0 - y1 * x0;
+            const double s0 = (__popcll(k0 & z) & 1) ? -1.0 : 1.0, s1 = (__popcll(k1 & z) & 1) ? -1.0 : 1.0;
+            ar += s0 * pr + s1 * pr;
+            ai += s0 * pi - s1 * pi;
+        }
+    }
+    const double sr = block_tree_sum(ar, sh);
+    const double si = block_tree_sum(ai, sh);
+    if (threadIdx.x == 0) {
+        part[chunk] = sr;
+        part[nch + chunk] = si;
+    }
+}
+
+// Sampling, within a chunk: one wave per shot.  Lane l holds the (up to) 64
+// consecutive amplitudes [64 l, 64 l + 64) of the shot's chunk of csize
+// (4096, or the whole state when it is smaller); lane
+// sums, an ordered prefix over the lanes, then the chosen lane walks its 64
+// probabilities in order to the first cumulative sum above the residual.  If
+// rounding leaves the residual at or above the chunk's total, the last index
+// with nonzero probability is taken.
+template <typename V>
+__global__ void __launch_bounds__(kRT)
+k_sample_chunk(const V* __restrict__ psi, uint32_t csize, const SampleReq* __restrict__ req, int64_t shots,
+               uint64_t* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t shot = (int64_t)blockIdx.x * (kRT / 64) + (threadIdx.x >> 6);
+    if (shot >= shots) return;
+    const SampleReq q = req[shot];
+    const uint32_t first = 64u * (uint32_t)lane;              // this lane's run inside the chunk
+    const int len = first >= csize ? 0 : (csize - first < 64u ? (int)(csize - first) : 64);
+    const uint64_t base = q.chunk * csize + first;
+    double ls = 0.0;
+    int lastnz = -1;
+    for (int j = 0; j < len; ++j) {
+        const V a = psi[base + j];
+        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        ls += p;
+        if (p > 0.0) lastnz = j;
+    }
+    // ordered exclusive prefix of the lane sums (lane 0 first)
+    double excl = 0.0, incl = 0.0;
+    for (int l = 0; l < 64; ++l) {
+        const double v = __shfl(ls, l);
+        if (l < lane) excl += v;
+    }
+    incl = excl + ls;
+    const unsigned long long hit = __ballot(incl > q.residual);
+    int pick = hit ? __ffsll(hit) - 1 : -1;
+    if (pick < 0) { // residual not reached: last nonzero probability of the chunk
+        const unsigned long long nz = __ballot(lastnz >= 0);
+        const int l = nz ? 63 - __clzll(nz) : 0;
+        const int j = __shfl(lastnz, l);
+        if (lane == 0) out[shot] = q.chunk * csize + 64 * (uint64_t)l + (uint64_t)(j < 0 ? 0 : j);
+        return;
+    }
+    if (lane == pick) {
+        double c = excl;
+        uint64_t idx = base + (len > 0 ? len - 1 : 0);
+        for (int j = 0; j < len; ++j) {
+            const V a = psi[base + j];
+            c += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+            if (c > q.residual) {
+                idx = base + j;
+                break;
+            }
+        }
+        out[shot] = idx;
+    }
+}
+
 } // namespace
+
+hipError_t launch_pauli_expect(const void* psi, int dt, int n, uint64_t x, uint64_t z, double* part,
+                               double* dev_out, hipStream_t st)
+{
+    const uint64_t nterms = x == 0 ? (1ull << n) : (1ull << (n - 1));
+    const int b = x == 0 ? 0 : __builtin_ctzll(x);
+    const uint64_t ch = 1ull << kChunkLog2;
+    const uint64_t nch = (nterms + ch - 1) / ch;
+    if (nch > 0x7fffffffull) return hipErrorInvalidValue;
+    if (dt == QS_C128)
+        hipLaunchKernelGGL(k_pauli_chunks<double2>, dim3((unsigned)nch), dim3(kRT), 0, st, (const double2*)psi,
+                           nterms, ch, nch, x, z, b, part);
+    else
+        hipLaunchKernelGGL(k_pauli_chunks<float2>, dim3((unsigned)nch), dim3(kRT), 0, st, (const float2*)psi,
+                           nterms, ch, nch, x, z, b, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prob_final, dim3(2), dim3(kRT), 0, st, part, nch, dev_out);
+    return hipGetLastError();
+}
+
+uint64_t pauli_scratch_doubles(int n) { return 2 * (((1ull << n) + 4095) / 4096) + 2; }
+
+hipError_t launch_sample_chunks(const void* psi, int dt, int n, const SampleReq* req, int64_t shots, uint64_t* out,
+                                hipStream_t st)
+{
+    if (shots <= 0) return hipSuccess;
+    const uint32_t csize = 1u << (n < kChunkLog2 ? n : kChunkLog2);
+    const int64_t g = (shots + kRT / 64 - 1) / (kRT / 64);
+    if (g > 0x7fffffffll) return hipErrorInvalidValue;
+    if (dt == QS_C128)
+        hipLaunchKernelGGL(k_sample_chunk<double2>, dim3((unsigned)g), dim3(kRT), 0, st, (const double2*)psi, csize,
+                           req, shots, out);
+    else
+        hipLaunchKernelGGL(k_sample_chunk<float2>, dim3((unsigned)g), dim3(kRT), 0, st, (const float2*)psi, csize,
+                           req, shots, out);
+    return hipGetLastError();
+}
 
 uint64_t reduce_scratch_doubles(int n, int m)
 {
