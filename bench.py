@@ -190,6 +190,32 @@ def _random_state_torch(torch, n, tdt, seed):
     return psi
 
 
+def diag_sweep(qs, s, n, S, reps=3, seed=13):
+    """CZ on (t, t+1) for t = 0..n-2 and CP(phi) with a seeded random control
+    on every target, through the diagonal kernel; each changes 2^(n-2)
+    amplitudes, so the algorithmic bytes are 2 S 2^(n-2) per gate."""
+    rng = np.random.default_rng(seed)
+    gates = [(t + 1, np.diag([1.0, -1.0]), 1 << t) for t in range(n - 1)]
+    for t in range(n):
+        c = int(rng.choice([q for q in range(n) if q != t]))
+        gates.append((t, np.diag([1.0, np.exp(1j * rng.uniform(0, 2 * np.pi))]), 1 << c))
+    qs.qs_trace_enable(s.h, True)
+    for _ in range(reps):
+        for t, u, cm in gates:
+            qs.qs_apply_1q(s.h, t, u, cm, cm)
+    recs = qs.qs_trace_read(s.h, 1 << 20)
+    qs.qs_trace_enable(s.h, False)
+    assert all(qs.KIND_NAMES[int(k)] == "diag" for k in recs["kind"])
+    by, ms = float(recs["bytes"].sum()), float(recs["ms"].sum())
+    return {"gates": len(gates), "reps": reps, "avg_ms": ms / len(recs),
+            "gbs_algorithmic": by / ms / 1e6, "frac": by / ms / 1e6 / PEAK_HBM_GBS,
+            "bytes_per_gate": 2 * S * (1 << (n - 2)),
+            "traffic": measured_traffic("diag", f"diag_sweep_n{n}_c{8 * S}", DIAG_SRCS),
+            "plain_path_bytes_per_gate": 2 * S * (1 << (n - 1)),
+            "note": "CZ on neighbouring pairs and CP with random controls; pairs with a qubit below the "
+                    "128-byte line (bit 3, complex128) read whole lines"}
+
+
 def run_sweep(a, qs, torch, W):
     n = a.n or 30
     dt = qs.QS_C128 if a.dtype == "c128" else qs.QS_C64
@@ -228,6 +254,7 @@ def run_sweep(a, qs, torch, W):
     recs = qs.qs_trace_read(s.h, 1 << 20)
     qs.qs_trace_enable(s.h, False)
     norm = s.norm()
+    diag = diag_sweep(qs, s, n, S) if a.mode == "pergate" else None
     s.close()
     kinds = _kinds(qs, recs)
     rl = _roofline(kinds)
@@ -247,6 +274,7 @@ def run_sweep(a, qs, torch, W):
                     for k, d in kinds.items()},
         "event_coverage": sum(d["ms"] for d in kinds.values()) / (elapsed * 1e3),
         "norm_minus_1": norm - 1.0,
+        "diag_sweep": diag,
     })
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline_sweep(a.cpu_n or 26)
@@ -605,10 +633,14 @@ def run_serve(a, qs, torch, W):
     return out
 
 
-def measured_traffic(kernel_class: str, tag: str):
+GATE_SRCS = ("paper_2506_09198_amd/csrc/gates.hip", "paper_2506_09198_amd/csrc/device_common.h")
+DIAG_SRCS = ("paper_2506_09198_amd/csrc/diag.hip", "paper_2506_09198_amd/csrc/device_common.h")
+
+
+def measured_traffic(kernel_class: str, tag: str, srcs=GATE_SRCS):
     """HBM bytes per launch of a kernel class from the committed rocprofv3
     counter summary, or None when the summary is missing or the kernel source
-    has changed since the counters were taken."""
+    (the files srcs) has changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{tag}_hbm_bytes.txt")
@@ -620,7 +652,6 @@ def measured_traffic(kernel_class: str, tag: str):
             rec = json.loads(line[len("TRAFFIC_JSON "):])
     if rec is None:
         return None
-    srcs = ["paper_2506_09198_amd/csrc/gates.hip", "paper_2506_09198_amd/csrc/device_common.h"]
     sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in srcs)).hexdigest()[:16]
     if sha != rec.get("src_sha"):
         return None

@@ -145,6 +145,21 @@ qs_status qs_apply_2q(qs_state s, int t0, int t1, const double* U,
 qs_status qs_apply_fused(qs_state s, const int* targets, int k, const double* U,
                          uint64_t ctrl_mask, uint64_t ctrl_vals);
 
+/* Diagonal gate on k distinct targets (1 <= k <= QS_MAX_FUSED): for every index
+ * i whose control bits match, psi[i] *= d[j], where bit b of j is bit
+ * targets[b] of i.  `diag` holds the 2^k complex entries (2^(k+1) doubles,
+ * interleaved re, im; host memory, read before the call returns).  A 128-byte
+ * line none of whose amplitudes has a factor other than exactly 1 is neither
+ * read nor written (the memory access filtering that Section I mentions as
+ * prior work); inside a touched line the unchanged amplitudes are written back
+ * bit for bit.  CZ and CP(phi) with both qubits at bit 3 or above (complex128;
+ * bit 4, complex64) touch a quarter of the state, a multi-controlled Z one
+ * line; all factors 1 launches nothing.
+ * qs_apply_1q, qs_apply_2q, qs_apply_fused and per-gate circuit runs take the
+ * same kernel whenever their matrix has no nonzero off-diagonal entry. */
+qs_status qs_apply_diag(qs_state s, const int* targets, int k, const double* diag,
+                        uint64_t ctrl_mask, uint64_t ctrl_vals);
+
 /* Execution options for qs_run_circuit.  Zero-initialised means defaults. */
 typedef struct {
     int32_t mode;        /* 0 = auto (fused tile passes), 1 = one launch per gate */
@@ -403,7 +418,7 @@ typedef struct {
 
 enum {
     QS_K_INIT = 0, QS_K_1Q_HI = 1, QS_K_1Q_LO = 2, QS_K_2Q = 3, QS_K_KQ = 4,
-    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7
+    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7, QS_K_DIAG = 8
 };
 
 /* Start (on != 0) or stop recording HIP events around every launch on the

@@ -23,7 +23,7 @@ QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_DEVICE, QS_ERR_BUSY, QS_ERR_UNSUPPORTED, Q
 QS_C64, QS_C128 = 1, 2
 QS_MAX_QUBITS = 34
 QS_MAX_FUSED = 6
-KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce"}
+KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce", 8: "diag"}
 
 TRACE_DTYPE = np.dtype([("kind", "<i4"), ("n", "<i4"), ("t0", "<i4"), ("t1", "<i4"), ("nctrl", "<i4"),
                         ("dtype", "<i4"), ("bytes", "<u8"), ("updates", "<u8"), ("ms", "<f4"),
@@ -108,6 +108,7 @@ def _load():
         "qs_apply_1q": ([vp, i32, dp, u64, u64], i32),
         "qs_apply_2q": ([vp, i32, i32, dp, u64, u64], i32),
         "qs_apply_fused": ([vp, ctypes.POINTER(i32), i32, dp, u64, u64], i32),
+        "qs_apply_diag": ([vp, ctypes.POINTER(i32), i32, dp, u64, u64], i32),
         "qs_run_circuit": ([vp, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts)], i32),
         "qs_plan_circuit": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
@@ -261,6 +262,19 @@ def qs_apply_fused(s: int, targets, U, ctrl_mask=0, ctrl_vals=None):
     f, p = _mat(U, len(t))
     _check(lib.qs_apply_fused(ctypes.c_void_p(s), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(t), p,
                               cm, cv))
+
+
+def qs_apply_diag(s: int, targets, diag, ctrl_mask=0, ctrl_vals=None):
+    """psi[i] *= diag[j] (bit b of j = bit targets[b] of i) where the controls match."""
+    t = np.ascontiguousarray(list(targets), dtype=np.int32)
+    d = np.ascontiguousarray(diag, dtype=np.complex128)
+    if d.shape != (1 << len(t),):
+        raise ValueError(f"diagonal shape {d.shape} != {(1 << len(t),)}")
+    cm = _mask(ctrl_mask)
+    cv = cm if ctrl_vals is None else _mask(ctrl_vals)
+    f = d.view(np.float64)
+    _check(lib.qs_apply_diag(ctypes.c_void_p(s), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(t),
+                             f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cm, cv))
 
 
 def qs_run_circuit(s: int, ops: np.ndarray, mats: np.ndarray, mode: int = 0, fuse_k: int = 0,
@@ -562,6 +576,9 @@ class State:
 
     def apply_fused(self, targets, U, controls=0, cvals=None):
         qs_apply_fused(self.h, targets, U, controls, cvals)
+
+    def apply_diag(self, targets, diag, controls=0, cvals=None):
+        qs_apply_diag(self.h, targets, diag, controls, cvals)
 
     def run(self, ops, mats, **kw):
         qs_run_circuit(self.h, ops, mats, **kw)

@@ -470,7 +470,11 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
                 const double* U = c.mats + op.moff;
                 int kind;
                 hipError_t err;
-                if (op.nt == 1)
+                DiagPlan dp;
+                if (diag_plan_matrix(c.n, op.t, op.nt, U, op.cmask, op.cvals, &dp)) {
+                    if (dp.identity) continue;
+                    err = launch_diag(psi, b->dt, dp, s);
+                } else if (op.nt == 1)
                     err = launch_apply_1q(psi, b->dt, c.n, op.t[0], U, op.cmask, op.cvals, s, &kind);
                 else if (op.nt == 2)
                     err = launch_apply_2q(psi, b->dt, c.n, op.t[0], op.t[1], U, op.cmask, op.cvals, s, &kind);

@@ -45,8 +45,13 @@ qs_status run_per_gate(qs_state s, const qs_op* ops, int64_t n_ops, const double
             st = apply_1q_internal(s, o.t[0], U, o.cmask, o.cvals);
         else if (o.nt == 2)
             st = apply_2q_internal(s, o.t[0], o.t[1], U, o.cmask, o.cvals);
-        else
-            st = apply_kq_dev_internal(s, o.t, o.nt, (const char*)dpool + o.moff * es, o.cmask, o.cvals);
+        else {
+            DiagPlan p;
+            if (diag_plan_matrix(s->n, o.t, o.nt, U, o.cmask, o.cvals, &p))
+                st = apply_diag_internal(s, p, o.t[0], o.t[1], o.cmask);
+            else
+                st = apply_kq_dev_internal(s, o.t, o.nt, (const char*)dpool + o.moff * es, o.cmask, o.cvals);
+        }
         if (st != QS_OK) return st;
     }
     return QS_OK;

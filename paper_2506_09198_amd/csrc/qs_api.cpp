@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -250,8 +251,25 @@ static qs_trace_rec make_rec(qs_state s, int t0, int t1, uint64_t cm)
     return r;
 }
 
+qs_status apply_diag_internal(qs_state s, const DiagPlan& p, int t0, int t1, uint64_t cm)
+{
+    if (p.identity) return QS_OK;
+    qs_trace_rec rec = make_rec(s, t0, t1, cm);
+    rec.updates = diag_changed(p);
+    rec.bytes = 2ull * amp_bytes(s->dt) * rec.updates;
+    return traced_launch(
+        s, rec,
+        [&](int* kind) {
+            *kind = QS_K_DIAG;
+            return launch_diag(s->d, s->dt, p, s->st);
+        },
+        "diagonal gate launch");
+}
+
 qs_status apply_1q_internal(qs_state s, int target, const double* U, uint64_t cm, uint64_t cv)
 {
+    DiagPlan p;
+    if (diag_plan_matrix(s->n, &target, 1, U, cm, cv, &p)) return apply_diag_internal(s, p, target, -1, cm);
     return traced_launch(
         s, make_rec(s, target, -1, cm),
         [&](int* kind) { return launch_apply_1q(s->d, s->dt, s->n, target, U, cm, cv, s->st, kind); },
@@ -260,6 +278,9 @@ qs_status apply_1q_internal(qs_state s, int target, const double* U, uint64_t cm
 
 qs_status apply_2q_internal(qs_state s, int t0, int t1, const double* U, uint64_t cm, uint64_t cv)
 {
+    DiagPlan p;
+    const int t[2] = {t0, t1};
+    if (diag_plan_matrix(s->n, t, 2, U, cm, cv, &p)) return apply_diag_internal(s, p, t0, t1, cm);
     return traced_launch(
         s, make_rec(s, t0, t1, cm),
         [&](int* kind) { return launch_apply_2q(s->d, s->dt, s->n, t0, t1, U, cm, cv, s->st, kind); },
@@ -472,9 +493,25 @@ qs_status qs_apply_fused(qs_state s, const int* targets, int k, const double* U,
     if (st != QS_OK) return st;
     if (!U || !targets) return set_err(QS_ERR_ARG, "null matrix or target list");
     if ((st = validate_gate(s->n, targets, k, cm, cv)) != QS_OK) return st;
+    DiagPlan p;
+    if (diag_plan_matrix(s->n, targets, k, U, cm, cv, &p))
+        return apply_diag_internal(s, p, targets[0], k > 1 ? targets[1] : -1, cm);
     const void* Ud = nullptr;
     if ((st = stage_bytes(s, U, (2ull << (2 * k)) * sizeof(double), &Ud)) != QS_OK) return st;
     return apply_kq_dev_internal(s, targets, k, Ud, cm, cv);
+}
+
+qs_status qs_apply_diag(qs_state s, const int* targets, int k, const double* diag, uint64_t cm, uint64_t cv)
+{
+    qs_status st = check_live(s);
+    if (st != QS_OK) return st;
+    if (!diag || !targets) return set_err(QS_ERR_ARG, "null diagonal or target list");
+    if ((st = validate_gate(s->n, targets, k, cm, cv)) != QS_OK) return st;
+    for (int j = 0; j < (2 << k); ++j)
+        if (!std::isfinite(diag[j])) return set_err(QS_ERR_ARG, "diagonal entry %d is not finite", j / 2);
+    DiagPlan p;
+    if (!diag_plan(s->n, targets, k, diag, cm, cv, &p)) return set_err(QS_ERR_ARG, "k=%d not supported", k);
+    return apply_diag_internal(s, p, targets[0], k > 1 ? targets[1] : -1, cm);
 }
 
 qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out)

@@ -41,6 +41,27 @@ hipError_t launch_apply_2q(void* psi, int dt, int n, int t0, int t1, const doubl
 hipError_t launch_apply_kq_dev(void* psi, int dt, int n, const int* targets, int k, const void* Ud,
                                uint64_t cm, uint64_t cv, hipStream_t st, int* kind);
 
+// Diagonal gates (phase-only kernel).  diag_plan folds the controls into the
+// diagonal d (2^k complex entries, entry j bit b = target t[b]) and finds the
+// fixed bits shared by every amplitude the gate changes; diag_plan_matrix
+// does the same for a dense 2^k x 2^k matrix and returns false when it has a
+// nonzero off-diagonal entry.
+constexpr int kDiagMaxFree = 6;
+struct DiagPlan {
+    bool identity;          // every factor is exactly 1: nothing to launch
+    int n, k, nctrl;
+    uint64_t changed_per;   // diagonal entries that differ from 1
+    uint64_t fixed_mask, fixed_val;
+    int nfree;
+    int fpos[kDiagMaxFree]; // qubit of free bit i
+    int fbit[kDiagMaxFree]; // matrix bit of free bit i
+    double tab[2 << kDiagMaxFree];
+};
+bool diag_plan(int n, const int* t, int k, const double* d, uint64_t cm, uint64_t cv, DiagPlan* p);
+bool diag_plan_matrix(int n, const int* t, int k, const double* U, uint64_t cm, uint64_t cv, DiagPlan* p);
+uint64_t diag_changed(const DiagPlan& p); // amplitudes the gate changes
+hipError_t launch_diag(void* psi, int dt, const DiagPlan& p, hipStream_t st);
+
 // Reductions.  `part` is device scratch of at least reduce_scratch_doubles()
 // doubles.  Results land in `dev_out` (device, 2^m doubles).
 // Pauli-string expectation: part needs pauli_scratch_doubles(n); dev_out

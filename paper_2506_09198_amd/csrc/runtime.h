@@ -58,5 +58,6 @@ bool inject_fault_now();
 qs_status apply_1q_internal(qs_state s, int target, const double* U, uint64_t cm, uint64_t cv);
 qs_status apply_2q_internal(qs_state s, int t0, int t1, const double* U, uint64_t cm, uint64_t cv);
 qs_status apply_kq_dev_internal(qs_state s, const int* t, int k, const void* Ud, uint64_t cm, uint64_t cv);
+qs_status apply_diag_internal(qs_state s, const DiagPlan& p, int t0, int t1, uint64_t cm);
 
 } // namespace qs
