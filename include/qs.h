@@ -169,7 +169,12 @@ typedef struct {
                             the tiles); 0 = default (2048).  A lower cap leaves compute units
                             to other streams, e.g. a serving loop beside a long run, at the
                             cost of this run's speed */
-    int32_t rsv[4];
+    int32_t remap;       /* 0 = auto: an uncontrolled SWAP gate becomes a relabeling of qubits
+                            (later gates are rewritten to the swapped positions) when that saves
+                            tile passes, and the qubit order is restored at the end by at most
+                            two in-place passes (the swap-shifted QFT of Section III-B);
+                            1 = never: SWAP gates run as 2q gates */
+    int32_t rsv[3];
 } qs_run_opts;
 
 /* Apply a whole circuit (ops[0..n_ops), matrices in mats[0..n_mats)) in
@@ -180,15 +185,16 @@ qs_status qs_run_circuit(qs_state s, const qs_op* ops, int64_t n_ops,
                          const double* mats, int64_t n_mats, const qs_run_opts* opts);
 
 /* Plan a circuit for an n-qubit state of type dt without executing it (host
- * only; needs no GPU).  *n_passes receives the number of LDS tile passes
- * (state read+write sweeps) qs_run_circuit would launch in mode 0, and
- * *n_ops_out the total operations inside them (a fused block counts once).
+ * only; needs no GPU).  *n_passes receives the number of state read+write
+ * sweeps qs_run_circuit would launch in mode 0 (LDS tile passes plus the
+ * passes that restore the qubit order after SWAP relabeling), and *n_ops_out
+ * the total operations inside the tile passes (a fused block counts once).
  * Same validation as qs_run_circuit. */
 qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
                           int64_t n_mats, const qs_run_opts* opts, int64_t* n_passes, int64_t* n_ops_out);
 
-/* The execution order qs_run_circuit (mode 0, no fused blocks) gives the
- * circuit's gates (host only; needs no GPU).  Gates that commute (neither
+/* The execution order qs_run_circuit (mode 0, no fused blocks, no SWAP
+ * relabeling) gives the circuit's gates (host only; needs no GPU).  Gates that commute (neither
  * acts non-diagonally on a qubit the other touches; controls act
  * diagonally) may be reordered so that one tile pass absorbs more of them.
  * order[i] is the circuit index of the i-th gate executed and pass_of[i] its
@@ -200,7 +206,9 @@ qs_status qs_plan_order(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, con
                         uint64_t* tile_mask);
 
 /* The tile passes qs_run_circuit (mode 0) would launch, for inspection and
- * for checking the planner on a host (host only; needs no GPU).  Call once
+ * for checking the planner on a host (host only; needs no GPU).  Their qubit
+ * positions are physical: after SWAP relabeling, qs_plan_restore gives the
+ * passes that follow them.  Call once
  * with pass_desc, ops_out and pool_out NULL to get *n_passes, *n_tile_ops
  * and *n_pool; then again with buffers of at least those sizes (the three
  * counts in, the actual counts out).  pass_desc: 36 int32 per pass: tile
@@ -215,6 +223,16 @@ qs_status qs_plan_order(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, con
 qs_status qs_plan_export(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
                          int64_t n_mats, const qs_run_opts* opts, int32_t* pass_desc, int64_t* n_passes,
                          void* ops_out, int64_t* n_tile_ops, double* pool_out, int64_t* n_pool);
+
+/* The passes qs_run_circuit (mode 0) launches after the tile passes to put the
+ * qubits back in order when the planner relabeled SWAP gates (host only).
+ * *n_restore (0, 1 or 2) passes; pass i is an involution of bit positions
+ * given as tau[64 i + p] = the position that position p exchanges with (p
+ * itself if unmoved, p < n); it swaps psi[y] with psi[y'] where y' is y with
+ * the bits at each exchanged pair of positions swapped.  tau: room for 128
+ * int32 (caller-owned).  Same validation as qs_run_circuit. */
+qs_status qs_plan_restore(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                          int64_t n_mats, const qs_run_opts* opts, int32_t* tau, int32_t* n_restore);
 
 /* ------------------------------------------------------------------ reductions */
 
@@ -418,7 +436,7 @@ typedef struct {
 
 enum {
     QS_K_INIT = 0, QS_K_1Q_HI = 1, QS_K_1Q_LO = 2, QS_K_2Q = 3, QS_K_KQ = 4,
-    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7, QS_K_DIAG = 8
+    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7, QS_K_DIAG = 8, QS_K_PERM = 9
 };
 
 /* Start (on != 0) or stop recording HIP events around every launch on the

@@ -23,7 +23,7 @@ QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_DEVICE, QS_ERR_BUSY, QS_ERR_UNSUPPORTED, Q
 QS_C64, QS_C128 = 1, 2
 QS_MAX_QUBITS = 34
 QS_MAX_FUSED = 6
-KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce", 8: "diag"}
+KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce", 8: "diag", 9: "perm"}
 
 TRACE_DTYPE = np.dtype([("kind", "<i4"), ("n", "<i4"), ("t0", "<i4"), ("t1", "<i4"), ("nctrl", "<i4"),
                         ("dtype", "<i4"), ("bytes", "<u8"), ("updates", "<u8"), ("ms", "<f4"),
@@ -77,7 +77,7 @@ class _ServerStats(ctypes.Structure):
 
 class _RunOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32),
-                ("max_blocks", ctypes.c_int32), ("rsv", ctypes.c_int32 * 4)]
+                ("max_blocks", ctypes.c_int32), ("remap", ctypes.c_int32), ("rsv", ctypes.c_int32 * 3)]
 
 
 def _load():
@@ -114,6 +114,8 @@ def _load():
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], i32),
         "qs_plan_order": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(u64)], i32),
+        "qs_plan_restore": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
+                             ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "qs_plan_export": ([i32, i32, vp, ctypes.c_int64, dp, ctypes.c_int64, ctypes.POINTER(_RunOpts),
                             ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64), vp, ctypes.POINTER(ctypes.c_int64),
                             dp, ctypes.POINTER(ctypes.c_int64)], i32),
@@ -278,22 +280,22 @@ def qs_apply_diag(s: int, targets, diag, ctrl_mask=0, ctrl_vals=None):
 
 
 def qs_run_circuit(s: int, ops: np.ndarray, mats: np.ndarray, mode: int = 0, fuse_k: int = 0,
-                   tile_qubits: int = 0, max_blocks: int = 0):
+                   tile_qubits: int = 0, max_blocks: int = 0, remap: int = 0):
     ops = np.ascontiguousarray(ops)
     if ops.dtype.itemsize != 64:
         raise ValueError("ops must be 64-byte records (workloads.OP_DTYPE)")
     mats = np.ascontiguousarray(mats, dtype=np.float64)
-    o = _RunOpts(mode, fuse_k, tile_qubits, max_blocks)
+    o = _RunOpts(mode, fuse_k, tile_qubits, max_blocks, remap)
     _check(lib.qs_run_circuit(ctypes.c_void_p(s), ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
                               mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o)))
 
 
 def qs_plan_circuit(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, mode: int = 0, fuse_k: int = 0,
-                    tile_qubits: int = 0):
-    """Host-only planning: returns (passes, ops inside passes)."""
+                    tile_qubits: int = 0, remap: int = 0):
+    """Host-only planning: returns (state passes incl. restoring ones, ops inside tile passes)."""
     ops = np.ascontiguousarray(ops)
     mats = np.ascontiguousarray(mats, dtype=np.float64)
-    o = _RunOpts(mode, fuse_k, tile_qubits)
+    o = _RunOpts(mode, fuse_k, tile_qubits, 0, remap)
     npass, nops = ctypes.c_int64(), ctypes.c_int64()
     _check(lib.qs_plan_circuit(n, dtype, ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
                                mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o),
@@ -325,12 +327,29 @@ TILE_OP_DTYPE = np.dtype([("kind", "<i4"), ("k", "<i4"), ("p", "<i4", (6,)), ("l
 assert TILE_OP_DTYPE.itemsize == 88
 
 
-def qs_plan_export(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_qubits: int = 0, fuse_k: int = 0):
-    """Host-only: (passes, tile_ops, pool) as planned for mode 0.  passes is a
-    list of dicts {m, L, op0, nops, Q}."""
+def qs_plan_restore(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_qubits: int = 0, fuse_k: int = 0,
+                    remap: int = 0):
+    """Host-only: the qubit-order restoring involutions run after the tile
+    passes (a list of 0-2 arrays tau, tau[p] = the position p exchanges with)."""
     ops = np.ascontiguousarray(ops)
     mats = np.ascontiguousarray(mats, dtype=np.float64)
-    o = _RunOpts(0, fuse_k, tile_qubits)
+    o = _RunOpts(0, fuse_k, tile_qubits, 0, remap)
+    tau = np.zeros(128, dtype=np.int32)
+    nr = ctypes.c_int32(0)
+    _check(lib.qs_plan_restore(n, dtype, ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
+                               mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o),
+                               tau.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nr)))
+    return [tau[64 * i:64 * i + n].copy() for i in range(nr.value)]
+
+
+def qs_plan_export(n: int, dtype: int, ops: np.ndarray, mats: np.ndarray, tile_qubits: int = 0, fuse_k: int = 0,
+                   remap: int = 0):
+    """Host-only: (passes, tile_ops, pool) as planned for mode 0.  passes is a
+    list of dicts {m, L, op0, nops, Q}; qubit positions are physical (see
+    qs_plan_restore)."""
+    ops = np.ascontiguousarray(ops)
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    o = _RunOpts(0, fuse_k, tile_qubits, 0, remap)
     np_, nt, npool = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     args = (n, dtype, ctypes.c_void_p(ops.ctypes.data if len(ops) else 0), len(ops),
             mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), mats.size, ctypes.byref(o))

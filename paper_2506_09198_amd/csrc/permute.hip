@@ -1,0 +1,123 @@
+// In-place permutation of qubit positions by an involution.
+//
+// When the planner turns SWAP gates into a relabeling of qubits (the
+// swap-shifted form of the blocked QFT, Section III-B), the state ends with
+// its qubits at permuted bit positions.  Any permutation of bit positions is
+// the product of two involutions, and an involution tau (disjoint pairs of
+// positions) induces an involution on amplitude indices: sigma(y) exchanges
+// the bits of y at each pair.  One pass per involution restores the order.
+//
+// Pairing a low bit with a high one (QFT pairs bit 0 with bit n-1) would
+// scatter a wave's partner accesses over the whole state, so the pass works
+// on tiles.  T = {0..K-1} together with the partners of those bits is closed
+// under tau; a tile holds the 2^|T| amplitudes that share their bits outside
+// T.  The pairs outside T map tile t to tile t' = sigma_out(t), the pairs
+// inside permute within a tile: new[t', sigma_in(u)] = old[t, u].  A
+// workgroup loads tiles t and t' (runs of 2^K consecutive amplitudes) into
+// LDS and writes each back permuted into the other, so every access is
+// coalesced and each amplitude is read and written once.
+#include <cstring>
+
+#include "device_common.h"
+
+namespace qs {
+
+namespace {
+
+constexpr int kLowRun = 5;            // K: consecutive amplitudes per run
+constexpr int kMaxT = 2 * kLowRun;    // |T| <= 2K
+constexpr int kMaxPairs = 32;
+
+struct InvArgs {
+    uint64_t ntiles;                  // 2^(n - |T|)
+    int32_t nt;                       // |T|
+    int32_t tpos[kMaxT];              // positions of T, ascending (the first K are 0..K-1)
+    int32_t sin_[kMaxT];              // compact bit j of a tile index -> compact bit sin_[j]
+    int32_t np;                       // pairs outside T
+    int32_t pa[kMaxPairs], pb[kMaxPairs];
+    InsertPlan ip;                    // the positions of T, inserted into the tile counter
+};
+
+template <typename V>
+__global__ void __launch_bounds__(256) k_bit_involution(V* __restrict__ psi, InvArgs a)
+{
+    __shared__ V la[1 << kMaxT], lb[1 << kMaxT];
+    const int E = 1 << a.nt;
+    auto deposit = [&](int u) {
+        uint64_t off = (uint64_t)(u & ((1 << kLowRun) - 1)) & (((uint64_t)1 << a.nt) - 1);
+        for (int j = kLowRun; j < a.nt; ++j) off |= (uint64_t)((u >> j) & 1) << a.tpos[j];
+        return off;
+    };
+    auto sigma_in = [&](int u) {
+        int v = 0;
+        for (int j = 0; j < a.nt; ++j) v |= ((u >> j) & 1) << a.sin_[j];
+        return v;
+    };
+    for (uint64_t b = blockIdx.x; b < a.ntiles; b += gridDim.x) {
+        const uint64_t t = ins_bits(b, a.ip);
+        uint64_t t2 = t;
+        for (int i = 0; i < a.np; ++i)
+            if (((t >> a.pa[i]) ^ (t >> a.pb[i])) & 1) t2 ^= (1ull << a.pa[i]) | (1ull << a.pb[i]);
+        if (t2 < t) continue; // the block of tile t2 does this pair (same decision for the whole block)
+        for (int u = threadIdx.x; u < E; u += 256) {
+            const uint64_t off = deposit(u);
+            la[u] = psi[t | off];
+            if (t2 != t) lb[u] = psi[t2 | off];
+        }
+        __syncthreads();
+        for (int u = threadIdx.x; u < E; u += 256) {
+            const uint64_t off = deposit(u);
+            const int su = sigma_in(u);
+            psi[t2 | off] = la[su];
+            if (t2 != t) psi[t | off] = lb[su];
+        }
+        __syncthreads();
+    }
+}
+
+} // namespace
+
+uint64_t involution_moved(int n, const int* tau)
+{
+    int np = 0;
+    for (int p = 0; p < n; ++p)
+        if (tau[p] > p) ++np;
+    return (1ull << n) - (1ull << (n - np)); // indices whose bits differ at some pair
+}
+
+hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipStream_t st)
+{
+    for (int p = 0; p < n; ++p)
+        if (tau[p] < 0 || tau[p] >= n || tau[tau[p]] != p) return hipErrorInvalidValue;
+    bool id = true;
+    for (int p = 0; p < n; ++p) id &= tau[p] == p;
+    if (id) return hipSuccess;
+    InvArgs a;
+    std::memset(&a, 0, sizeof a);
+    const int K = n < kLowRun ? n : kLowRun;
+    uint64_t T = 0;
+    for (int p = 0; p < K; ++p) T |= (1ull << p) | (1ull << tau[p]);
+    int pos_to_j[64];
+    for (int p = 0; p < n; ++p)
+        if ((T >> p) & 1) {
+            pos_to_j[p] = a.nt;
+            a.tpos[a.nt++] = p;
+        }
+    for (int j = 0; j < a.nt; ++j) a.sin_[j] = pos_to_j[tau[a.tpos[j]]];
+    for (int p = 0; p < n; ++p)
+        if (!((T >> p) & 1) && tau[p] > p) {
+            a.pa[a.np] = p;
+            a.pb[a.np] = tau[p];
+            a.np++;
+        }
+    a.ip = make_insert_plan(T);
+    a.ntiles = 1ull << (n - a.nt);
+    const unsigned g = (unsigned)(a.ntiles < (1ull << 20) ? a.ntiles : (1ull << 20));
+    if (dt == QS_C128)
+        hipLaunchKernelGGL(k_bit_involution<double2>, dim3(g), dim3(256), 0, st, (double2*)psi, a);
+    else
+        hipLaunchKernelGGL(k_bit_involution<float2>, dim3(g), dim3(256), 0, st, (float2*)psi, a);
+    return hipGetLastError();
+}
+
+} // namespace qs

@@ -872,6 +872,96 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
     }
 }
 
+static bool is_swap(const qs_op& o, const double* U)
+{
+    if (o.nt != 2 || o.cmask != 0) return false;
+    static const double S[32] = {1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0,
+                                 0, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 0};
+    for (int i = 0; i < 32; ++i)
+        if (U[i] != S[i]) return false;
+    return true;
+}
+
+bool remap_swaps(int n, const qs_op* ops, int64_t n_ops, const double* mats, Remap& r)
+{
+    bool any = false;
+    for (int64_t g = 0; g < n_ops && !any; ++g) any = is_swap(ops[g], mats + ops[g].moff);
+    if (!any) return false;
+    int perm[64]; // logical qubit -> bit position holding it
+    for (int q = 0; q < 64; ++q) perm[q] = q;
+    auto map_bits = [&](uint64_t bits) {
+        uint64_t out = 0;
+        for (; bits; bits &= bits - 1) out |= 1ull << perm[__builtin_ctzll(bits)];
+        return out;
+    };
+    r.ops.clear();
+    r.src.clear();
+    for (int64_t g = 0; g < n_ops; ++g) {
+        const qs_op& o = ops[g];
+        if (is_swap(o, mats + o.moff)) {
+            std::swap(perm[o.t[0]], perm[o.t[1]]);
+            continue;
+        }
+        qs_op m = o;
+        for (int j = 0; j < o.nt; ++j) m.t[j] = perm[o.t[j]];
+        m.cmask = map_bits(o.cmask);
+        m.cvals = map_bits(o.cvals);
+        r.ops.push_back(m);
+        r.src.push_back(g);
+    }
+    // restoring permutation rho: position perm[q] -> q, as tau[1] o tau[0].
+    // For a cycle c_0 -> c_1 -> ... -> c_{k-1} of rho, tau0(c_i) = c_{-i} and
+    // tau1(c_i) = c_{1-i} (indices mod k) are involutions with
+    // tau1(tau0(c_i)) = c_{i+1}.
+    int rho[64], t0[64], t1[64];
+    for (int q = 0; q < n; ++q) rho[perm[q]] = q;
+    for (int p = 0; p < 64; ++p) t0[p] = t1[p] = p;
+    bool seen[64] = {false};
+    for (int p0 = 0; p0 < n; ++p0) {
+        if (seen[p0]) continue;
+        int c[64], k = 0;
+        for (int p = p0; !seen[p]; p = rho[p]) {
+            seen[p] = true;
+            c[k++] = p;
+        }
+        for (int i = 0; i < k; ++i) {
+            t0[c[i]] = c[(k - i) % k];
+            t1[c[i]] = c[(k + 1 - i) % k];
+        }
+    }
+    r.nrestore = 0;
+    for (const int* t : {t0, t1}) {
+        bool id = true;
+        for (int p = 0; p < n; ++p) id &= t[p] == p;
+        if (!id) std::memcpy(r.tau[r.nrestore++], t, sizeof t0);
+    }
+    return true;
+}
+
+void plan_circuit_remap(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po, int remap,
+                        std::vector<PlanPass>& passes, std::vector<double>& pool, Remap& r)
+{
+    r.nrestore = 0;
+    plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+    // QS_REMAP_ALWAYS=1 relabels whenever there is a SWAP gate (for tests)
+    const bool always = env_int("QS_REMAP_ALWAYS", 0) != 0;
+    Remap rr;
+    if (remap != 0 || (passes.size() <= 1 && !always) || !remap_swaps(n, ops, n_ops, mats, rr)) return;
+    std::vector<PlanPass> p2;
+    std::vector<double> pool2;
+    if (!rr.ops.empty()) plan_circuit(n, rr.ops.data(), (int64_t)rr.ops.size(), mats, po, p2, pool2);
+    if (!always && (double)p2.size() + 0.5 * rr.nrestore >= (double)passes.size()) return;
+    for (PlanPass& P : p2) {
+        for (int64_t& g : P.src)
+            if (g >= 0) g = rr.src[(size_t)g];
+        for (int64_t& g : P.order)
+            if (g >= 0) g = rr.src[(size_t)g];
+    }
+    passes.swap(p2);
+    pool.swap(pool2);
+    r = std::move(rr);
+}
+
 static int default_tile_qubits(int dt)
 {
     const int e = env_int("QS_TILE_QUBITS", 0);
@@ -916,9 +1006,11 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
     PlanOpts po;
     qs_status pst = plan_opts(s->dt, ops, n_ops, o, po);
     if (pst != QS_OK) return pst;
+    if (o.remap != 0 && o.remap != 1) return set_err(QS_ERR_ARG, "remap=%d is not 0 or 1", o.remap);
     std::vector<PlanPass> passes;
     std::vector<double> pool;
-    plan_circuit(s->n, ops, n_ops, mats, po, passes, pool);
+    Remap rm;
+    plan_circuit_remap(s->n, ops, n_ops, mats, po, o.remap, passes, pool, rm);
 
     // One staging copy: every pass's op table, then the FP64 matrix pool.
     size_t nops_total = 0;
@@ -957,6 +1049,23 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
         if (st != QS_OK) return st;
         op0 += p.ops.size();
     }
+    for (int i = 0; i < rm.nrestore; ++i) {
+        qs_trace_rec rec;
+        std::memset(&rec, 0, sizeof rec);
+        rec.n = s->n;
+        rec.t0 = rec.t1 = -1;
+        rec.dtype = s->dt;
+        rec.bytes = 2ull * amp_bytes(s->dt) * involution_moved(s->n, rm.tau[i]);
+        const int* tau = rm.tau[i];
+        st = traced_launch(
+            s, rec,
+            [&](int* kind) {
+                *kind = QS_K_PERM;
+                return launch_bit_involution(s->d, s->dt, s->n, tau, s->st);
+            },
+            "qubit order restore launch");
+        if (st != QS_OK) return st;
+    }
     return QS_OK;
 }
 
@@ -977,13 +1086,15 @@ extern "C" qs_status qs_plan_circuit(int n, qs_dtype dt, const qs_op* ops, int64
     if (opts) o = *opts;
     PlanOpts po;
     if ((st = plan_opts(dt, ops, n_ops, o, po)) != QS_OK) return st;
+    if (o.remap != 0 && o.remap != 1) return set_err(QS_ERR_ARG, "remap=%d is not 0 or 1", o.remap);
     std::vector<PlanPass> passes;
     std::vector<double> pool;
-    if (n_ops > 0) plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+    Remap rm;
+    if (n_ops > 0) plan_circuit_remap(n, ops, n_ops, mats, po, o.remap, passes, pool, rm);
     int64_t c = 0; // segment headers are bookkeeping, not operations
     for (auto& p : passes)
         for (auto& t : p.ops) c += t.kind != TK_SEG;
-    *n_passes = (int64_t)passes.size();
+    *n_passes = (int64_t)passes.size() + rm.nrestore;
     *n_ops_out = c;
     return QS_OK;
 }
@@ -1038,9 +1149,11 @@ extern "C" qs_status qs_plan_export(int n, qs_dtype dt, const qs_op* ops, int64_
     if (opts) o = *opts;
     PlanOpts po;
     if ((st = plan_opts(dt, ops, n_ops, o, po)) != QS_OK) return st;
+    if (o.remap != 0 && o.remap != 1) return set_err(QS_ERR_ARG, "remap=%d is not 0 or 1", o.remap);
     std::vector<PlanPass> passes;
     std::vector<double> pool;
-    if (n_ops > 0) plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+    Remap rm;
+    if (n_ops > 0) plan_circuit_remap(n, ops, n_ops, mats, po, o.remap, passes, pool, rm);
     int64_t total = 0;
     for (auto& p : passes) total += (int64_t)p.ops.size();
     const bool fill = pass_desc && ops_out && pool_out;
@@ -1064,5 +1177,30 @@ extern "C" qs_status qs_plan_export(int n, qs_dtype dt, const qs_op* ops, int64_
     *n_passes = (int64_t)passes.size();
     *n_tile_ops = total;
     *n_pool = (int64_t)pool.size();
+    return QS_OK;
+}
+
+extern "C" qs_status qs_plan_restore(int n, qs_dtype dt, const qs_op* ops, int64_t n_ops, const double* mats,
+                                    int64_t n_mats, const qs_run_opts* opts, int32_t* tau, int32_t* n_restore)
+{
+    using namespace qs;
+    if (!tau || !n_restore) return set_err(QS_ERR_ARG, "null output");
+    if (n < 1 || n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "n=%d outside [1, %d]", n, QS_MAX_QUBITS);
+    if (dt != QS_C64 && dt != QS_C128) return set_err(QS_ERR_ARG, "unknown dtype %d", (int)dt);
+    qs_status st = validate_circuit(n, ops, n_ops, mats, n_mats);
+    if (st != QS_OK) return st;
+    qs_run_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    PlanOpts po;
+    if ((st = plan_opts(dt, ops, n_ops, o, po)) != QS_OK) return st;
+    if (o.remap != 0 && o.remap != 1) return set_err(QS_ERR_ARG, "remap=%d is not 0 or 1", o.remap);
+    std::vector<PlanPass> passes;
+    std::vector<double> pool;
+    Remap rm;
+    if (n_ops > 0) plan_circuit_remap(n, ops, n_ops, mats, po, o.remap, passes, pool, rm);
+    for (int i = 0; i < 2; ++i)
+        for (int p = 0; p < 64; ++p) tau[64 * i + p] = (i < rm.nrestore && p < n) ? rm.tau[i][p] : p;
+    *n_restore = rm.nrestore;
     return QS_OK;
 }

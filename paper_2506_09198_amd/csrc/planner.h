@@ -123,6 +123,30 @@ struct PlanOpts {
 void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po,
                   std::vector<PlanPass>& passes, std::vector<double>& mats_out);
 
+// Qubit relabeling.  An uncontrolled SWAP gate exchanges two qubits' values;
+// instead of moving amplitudes, the planner can record that the two logical
+// qubits now live at each other's bit positions and rewrite every later gate
+// to the physical positions.  The state then ends with logical qubit q at
+// position perm[q]; the restoring permutation of bit positions (position
+// perm[q] -> q) is the product of at most two involutions tau[0], tau[1]
+// (position maps, applied in that order), each one in-place pass.
+struct Remap {
+    std::vector<qs_op> ops;   // the circuit without its SWAP gates, on physical qubits
+    std::vector<int64_t> src; // index of each in the original circuit
+    int nrestore = 0;
+    int tau[2][64];
+};
+// False (and r untouched) when the circuit has no uncontrolled SWAP gate.
+bool remap_swaps(int n, const qs_op* ops, int64_t n_ops, const double* mats, Remap& r);
+// Plan with relabeling when its tile passes plus half a pass per restoring
+// involution are fewer than the plain plan's (remap = 0), or never (remap =
+// 1).  r.nrestore = 0 when the plain plan is kept; P.src and P.order index the
+// original circuit either way.
+void plan_circuit_remap(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po, int remap,
+                        std::vector<PlanPass>& passes, std::vector<double>& mats_out, Remap& r);
+hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipStream_t st);
+uint64_t involution_moved(int n, const int* tau); // amplitudes one restoring pass moves
+
 // Run fn(i) for i in [0, n) on up to 16 host threads (independent items,
 // e.g. the circuits of a batch, which are planned one per call).
 template <typename F>

@@ -44,11 +44,11 @@ def _random_mixed(n, count, seed):
 def _circuits():
     return [W.random_u3_cnot(9, 150, seed=3), W.rqc_chain(10, 8, 4), W.qft(9, 300), W.grover(8, 77),
             _random_mixed(9, 160, 5), _random_mixed(10, 200, 6), _random_mixed(12, 250, 7), W.rqc_chain(12, 10, 8),
-            W.rqc_chain(13, 2, 632), W.rqc_chain(12, 3, 2)]
+            W.rqc_chain(13, 2, 632), W.rqc_chain(12, 3, 2), W.swap_network(11, 120, 9)]
 
 
 @pytest.mark.parametrize("tq,low", [(4, 2), (5, 3), (6, 0), (10, 3), (11, 5)])
-@pytest.mark.parametrize("ci", range(10))
+@pytest.mark.parametrize("ci", range(11))
 def test_planned_order_matches_oracle(qs, monkeypatch, ci, tq, low):
     monkeypatch.setenv("QS_TILE_LOW", str(low))
     c = _circuits()[ci]
@@ -56,7 +56,7 @@ def test_planned_order_matches_oracle(qs, monkeypatch, ci, tq, low):
     order, pass_of, masks = qs.qs_plan_order(c.n, qs.QS_C128, ops, mats, tile_qubits=tq)
     assert sorted(order.tolist()) == list(range(len(ops)))
     assert np.all(np.diff(pass_of) >= 0)
-    assert len(masks) == qs.qs_plan_circuit(c.n, qs.QS_C128, ops, mats, tile_qubits=tq)[0]
+    assert len(masks) == qs.qs_plan_circuit(c.n, qs.QS_C128, ops, mats, tile_qubits=tq, remap=1)[0]
     for g, p in zip(order, pass_of):
         o = ops[g]
         dense = not np.allclose(np.diag(np.diag(c.gates[g][1])), c.gates[g][1], atol=0, rtol=0)
@@ -107,11 +107,12 @@ def test_noncommuting_swap_is_detected():
 
 @pytest.mark.parametrize("dt", [1, 2])
 @pytest.mark.parametrize("tq,low", [(10, 5), (11, 6), (12, 5), (13, 6), (0, 5)])
-@pytest.mark.parametrize("ci", range(10))
+@pytest.mark.parametrize("ci", range(11))
 def test_encoded_plan_matches_oracle(qs, monkeypatch, ci, tq, low, dt):
     """The planner's encoded passes (segments, fused register blocks, the
-    diagonal forms), executed by a host model of the tile kernels, give the
-    oracle's state; tile sizes up to the whole state (tq = 0: tile = n)."""
+    diagonal forms) and restoring passes, executed by a host model of the
+    kernels, give the oracle's state; tile sizes up to the whole state (tq =
+    0: tile = n)."""
     from tests.tile_model import run_plan
 
     monkeypatch.setenv("QS_TILE_LOW", str(low))
@@ -119,6 +120,70 @@ def test_encoded_plan_matches_oracle(qs, monkeypatch, ci, tq, low, dt):
     t = c.n if tq == 0 else tq
     ops, mats = c.arrays()
     passes, tops, pool = qs.qs_plan_export(c.n, dt, ops, mats, tile_qubits=t)
-    got = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis))
+    restore = qs.qs_plan_restore(c.n, dt, ops, mats, tile_qubits=t)
+    got = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis), restore)
     ref = oracle.run_circuit(c)
     assert float(np.max(np.abs(got - ref))) <= 1e-12
+
+
+def _swap_circuits():
+    return [W.qft(9, 300), W.qft(12, 1234), W.swap_network(11, 120, 9), W.swap_network(12, 200, 10),
+            W.swap_network(7, 60, 11)]
+
+
+@pytest.mark.parametrize("dt", [1, 2])
+@pytest.mark.parametrize("tq,low", [(4, 2), (6, 3), (10, 5), (11, 6)])
+@pytest.mark.parametrize("ci", range(5))
+def test_relabeled_plan_matches_oracle(qs, monkeypatch, ci, tq, low, dt):
+    """With every uncontrolled SWAP turned into a relabeling (forced), the
+    passes on physical positions followed by the restoring involutions give
+    the oracle's state, and the plan has no SWAP left in it."""
+    from tests.tile_model import run_plan
+
+    monkeypatch.setenv("QS_TILE_LOW", str(low))
+    monkeypatch.setenv("QS_REMAP_ALWAYS", "1")
+    c = _swap_circuits()[ci]
+    ops, mats = c.arrays()
+    passes, tops, pool = qs.qs_plan_export(c.n, dt, ops, mats, tile_qubits=tq)
+    restore = qs.qs_plan_restore(c.n, dt, ops, mats, tile_qubits=tq)
+    assert 1 <= len(restore) <= 2
+    for tau in restore:  # involutions of bit positions
+        assert sorted(tau.tolist()) == list(range(c.n)) and all(tau[tau[p]] == p for p in range(c.n))
+    got = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis), restore)
+    ref = oracle.run_circuit(c)
+    assert float(np.max(np.abs(got - ref))) <= 1e-12
+    # dropping the restore passes must break the comparison (the qubits are permuted)
+    bad = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis))
+    assert float(np.max(np.abs(bad - ref))) > 1e-6
+
+
+def test_long_swap_cycle_needs_two_involutions(qs, monkeypatch):
+    """A 5-cycle of qubits (four SWAPs) is not an involution: two restoring
+    passes; QFT's swaps pair disjoint qubits: one."""
+    monkeypatch.setenv("QS_REMAP_ALWAYS", "1")
+    c = W.Circuit(8, "cycle5")
+    for q in range(8):
+        c.g1(q, W.H)
+    for a in range(4):
+        c.g2(a, a + 1, W.SWAP)
+    c.g1(0, W.X)
+    ops, mats = c.arrays()
+    assert len(qs.qs_plan_restore(8, 2, ops, mats, tile_qubits=4)) == 2
+    q = W.qft(10, 3)
+    ops, mats = q.arrays()
+    assert len(qs.qs_plan_restore(10, 2, ops, mats, tile_qubits=4)) == 1
+
+
+def test_swap_relabeling_pays_for_qft(qs):
+    """32-qubit QFT: relabeling its 16 SWAPs saves tile passes, at the cost of
+    one restoring pass; remap = 1 keeps the SWAPs as gates."""
+    c = W.qft(32, 5)
+    ops, mats = c.arrays()
+    for dt in (1, 2):
+        auto = qs.qs_plan_circuit(32, dt, ops, mats)[0]
+        plain = qs.qs_plan_circuit(32, dt, ops, mats, remap=1)[0]
+        assert auto + 2 <= plain, (dt, auto, plain)
+        assert len(qs.qs_plan_restore(32, dt, ops, mats)) == 1
+        assert qs.qs_plan_restore(32, dt, ops, mats, remap=1) == []
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_circuit(32, 1, ops, mats, remap=2)

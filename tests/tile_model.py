@@ -2,7 +2,9 @@
 infrastructure).  It executes the planner's encoded operations -- tile
 qubits, register segments, fused register blocks, diagonal forms -- on a
 complex128 state with numpy, so a CPU test can compare the result with the
-FP64 oracle and catch an encoding mistake without a GPU.  It follows the
+FP64 oracle and catch an encoding mistake without a GPU.  After SWAP
+relabeling the passes act on physical qubit positions, and the restoring
+involutions (one in-place exchange of bit pairs each) follow them.  It follows the
 field meanings the kernels use; it does not model rounding, thread layout
 or the matrix-core blocks.
 """
@@ -136,8 +138,22 @@ def _top(T, base, op, pool):
     raise NotImplementedError(f"op kind {kind} is not modelled")
 
 
-def run_plan(n, passes, tops, pool, psi):
-    """Apply the planned passes to psi (complex128, 2^n); returns the result."""
+def apply_involution(psi, n, tau):
+    """The restoring pass: swap psi[y] with psi[y'] where y' is y with the bits
+    at each exchanged pair of positions (p, tau[p]) swapped."""
+    y = np.arange(1 << n, dtype=np.int64)
+    z = y.copy()
+    for p in range(n):
+        q = int(tau[p])
+        if q > p:
+            diff = ((y >> p) ^ (y >> q)) & 1
+            z ^= diff * ((1 << p) | (1 << q))
+    return psi[z]
+
+
+def run_plan(n, passes, tops, pool, psi, restore=()):
+    """Apply the planned passes, then the restoring involutions, to psi
+    (complex128, 2^n); returns the result."""
     psi = np.array(psi, dtype=np.complex128)
     for P in passes:
         m, Q = P["m"], P["Q"]
@@ -165,4 +181,6 @@ def run_plan(n, passes, tops, pool, psi):
             _top(T, base, op, pool)
             i += 1
         psi[idx] = T
+    for tau in restore:
+        psi = apply_involution(psi, n, tau)
     return psi

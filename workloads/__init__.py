@@ -274,6 +274,35 @@ def grover(n: int, mark: int, rounds: int | None = None, gate_cap: int = 200) ->
     return c
 
 
+def swap_network(n: int, count: int, seed: int) -> Circuit:
+    """A U3 on every qubit, then `count` gates drawn from Generator([seed, 4]):
+    uncontrolled SWAPs that walk a random cycle of the qubits (so their
+    product is a long permutation) or join a random pair, controlled SWAPs,
+    Haar 4x4 gates and controlled phases."""
+    rng = _rng(seed, 4)
+    c = Circuit(n, f"swapnet_n{n}_c{count}_s{seed}")
+    for q in range(n):
+        c.g1(q, u3(*rng.uniform(0, 2 * np.pi, 3)))
+    cyc = [int(q) for q in rng.permutation(n)]
+    for i in range(count):
+        r = int(rng.integers(6))
+        if r < 2:
+            c.g2(cyc[i % n], cyc[(i + 1) % n], SWAP)
+        elif r == 2:
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            c.g2(a, b, SWAP)
+        elif r == 3:
+            a, b, k = (int(x) for x in rng.choice(n, 3, replace=False))
+            c.add([a, b], SWAP, [k], 0 if rng.random() < 0.5 else 1 << k)
+        elif r == 4:
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            c.g2(a, b, haar_unitary(4, rng))
+        else:
+            t, k = (int(x) for x in rng.choice(n, 2, replace=False))
+            c.add([t], phase(rng.uniform(0, 2 * np.pi)), [k], 1 << k)
+    return c
+
+
 # ---------------------------------------------------------------------------
 # States and mixes
 # ---------------------------------------------------------------------------
