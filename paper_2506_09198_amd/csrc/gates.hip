@@ -217,10 +217,16 @@ template <typename R, int K, int NH>
 static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
 {
     static int ppl_env = env_int(NH == 0 ? "QS_PPL_H0" : (NH == 1 ? "QS_PPL_H1" : "QS_PPL_H2"), 0);
-    // Measured on MI355X (n=30 c128): 4 / 2 / 1 slots for NH = 0 / 1 / 2,
-    // except two high targets both at bit 18 or above, where 2 slots recover
-    // 10-15% (their four streams are megabytes apart).
-    int ppl = NH == 0 ? 4 : (NH == 1 ? 2 : (ga.roff[1] >= (1ull << 18) && ga.roff[2] >= (1ull << 18) ? 2 : 1));
+    // Measured on MI355X (n=30 c128, every target): 4 slots without high
+    // targets; one high target (1q, or 2q with the other target low): 1 slot
+    // while its partner is less than 16 MiB away (t < 20), 2 beyond (150-300
+    // GB/s either way); two high targets: 1 slot, except both at bit 18 or
+    // above, where 2 slots recover 10-15% (their four streams are megabytes
+    // apart).
+    using V = typename CT<R>::V;
+    int ppl = NH == 0 ? 4
+              : NH == 1 ? (ga.roff[1] * sizeof(V) < (16ull << 20) ? 1 : 2)
+                        : (ga.roff[1] >= (1ull << 18) && ga.roff[2] >= (1ull << 18) ? 2 : 1);
     if (ppl_env > 0) ppl = ppl_env;
     auto go = [&](auto pplc) {
         constexpr int P = decltype(pplc)::value;

@@ -24,8 +24,8 @@ namespace qs {
 
 namespace {
 
-constexpr int kLowRun = 5;            // K: consecutive amplitudes per run
-constexpr int kMaxT = 2 * kLowRun;    // |T| <= 2K
+constexpr int kMaxRun = 6;            // K <= 6: runs of up to 64 consecutive amplitudes
+constexpr int kMaxT = 2 * kMaxRun;    // |T| <= 2K
 constexpr int kMaxPairs = 32;
 
 struct InvArgs {
@@ -38,14 +38,14 @@ struct InvArgs {
     InsertPlan ip;                    // the positions of T, inserted into the tile counter
 };
 
-template <typename V>
+template <typename V, int K>
 __global__ void __launch_bounds__(256) k_bit_involution(V* __restrict__ psi, InvArgs a)
 {
-    __shared__ V la[1 << kMaxT], lb[1 << kMaxT];
+    __shared__ V la[1 << (2 * K)], lb[1 << (2 * K)];
     const int E = 1 << a.nt;
     auto deposit = [&](int u) {
-        uint64_t off = (uint64_t)(u & ((1 << kLowRun) - 1)) & (((uint64_t)1 << a.nt) - 1);
-        for (int j = kLowRun; j < a.nt; ++j) off |= (uint64_t)((u >> j) & 1) << a.tpos[j];
+        uint64_t off = (uint64_t)(u & ((1 << K) - 1)) & (((uint64_t)1 << a.nt) - 1);
+        for (int j = K; j < a.nt; ++j) off |= (uint64_t)((u >> j) & 1) << a.tpos[j];
         return off;
     };
     auto sigma_in = [&](int u) {
@@ -94,7 +94,13 @@ hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipSt
     if (id) return hipSuccess;
     InvArgs a;
     std::memset(&a, 0, sizeof a);
-    const int K = n < kLowRun ? n : kLowRun;
+    // Runs of 2^Kr amplitudes; both tiles of a pair sit in LDS.  Measured at
+    // 30 qubits (QFT restore): 256-byte runs are best -- Kr = 5 for complex64
+    // (2.7 TB/s; Kr = 6 needs 64 KiB of LDS per block and drops to 1.1),
+    // Kr = 4 for complex128 (3.3 TB/s against 3.0 at Kr = 5).
+    static const int kenv = env_int("QS_PERM_RUN", 0);
+    const int Kr = (kenv >= 4 && kenv <= (dt == QS_C128 ? 5 : 6)) ? kenv : (dt == QS_C128 ? 4 : 5);
+    const int K = n < Kr ? n : Kr;
     uint64_t T = 0;
     for (int p = 0; p < K; ++p) T |= (1ull << p) | (1ull << tau[p]);
     int pos_to_j[64];
@@ -113,10 +119,19 @@ hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipSt
     a.ip = make_insert_plan(T);
     a.ntiles = 1ull << (n - a.nt);
     const unsigned g = (unsigned)(a.ntiles < (1ull << 20) ? a.ntiles : (1ull << 20));
-    if (dt == QS_C128)
-        hipLaunchKernelGGL(k_bit_involution<double2>, dim3(g), dim3(256), 0, st, (double2*)psi, a);
-    else
-        hipLaunchKernelGGL(k_bit_involution<float2>, dim3(g), dim3(256), 0, st, (float2*)psi, a);
+    if (dt == QS_C128) {
+        if (Kr == 4)
+            hipLaunchKernelGGL((k_bit_involution<double2, 4>), dim3(g), dim3(256), 0, st, (double2*)psi, a);
+        else
+            hipLaunchKernelGGL((k_bit_involution<double2, 5>), dim3(g), dim3(256), 0, st, (double2*)psi, a);
+    } else {
+        if (Kr == 4)
+            hipLaunchKernelGGL((k_bit_involution<float2, 4>), dim3(g), dim3(256), 0, st, (float2*)psi, a);
+        else if (Kr == 5)
+            hipLaunchKernelGGL((k_bit_involution<float2, 5>), dim3(g), dim3(256), 0, st, (float2*)psi, a);
+        else
+            hipLaunchKernelGGL((k_bit_involution<float2, 6>), dim3(g), dim3(256), 0, st, (float2*)psi, a);
+    }
     return hipGetLastError();
 }
 
