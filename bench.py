@@ -431,7 +431,7 @@ def run_batch(a, qs, torch, W):
         r = {"circuits_per_s": count / float(np.median(e2e)), "end_to_end_ms": 1e3 * float(np.median(e2e)),
              "device_ms": float(np.median(dev)), "submit_ms": 1e3 * (t1 - t0), "launches": st["launches"],
              "passes": st["passes"], "class_ms": st["class_ms"], "class_circuits": st["class_circuits"],
-             "amp_updates_per_s": upd_total / float(np.median(e2e))}
+             "submit_phases_ms": st["submit_ms"], "amp_updates_per_s": upd_total / float(np.median(e2e))}
         return r, keep
 
     res = {}

@@ -302,6 +302,9 @@ typedef struct {
                             pass-major classes, from the same first event (0 if empty) */
     uint32_t class_circuits[3];
     uint32_t rsv;
+    double submit_ms[4]; /* host time inside qs_batch_submit: device allocation, planning,
+                            packing the plans into one descriptor buffer, upload and
+                            enqueue */
 } qs_batch_stats;
 
 /* Run `count` independent circuits (batching survey item; the paper times one

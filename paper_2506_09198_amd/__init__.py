@@ -55,7 +55,8 @@ class _TuneEntry(ctypes.Structure):
 
 class _BatchStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("device_ms", ctypes.c_double),
-                ("class_ms", ctypes.c_double * 3), ("class_circuits", ctypes.c_uint32 * 3), ("rsv", ctypes.c_uint32)]
+                ("class_ms", ctypes.c_double * 3), ("class_circuits", ctypes.c_uint32 * 3), ("rsv", ctypes.c_uint32),
+                ("submit_ms", ctypes.c_double * 4)]
 
 
 class _ServerOpts(ctypes.Structure):
@@ -459,7 +460,8 @@ def qs_batch_get_stats(b: int) -> dict:
     st = _BatchStats()
     _check(lib.qs_batch_get_stats(ctypes.c_void_p(b), ctypes.byref(st)))
     return {"launches": st.launches, "passes": st.passes, "device_ms": st.device_ms,
-            "class_ms": list(st.class_ms), "class_circuits": list(st.class_circuits)}
+            "class_ms": list(st.class_ms), "class_circuits": list(st.class_circuits),
+            "submit_ms": dict(zip(("alloc", "plan", "pack", "enqueue"), st.submit_ms))}
 
 
 def qs_batch_release(b: int):

@@ -15,7 +15,9 @@
 // over the streams: the unfused reference the fused mode is compared against.
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "planner.h"
@@ -32,6 +34,7 @@ struct qs_batch_s {
     char* dbuf = nullptr; // descriptors, passes, ops, matrices
     uint64_t dbuf_bytes = 0;
     char* hbuf = nullptr; // pinned staging for dbuf
+    uint64_t hbuf_cap = 0;
     std::vector<uint64_t> off;
     std::vector<int> n;
     std::vector<hipStream_t> st;
@@ -60,6 +63,44 @@ struct qs_batch_s {
 
 namespace {
 
+// One spare pinned staging buffer kept across batches: pinning a fresh
+// gigabyte per submit costs far more than filling it.  A batch takes the spare
+// when it is large enough (else allocates its own) and hands its buffer back
+// on release; the larger of the two is kept.
+std::mutex g_pin_mu;
+char* g_pin = nullptr;
+uint64_t g_pin_cap = 0;
+
+qs_status pinned_acquire(uint64_t bytes, char** out, uint64_t* cap)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        if (g_pin && g_pin_cap >= bytes) {
+            *out = g_pin;
+            *cap = g_pin_cap;
+            g_pin = nullptr;
+            g_pin_cap = 0;
+            return QS_OK;
+        }
+    }
+    const uint64_t want = bytes + bytes / 4; // room for a slightly larger next batch
+    if (hipHostMalloc((void**)out, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return set_err(QS_ERR_OOM, "hipHostMalloc(%llu) failed", (unsigned long long)want);
+    }
+    *cap = want;
+    return QS_OK;
+}
+
+void pinned_release(char* p, uint64_t cap)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_pin || cap > g_pin_cap) std::swap(g_pin, p), std::swap(g_pin_cap, cap);
+    if (p) (void)hipHostFree(p);
+}
+
 qs_status bfail(qs_batch b, hipError_t e, const char* what)
 {
     b->failed = true;
@@ -80,7 +121,7 @@ void release(qs_batch b)
     for (hipStream_t s : b->st) (void)hipStreamDestroy(s);
     if (b->arena) dev_free(b->arena, b->arena_bytes);
     if (b->dbuf) dev_free(b->dbuf, b->dbuf_bytes);
-    if (b->hbuf) (void)hipHostFree(b->hbuf);
+    pinned_release(b->hbuf, b->hbuf_cap); // the streams are idle: the upload is done
     (void)hipGetLastError();
     delete b;
 }
@@ -220,6 +261,12 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     }
     if (qs_device_count() < 1) return set_err(QS_ERR_DEVICE, "no HIP device available");
 
+    using clk = std::chrono::steady_clock;
+    auto t_last = clk::now();
+    auto phase = [&]() { // host milliseconds since the previous phase ended
+        const auto t = clk::now();
+        return std::chrono::duration<double, std::milli>(t - std::exchange(t_last, t)).count();
+    };
     qs_batch b = new qs_batch_s();
     std::memset(&b->stats, 0, sizeof b->stats);
     b->dt = o.dtype;
@@ -266,13 +313,11 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     }
     for (size_t i = 1; i < b->st.size(); ++i) (void)hipStreamWaitEvent(b->st[i], b->t0, 0);
 
+    b->stats.submit_ms[0] = phase();
     // ------------------------------------------------------------ plan
     enum { C_WHOLE = 0, C_PERSIST = 1, C_STREAM = 2 };
     std::vector<int> cls(count, C_STREAM);
     std::vector<BatchCirc> bc(count);
-    std::vector<BatchPass> bpass;
-    std::vector<TileOp> bops;
-    std::vector<double> bmats;
     int persist_m = 0, stream_m = 0;
     // classes and tile sizes first (the first circuit of a class fixes its
     // tile size), then the plans on host threads, then one concatenation
@@ -309,45 +354,30 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
             const qs_circuit& c = circuits[i];
             if (c.n_ops > 0) plan_circuit(c.n, c.ops, c.n_ops, c.mats, popts[i], plans[i], pools[i]);
         });
-    for (int i = 0; i < count && b->mode == 0; ++i) {
-        std::vector<PlanPass>& passes = plans[i];
-        std::vector<double>& pool = pools[i];
-        const size_t pool_base = bmats.size() + (bmats.size() & 1); // keep 16-byte alignment
-        bmats.resize(pool_base);
-        bmats.insert(bmats.end(), pool.begin(), pool.end());
-        bc[i].pass0 = (int)bpass.size();
-        bc[i].npass = (int)passes.size();
-        for (auto& p : passes) {
-            BatchPass d;
-            std::memset(&d, 0, sizeof d);
-            d.m = p.m;
-            d.L = p.L;
-            uint64_t qm = 0;
-            for (int j = 0; j < p.m; ++j) {
-                d.q[j] = p.Q[j];
-                qm |= 1ull << p.Q[j];
-            }
-            d.ip = make_insert_plan(qm);
-            d.op0 = (int)bops.size();
-            d.nops = (int)p.ops.size();
-            for (TileOp t : p.ops) {
-                t.moff += pool_base;
-                bops.push_back(t);
-            }
-            bpass.push_back(d);
-            b->stats.passes += 1;
+    b->stats.submit_ms[1] = phase();
+    // Sizes first: each circuit's passes, ops and matrix pool get a fixed
+    // place in the descriptor buffer, so host threads can fill it in parallel.
+    std::vector<int64_t> pass0(count + 1, 0), opx0(count + 1, 0), mat0(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        int64_t np = 0, no = 0, nm = 0;
+        if (b->mode == 0) {
+            np = (int64_t)plans[i].size();
+            for (const PlanPass& p : plans[i]) no += (int64_t)p.ops.size();
+            nm = (int64_t)pools[i].size();
+        } else {
+            nm = circuits[i].n_mats;
         }
-        std::vector<PlanPass>().swap(passes);
-        std::vector<double>().swap(pool);
+        pass0[i + 1] = pass0[i] + np;
+        opx0[i + 1] = opx0[i] + no;
+        mat0[i + 1] = mat0[i] + ((nm + 1) & ~int64_t(1)); // keep 16-byte alignment
+        bc[i].pass0 = (int)pass0[i];
+        bc[i].npass = (int)np;
     }
-    // per-gate mode: stage every circuit's matrices (dense k > 2 gates read them)
+    b->stats.passes = (uint64_t)pass0[count];
+    // per-gate mode: dense k > 2 gates read their matrices from the pool
     std::vector<size_t> gate_pool_base(count, 0);
-    if (b->mode == 1) {
-        for (int i = 0; i < count; ++i) {
-            gate_pool_base[i] = bmats.size();
-            bmats.insert(bmats.end(), circuits[i].mats, circuits[i].mats + circuits[i].n_mats);
-        }
-    }
+    if (b->mode == 1)
+        for (int i = 0; i < count; ++i) gate_pool_base[i] = (size_t)mat0[i];
     // pass-major rounds over the streamed circuits: round r = pass r of each
     std::vector<RoundEntry> rents;
     std::vector<std::pair<size_t, std::pair<int, uint32_t>>> rounds; // (entry offset, (count, blocks))
@@ -392,28 +422,62 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const uint64_t o_circ = 0;
     const uint64_t o_pass = al(o_circ + bc.size() * sizeof(BatchCirc));
-    const uint64_t o_ops = al(o_pass + bpass.size() * sizeof(BatchPass));
-    const uint64_t o_list = al(o_ops + bops.size() * sizeof(TileOp));
+    const uint64_t o_ops = al(o_pass + (uint64_t)pass0[count] * sizeof(BatchPass));
+    const uint64_t o_list = al(o_ops + (uint64_t)opx0[count] * sizeof(TileOp));
     const uint64_t o_ents = al(o_list + lists.size() * sizeof(int32_t));
     const uint64_t o_mats = al(o_ents + rents.size() * sizeof(RoundEntry));
-    b->dbuf_bytes = al(o_mats + bmats.size() * sizeof(double)) + 256;
+    b->dbuf_bytes = al(o_mats + (uint64_t)mat0[count] * sizeof(double)) + 256;
     if ((st = dev_alloc((void**)&b->dbuf, b->dbuf_bytes, "batch descriptors")) != QS_OK) {
         release(b);
         return st;
     }
-    e = hipHostMalloc((void**)&b->hbuf, b->dbuf_bytes, hipHostMallocDefault);
-    if (e != hipSuccess) {
+    if ((st = pinned_acquire(b->dbuf_bytes, &b->hbuf, &b->hbuf_cap)) != QS_OK) {
         release(b);
-        (void)hipGetLastError();
-        return set_err(QS_ERR_OOM, "hipHostMalloc(%llu) failed", (unsigned long long)b->dbuf_bytes);
+        return st;
     }
+    std::vector<uint8_t> needs_full(count, 0);
+    parallel_for(count, [&](int i) {
+        double* M = (double*)(b->hbuf + o_mats) + mat0[i];
+        if (b->mode == 1) {
+            std::memcpy(M, circuits[i].mats, (size_t)circuits[i].n_mats * sizeof(double));
+            return;
+        }
+        std::vector<PlanPass>& passes = plans[i];
+        std::vector<double>& pool = pools[i];
+        if (!pool.empty()) std::memcpy(M, pool.data(), pool.size() * sizeof(double));
+        BatchPass* P = (BatchPass*)(b->hbuf + o_pass) + pass0[i];
+        TileOp* T = (TileOp*)(b->hbuf + o_ops) + opx0[i];
+        int64_t op = opx0[i];
+        for (size_t j = 0; j < passes.size(); ++j) {
+            const PlanPass& p = passes[j];
+            BatchPass d;
+            std::memset(&d, 0, sizeof d);
+            d.m = p.m;
+            d.L = p.L;
+            uint64_t qm = 0;
+            for (int k = 0; k < p.m; ++k) {
+                d.q[k] = p.Q[k];
+                qm |= 1ull << p.Q[k];
+            }
+            d.ip = make_insert_plan(qm);
+            d.op0 = (int)op;
+            d.nops = (int)p.ops.size();
+            P[j] = d;
+            for (TileOp t : p.ops) {
+                t.moff += (uint64_t)mat0[i];
+                *T++ = t;
+            }
+            needs_full[i] |= ops_need_full(p.ops.data(), p.ops.size(), p.m);
+            op += (int64_t)p.ops.size();
+        }
+        std::vector<PlanPass>().swap(passes);
+        std::vector<double>().swap(pool);
+    });
     std::memcpy(b->hbuf + o_circ, bc.data(), bc.size() * sizeof(BatchCirc));
-    std::memcpy(b->hbuf + o_pass, bpass.data(), bpass.size() * sizeof(BatchPass));
-    std::memcpy(b->hbuf + o_ops, bops.data(), bops.size() * sizeof(TileOp));
     std::memcpy(b->hbuf + o_list, lists.data(), lists.size() * sizeof(int32_t));
     std::memcpy(b->hbuf + o_ents, rents.data(), rents.size() * sizeof(RoundEntry));
-    std::memcpy(b->hbuf + o_mats, bmats.data(), bmats.size() * sizeof(double));
     hipStream_t s0 = b->st[0];
+    b->stats.submit_ms[2] = phase();
     e = hipMemcpyAsync(b->dbuf, b->hbuf, b->dbuf_bytes, hipMemcpyHostToDevice, s0);
     if (e != hipSuccess) {
         qs_status r = bfail(b, e, "batch upload");
@@ -450,7 +514,7 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         S.stream_m = stream_m;
         S.rounds = rounds;
         S.any_full = false; // any pass needs the full tile kernel
-        for (const BatchPass& d : bpass) S.any_full |= ops_need_full(bops.data() + d.op0, (size_t)d.nops, d.m);
+        for (uint8_t f : needs_full) S.any_full |= f != 0;
         S.dcirc = dcirc;
         S.dpass = dpass;
         S.dops = dops;
@@ -489,6 +553,7 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         e = hipEventRecord(b->done[i], b->st[i]);
         if (e != hipSuccess && st == QS_OK) st = bfail(b, e, "hipEventRecord");
     }
+    b->stats.submit_ms[3] = phase();
     if (st != QS_OK) {
         release(b);
         return st;
