@@ -131,3 +131,39 @@ def test_planner_fuses_blocks_for_c64(qs, monkeypatch):
         qs.qs_plan_circuit(20, qs.QS_C128, ops, mats, tile_qubits=12)
     with pytest.raises(qs.QSError):
         qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, fuse_k=3)
+
+
+def test_new_entry_points_reject_null_handles(qs):
+    for call in (lambda: qs.qs_apply_diag(0, [0], np.array([1, -1])),
+                 lambda: qs.qs_expect_pauli(0, 1, 0),
+                 lambda: qs.qs_sample(0, np.array([0.5]))):
+        with pytest.raises(qs.QSError) as e:
+            call()
+        assert e.value.status == qs.QS_ERR_ARG
+
+
+def test_plan_restore_validation_and_shape(qs):
+    c = W.qft(12, 7)
+    ops, mats = c.arrays()
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_restore(12, qs.QS_C64, ops, mats, remap=3)
+    bad = ops.copy()
+    bad[0]["t"][0] = 12
+    with pytest.raises(qs.QSError):
+        qs.qs_plan_restore(12, qs.QS_C64, bad, mats)
+    taus = qs.qs_plan_restore(12, qs.QS_C64, ops, mats, tile_qubits=6)
+    assert len(taus) <= 2
+    for tau in taus:
+        assert tau.shape == (12,) and all(tau[tau[p]] == p for p in range(12))
+    # no SWAP gate: nothing to restore, with or without relabeling
+    r = W.rqc_chain(14, 6, 3)
+    ops, mats = r.arrays()
+    assert qs.qs_plan_restore(14, qs.QS_C64, ops, mats) == []
+
+
+def test_batch_stats_layout(qs):
+    import ctypes
+
+    # launches, passes, device_ms, class_ms[3], class_circuits[3], rsv, submit_ms[4]
+    assert ctypes.sizeof(qs._BatchStats) == 8 * 3 + 8 * 3 + 4 * 3 + 4 + 8 * 4
+    assert ctypes.sizeof(qs._RunOpts) == 4 * 8
