@@ -216,6 +216,27 @@ def diag_sweep(qs, s, n, S, reps=3, seed=13):
                     "128-byte line (bit 3, complex128) read whole lines"}
 
 
+def per_target_table(gates, recs, steps):
+    """GB/s per target index (median over the timed steps) for each gate of
+    the sweep: 1q by target; 2q by first target, adjacent (t, t+1) and far
+    (t, t+15), uncontrolled and with one control."""
+    G = len(gates)
+    if len(recs) < G * steps:
+        return None
+    ms = np.median(np.array([float(r) for r in recs["ms"][:G * steps]]).reshape(steps, G), axis=0)
+    by = np.array([float(b) for b in recs["bytes"][:G]])
+    gbs = by / ms / 1e6
+    out = {"1q": [], "2q_adjacent": [], "2q_adjacent_ctrl": [], "2q_far": [], "2q_far_ctrl": []}
+    for (tg, u, cm, cv), g in zip(gates, gbs):
+        if len(tg) == 1:
+            key = "1q"
+        else:
+            key = ("2q_adjacent" if tg[1] == tg[0] + 1 else "2q_far") + ("_ctrl" if cm else "")
+        out[key].append(round(float(g)))
+    out["note"] = "GB/s of algorithmic bytes per launch, index = first target"
+    return out
+
+
 def run_sweep(a, qs, torch, W):
     n = a.n or 30
     dt = qs.QS_C128 if a.dtype == "c128" else qs.QS_C64
@@ -258,6 +279,7 @@ def run_sweep(a, qs, torch, W):
     s.close()
     kinds = _kinds(qs, recs)
     rl = _roofline(kinds)
+    per_target = per_target_table(gates, recs, a.steps) if a.mode == "pergate" else None
     if a.mode == "pergate":
         rl["traffic"] = measured_traffic(rl["kernel"], f"gate_sweep_n{n}_{a.dtype}")
     out = _header(a, "amplitude-updates/s", upd_step * a.steps / elapsed, "amp-updates/s",
@@ -274,6 +296,7 @@ def run_sweep(a, qs, torch, W):
                     for k, d in kinds.items()},
         "event_coverage": sum(d["ms"] for d in kinds.values()) / (elapsed * 1e3),
         "norm_minus_1": norm - 1.0,
+        "per_target_gbs": per_target,
         "diag_sweep": diag,
     })
     if not a.no_cpu:
