@@ -15,9 +15,13 @@
  *   index i (bit t clear) with i + 2^t (Alg. 1, Section II-C).
  * - Matrices are always FP64 at the ABI: 2^k x 2^k complex, row-major,
  *   interleaved (re, im).  For a gate on targets t[0..k), t[j] is bit j of the
- *   matrix row/column index (t[0] is the least significant).  For QS_C64 states
- *   the library rounds matrices (and any fused products, formed in FP64) to
- *   FP32 once.
+ *   matrix row/column index (t[0] is the least significant).  QS_C64 states
+ *   store FP32 amplitudes, but every update is computed in FP64 with the FP64
+ *   matrices (fused products too, formed in FP64); each stored amplitude is
+ *   rounded to FP32 once per write.  Matrices are not checked for unitarity
+ *   unless the environment sets QS_CHECK_UNITARY=1: then every gate matrix
+ *   with max |(U^H U - I)_ij| > 1e-10 (or a diagonal entry of modulus other
+ *   than 1) is rejected with QS_ERR_ARG.
  * - Controls are a bitmask ctrl_mask with required values ctrl_vals (a subset
  *   of ctrl_mask; ctrl_vals == ctrl_mask means "control on 1").  A controlled
  *   gate updates only the amplitudes whose control bits match and leaves all
@@ -327,6 +331,16 @@ qs_status qs_batch_state(qs_batch b, int i, void** dev_ptr, int* n);
 /* Copy circuit i's final state to host memory (2^n elements of the batch
  * dtype); waits for the batch first. */
 qs_status qs_batch_download(qs_batch b, int i, void* host);
+
+/* Marginal probabilities (as qs_probabilities: 0 <= m <= min(24, n), distinct
+ * qubits, out[o] over the indices whose qubits[j] bits spell o, FP64 in a fixed
+ * order) and squared norm of circuit i's final state, computed on the device
+ * from the state in the batch arena; wait for the batch first and block until
+ * out (host, 2^m doubles / one double) is filled.  Together with
+ * qs_batch_download they give each circuit's result as a state, a distribution
+ * or a norm.  Not thread-safe against other calls on the same batch. */
+qs_status qs_batch_probabilities(qs_batch b, int i, const int* qubits, int m, double* out);
+qs_status qs_batch_norm(qs_batch b, int i, double* out);
 
 qs_status qs_batch_get_stats(qs_batch b, qs_batch_stats* out);
 

@@ -133,6 +133,8 @@ def _load():
         "qs_batch_state": ([vp, i32, ctypes.POINTER(vp), ctypes.POINTER(i32)], i32),
         "qs_batch_download": ([vp, i32, vp], i32),
         "qs_batch_get_stats": ([vp, ctypes.POINTER(_BatchStats)], i32),
+        "qs_batch_probabilities": ([vp, i32, ctypes.POINTER(i32), i32, dp], i32),
+        "qs_batch_norm": ([vp, i32, dp], i32),
         "qs_batch_release": ([vp], i32),
         "qs_server_create": ([ctypes.POINTER(_ServerOpts), ctypes.POINTER(vp)], i32),
         "qs_server_submit": ([vp, ctypes.POINTER(_Circuit), ctypes.POINTER(ctypes.c_uint64)], i32),
@@ -462,6 +464,20 @@ def qs_batch_get_stats(b: int) -> dict:
     return {"launches": st.launches, "passes": st.passes, "device_ms": st.device_ms,
             "class_ms": list(st.class_ms), "class_circuits": list(st.class_circuits),
             "submit_ms": dict(zip(("alloc", "plan", "pack", "enqueue"), st.submit_ms))}
+
+
+def qs_batch_probabilities(b: int, i: int, qubits) -> np.ndarray:
+    q = np.ascontiguousarray(list(qubits), dtype=np.int32)
+    out = np.empty(1 << len(q), dtype=np.float64)
+    _check(lib.qs_batch_probabilities(ctypes.c_void_p(b), int(i), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      len(q), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def qs_batch_norm(b: int, i: int) -> float:
+    out = np.zeros(1, dtype=np.float64)
+    _check(lib.qs_batch_norm(ctypes.c_void_p(b), int(i), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return float(out[0])
 
 
 def qs_batch_release(b: int):

@@ -59,6 +59,8 @@ struct qs_batch_s {
     } sched;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    double* red = nullptr; // reduction scratch for qs_batch_probabilities
+    uint64_t red_cap = 0;  // doubles
 };
 
 namespace {
@@ -121,6 +123,7 @@ void release(qs_batch b)
     for (hipStream_t s : b->st) (void)hipStreamDestroy(s);
     if (b->arena) dev_free(b->arena, b->arena_bytes);
     if (b->dbuf) dev_free(b->dbuf, b->dbuf_bytes);
+    if (b->red) dev_free(b->red, b->red_cap * sizeof(double));
     pinned_release(b->hbuf, b->hbuf_cap); // the streams are idle: the upload is done
     (void)hipGetLastError();
     delete b;
@@ -612,6 +615,41 @@ qs_status qs_batch_download(qs_batch b, int i, void* host)
     if (e != hipSuccess) return bfail(b, e, "batch download");
     return QS_OK;
 }
+
+qs_status qs_batch_probabilities(qs_batch b, int i, const int* qubits, int m, double* out)
+{
+    if (!b) return set_err(QS_ERR_ARG, "null batch handle");
+    if (i < 0 || i >= b->count) return set_err(QS_ERR_ARG, "circuit index %d outside [0, %d)", i, b->count);
+    if (!out) return set_err(QS_ERR_ARG, "null output");
+    const int n = b->n[i];
+    if (m < 0 || m > 24 || m > n) return set_err(QS_ERR_ARG, "m=%d outside [0, min(24, n)]", m);
+    if (m > 0 && !qubits) return set_err(QS_ERR_ARG, "null qubit list");
+    uint64_t seen = 0;
+    for (int j = 0; j < m; ++j) {
+        if (qubits[j] < 0 || qubits[j] >= n) return set_err(QS_ERR_ARG, "qubit %d outside [0, %d)", qubits[j], n);
+        if ((seen >> qubits[j]) & 1) return set_err(QS_ERR_ARG, "duplicate qubit %d", qubits[j]);
+        seen |= 1ull << qubits[j];
+    }
+    qs_status st = qs_batch_wait(b, -1);
+    if (st != QS_OK) return st;
+    const uint64_t need = reduce_scratch_doubles(n, m) + (1ull << m);
+    if (need > b->red_cap) {
+        if (b->red) dev_free(b->red, b->red_cap * sizeof(double));
+        b->red = nullptr;
+        b->red_cap = 0;
+        if ((st = dev_alloc((void**)&b->red, need * sizeof(double), "batch reduction scratch")) != QS_OK) return st;
+        b->red_cap = need;
+    }
+    double* dout = b->red + reduce_scratch_doubles(n, m);
+    hipStream_t s0 = b->st[0];
+    hipError_t e = launch_probabilities(b->arena + b->off[i], b->dt, n, qubits, m, b->red, dout, s0);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) << m, hipMemcpyDeviceToHost, s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(s0);
+    if (e != hipSuccess) return bfail(b, e, "batch probabilities");
+    return QS_OK;
+}
+
+qs_status qs_batch_norm(qs_batch b, int i, double* out) { return qs_batch_probabilities(b, i, nullptr, 0, out); }
 
 qs_status qs_batch_get_stats(qs_batch b, qs_batch_stats* out)
 {

@@ -15,6 +15,7 @@ qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double*
     if (n_ops < 0 || n_mats < 0) return set_err(QS_ERR_ARG, "negative op or matrix count");
     if (n_ops > 0 && !ops) return set_err(QS_ERR_ARG, "null op table");
     if (n_mats > 0 && !mats) return set_err(QS_ERR_ARG, "null matrix pool");
+    const bool chk = check_unitary_enabled();
     for (int64_t g = 0; g < n_ops; ++g) {
         const qs_op& o = ops[g];
         if (o.flags != 0 || o.rsv != 0) return set_err(QS_ERR_ARG, "op %lld: flags/rsv must be 0", (long long)g);
@@ -23,6 +24,8 @@ qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double*
         const uint64_t need = 2ull << (2 * o.nt);
         if (o.moff > (uint64_t)n_mats || need > (uint64_t)n_mats - o.moff)
             return set_err(QS_ERR_ARG, "op %lld: matrix range outside the pool", (long long)g);
+        if (chk && (st = check_unitary(mats + o.moff, o.nt)) != QS_OK)
+            return set_err(st, "op %lld: %s", (long long)g, qs_last_error());
     }
     return QS_OK;
 }

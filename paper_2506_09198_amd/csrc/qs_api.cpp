@@ -3,6 +3,7 @@
 // *.hip translation units; circuit planning in planner.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -234,6 +235,30 @@ qs_status validate_gate(int n, const int* t, int k, uint64_t cm, uint64_t cv)
     if (cm & ~qubit_mask_ok(n)) return set_err(QS_ERR_ARG, "control mask has qubits >= n=%d", n);
     if (cm & tm) return set_err(QS_ERR_ARG, "a target is also a control");
     if (cv & ~cm) return set_err(QS_ERR_ARG, "ctrl_vals has bits outside ctrl_mask");
+    return QS_OK;
+}
+
+// With QS_CHECK_UNITARY=1 every gate matrix must satisfy max |(U^H U - I)_ij|
+// <= 1e-10.  The switch is read once per API call (so a process can turn it
+// on and off), the check itself is unconditional.
+bool check_unitary_enabled() { return env_int("QS_CHECK_UNITARY", 0) != 0; }
+
+qs_status check_unitary(const double* U, int k)
+{
+    const int D = 1 << k;
+    double worst = 0.0;
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j) {
+            double re = (i == j) ? -1.0 : 0.0, im = 0.0;
+            for (int r = 0; r < D; ++r) { // (U^H U)_ij = sum_r conj(U_ri) U_rj
+                const double ar = U[2 * (r * D + i)], ai = U[2 * (r * D + i) + 1];
+                const double br = U[2 * (r * D + j)], bi = U[2 * (r * D + j) + 1];
+                re += ar * br + ai * bi;
+                im += ar * bi - ai * br;
+            }
+            worst = std::max(worst, std::hypot(re, im));
+        }
+    if (!(worst <= 1e-10)) return set_err(QS_ERR_ARG, "matrix is not unitary (max |U^H U - I| = %.3g)", worst);
     return QS_OK;
 }
 
@@ -474,6 +499,7 @@ qs_status qs_apply_1q(qs_state s, int target, const double* U, uint64_t cm, uint
     if (st != QS_OK) return st;
     if (!U) return set_err(QS_ERR_ARG, "null matrix");
     if ((st = validate_gate(s->n, &target, 1, cm, cv)) != QS_OK) return st;
+    if (check_unitary_enabled() && (st = check_unitary(U, 1)) != QS_OK) return st;
     return apply_1q_internal(s, target, U, cm, cv);
 }
 
@@ -484,6 +510,7 @@ qs_status qs_apply_2q(qs_state s, int t0, int t1, const double* U, uint64_t cm, 
     if (!U) return set_err(QS_ERR_ARG, "null matrix");
     const int t[2] = {t0, t1};
     if ((st = validate_gate(s->n, t, 2, cm, cv)) != QS_OK) return st;
+    if (check_unitary_enabled() && (st = check_unitary(U, 2)) != QS_OK) return st;
     return apply_2q_internal(s, t0, t1, U, cm, cv);
 }
 
@@ -493,6 +520,7 @@ qs_status qs_apply_fused(qs_state s, const int* targets, int k, const double* U,
     if (st != QS_OK) return st;
     if (!U || !targets) return set_err(QS_ERR_ARG, "null matrix or target list");
     if ((st = validate_gate(s->n, targets, k, cm, cv)) != QS_OK) return st;
+    if (check_unitary_enabled() && (st = check_unitary(U, k)) != QS_OK) return st;
     DiagPlan p;
     if (diag_plan_matrix(s->n, targets, k, U, cm, cv, &p))
         return apply_diag_internal(s, p, targets[0], k > 1 ? targets[1] : -1, cm);
@@ -509,6 +537,10 @@ qs_status qs_apply_diag(qs_state s, const int* targets, int k, const double* dia
     if ((st = validate_gate(s->n, targets, k, cm, cv)) != QS_OK) return st;
     for (int j = 0; j < (2 << k); ++j)
         if (!std::isfinite(diag[j])) return set_err(QS_ERR_ARG, "diagonal entry %d is not finite", j / 2);
+    if (check_unitary_enabled())
+        for (int j = 0; j < (1 << k); ++j)
+            if (!(std::fabs(std::hypot(diag[2 * j], diag[2 * j + 1]) - 1.0) <= 1e-10))
+                return set_err(QS_ERR_ARG, "diagonal entry %d does not have modulus 1", j);
     DiagPlan p;
     if (!diag_plan(s->n, targets, k, diag, cm, cv, &p)) return set_err(QS_ERR_ARG, "k=%d not supported", k);
     return apply_diag_internal(s, p, targets[0], k > 1 ? targets[1] : -1, cm);

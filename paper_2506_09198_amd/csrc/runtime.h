@@ -59,5 +59,9 @@ qs_status apply_1q_internal(qs_state s, int target, const double* U, uint64_t cm
 qs_status apply_2q_internal(qs_state s, int t0, int t1, const double* U, uint64_t cm, uint64_t cv);
 qs_status apply_kq_dev_internal(qs_state s, const int* t, int k, const void* Ud, uint64_t cm, uint64_t cv);
 qs_status apply_diag_internal(qs_state s, const DiagPlan& p, int t0, int t1, uint64_t cm);
+// QS_ERR_ARG unless U (2^k x 2^k, FP64 interleaved) is unitary to 1e-10;
+// callers check only when check_unitary_enabled() (QS_CHECK_UNITARY=1).
+bool check_unitary_enabled();
+qs_status check_unitary(const double* U, int k);
 
 } // namespace qs

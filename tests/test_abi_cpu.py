@@ -167,3 +167,16 @@ def test_batch_stats_layout(qs):
     # launches, passes, device_ms, class_ms[3], class_circuits[3], rsv, submit_ms[4]
     assert ctypes.sizeof(qs._BatchStats) == 8 * 3 + 8 * 3 + 4 * 3 + 4 + 8 * 4
     assert ctypes.sizeof(qs._RunOpts) == 4 * 8
+
+
+def test_unitarity_check_is_opt_in(qs, monkeypatch):
+    c = W.Circuit(3).g1(0, W.H).g2(1, 2, W.SWAP)
+    ops, mats = c.arrays()
+    bad = mats.copy()
+    bad[:8] = [1, 0, 1, 0, 1, 0, -1, 0]  # H without its 1/sqrt(2)
+    qs.qs_plan_circuit(3, qs.QS_C128, ops, bad)  # not checked by default
+    monkeypatch.setenv("QS_CHECK_UNITARY", "1")
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_plan_circuit(3, qs.QS_C128, ops, bad)
+    assert e.value.status == qs.QS_ERR_ARG and "unitary" in qs.qs_last_error()
+    qs.qs_plan_circuit(3, qs.QS_C128, ops, mats)  # the real gates pass

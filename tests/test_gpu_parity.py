@@ -430,3 +430,29 @@ def test_batch_tune(qs, dt):
                 assert abs(np.vdot(want, got)) ** 2 >= 1 - 1e-6, c.name
     finally:
         qs.qs_batch_release(b)
+
+
+@pytest.mark.parametrize("dt", DTS)
+def test_batch_probabilities_and_norm(qs, dt):
+    """Per-circuit marginals and norms of a fused batch, computed on the
+    device, against the oracle's reductions of the downloaded final states."""
+    circs = _batch_mix(21)
+    arrs = [(c.n, *c.arrays(), c.init_basis) for c in circs]
+    b = qs.qs_batch_submit(arrs, dtype=dt, mode=0)
+    qs.qs_batch_wait(b)
+    rng = np.random.default_rng(4)
+    for i, c in enumerate(circs):
+        got_state = qs.qs_batch_download(b, i, dt).astype(np.complex128)
+        for qb in ([], [0], list(rng.permutation(c.n)[: min(3, c.n)]), list(range(c.n))):
+            qb = [int(q) for q in qb]
+            got = qs.qs_batch_probabilities(b, i, qb)
+            want = oracle.probabilities(c.n, got_state, qb)
+            assert np.max(np.abs(got - want)) <= 1e-13, (c.name, qb)
+        assert abs(qs.qs_batch_norm(b, i) - oracle.norm2(c.n, got_state)) <= 1e-13
+    with pytest.raises(qs.QSError):
+        qs.qs_batch_probabilities(b, len(circs), [0])
+    with pytest.raises(qs.QSError):
+        qs.qs_batch_probabilities(b, 0, [0, 0])
+    with pytest.raises(qs.QSError):
+        qs.qs_batch_probabilities(b, 0, list(range(circs[0].n + 1)))
+    qs.qs_batch_release(b)
