@@ -295,7 +295,11 @@ typedef struct {
     int32_t tile_qubits; /* as in qs_run_opts */
     int32_t graph;       /* mode 0: 1 = capture the device work in a HIP graph (launched now and
                             by every qs_batch_replay) */
-    int32_t rsv[2];
+    int32_t whole_max;   /* mode 0: circuits with n <= whole_max run whole in one workgroup's LDS
+                            (0 = 12 for complex128, 13 for complex64; at most those) */
+    int32_t persist_max; /* mode 0: circuits with whole_max < n <= persist_max run their passes in
+                            one persistent workgroup, larger ones pass-major (0 = 15 / 16; at
+                            most 20) */
 } qs_batch_opts;
 
 typedef struct {
@@ -311,8 +315,8 @@ typedef struct {
                             enqueue */
 } qs_batch_stats;
 
-/* Run `count` independent circuits (batching survey item; the paper times one
- * circuit at a time, Section III).  All circuits are validated first (nothing
+/* Run `count` independent circuits (the paper times one circuit at a time,
+ * Section III).  All circuits are validated first (nothing
  * is enqueued if one is invalid), then one device arena is allocated for all
  * final states and the work is enqueued on the batch's own streams; the call
  * returns without waiting.  Each circuit's result equals running it alone with
@@ -356,16 +360,20 @@ qs_status qs_batch_replay(qs_batch b);
 typedef struct {
     int32_t tile_qubits;
     int32_t fuse_k;
-    double device_ms; /* best device time of two replays of the sample */
+    int32_t whole_max;   /* class boundaries as in qs_batch_opts (never 0 here) */
+    int32_t persist_max;
+    double device_ms;    /* best device time of two replays of the sample */
 } qs_tune_entry;
 
-/* Autotune a batch configuration on a sample of circuits (survey batching
- * item): every candidate tile size (10..12) and, for complex64, fused
- * matrix-core width (0, 4, 5) is planned, run, and replayed twice on the
- * device; *opts (dtype and mode as given, mode 0 only) gets the fastest
- * tile_qubits and fuse_k.  out[0..max_out) receives the timings (NULL
- * allowed), *n_out their number.  Allocates and frees device memory for the
- * sample's states. */
+/* Autotune a batch configuration on a sample of circuits.  Stage 1 times
+ * every tile size (10..12) and, for complex64, fused matrix-core width (0, 4,
+ * 5) with the default class boundaries; stage 2 keeps the fastest of those and
+ * times the workgroup classes around the defaults (whole-in-LDS limit one
+ * lower; persistent limit two lower to two higher).  Each candidate is
+ * planned, run, and replayed twice on the device; *opts (dtype and mode as
+ * given, mode 0 only) gets the fastest tile_qubits, fuse_k, whole_max and
+ * persist_max.  out[0..max_out) receives the timings (NULL allowed), *n_out
+ * their number.  Allocates and frees device memory for the sample's states. */
 qs_status qs_batch_tune(const qs_circuit* sample, int count, qs_batch_opts* opts, qs_tune_entry* out, int max_out,
                         int* n_out);
 
@@ -402,8 +410,8 @@ typedef struct {
     uint32_t queued, active;
 } qs_server_stats;
 
-/* Create a serving loop with its own stream and device pools (serving
- * survey item; the paper runs one circuit at a time).  Requests are admitted
+/* Create a serving loop with its own stream and device pools (the paper runs
+ * one circuit at a time).  Requests are admitted
  * in arrival order (later small ones may pass a large one that does not fit
  * yet, up to 64 times) while their state fits hbm_budget; admitted requests
  * advance together in rounds of one tile pass each, and requests arriving

@@ -46,11 +46,12 @@ class _Circuit(ctypes.Structure):
 class _BatchOpts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("mode", ctypes.c_int32), ("streams", ctypes.c_int32),
                 ("fuse_k", ctypes.c_int32), ("tile_qubits", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("rsv", ctypes.c_int32 * 2)]
+                ("whole_max", ctypes.c_int32), ("persist_max", ctypes.c_int32)]
 
 
 class _TuneEntry(ctypes.Structure):
-    _fields_ = [("tile_qubits", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("device_ms", ctypes.c_double)]
+    _fields_ = [("tile_qubits", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("whole_max", ctypes.c_int32),
+                ("persist_max", ctypes.c_int32), ("device_ms", ctypes.c_double)]
 
 
 class _BatchStats(ctypes.Structure):
@@ -417,10 +418,10 @@ def _circuit_array(circuits):
 
 
 def qs_batch_submit(circuits, dtype: int = QS_C128, mode: int = 0, streams: int = 0, fuse_k: int = 0,
-                    tile_qubits: int = 0, graph: int = 0) -> int:
+                    tile_qubits: int = 0, graph: int = 0, whole_max: int = 0, persist_max: int = 0) -> int:
     """circuits: iterable of (n, ops, mats, init_basis) or objects with .n/.arrays()/.init_basis."""
     keep, arr = _circuit_array(circuits)
-    o = _BatchOpts(dtype, mode, streams, fuse_k, tile_qubits, graph)
+    o = _BatchOpts(dtype, mode, streams, fuse_k, tile_qubits, graph, whole_max, persist_max)
     h = ctypes.c_void_p()
     _check(lib.qs_batch_submit(arr, len(circuits), ctypes.byref(o), ctypes.byref(h)))
     return h.value
@@ -431,14 +432,16 @@ def qs_batch_replay(b: int):
 
 
 def qs_batch_tune(sample, dtype: int = QS_C128, streams: int = 0):
-    """Time candidate (tile_qubits, fuse_k) on a sample; returns (best dict, all timings)."""
+    """Time candidate (tile_qubits, fuse_k, whole_max, persist_max) on a sample;
+    returns (best dict, all timings)."""
     keep, arr = _circuit_array(sample)
     o = _BatchOpts(dtype, 0, streams, 0, 0, 0)
-    out = (_TuneEntry * 16)()
+    out = (_TuneEntry * 32)()
     k = ctypes.c_int()
-    _check(lib.qs_batch_tune(arr, len(sample), ctypes.byref(o), out, 16, ctypes.byref(k)))
-    rows = [{"tile_qubits": e.tile_qubits, "fuse_k": e.fuse_k, "device_ms": e.device_ms} for e in out[:k.value]]
-    return {"tile_qubits": o.tile_qubits, "fuse_k": o.fuse_k}, rows
+    _check(lib.qs_batch_tune(arr, len(sample), ctypes.byref(o), out, 32, ctypes.byref(k)))
+    keys = ("tile_qubits", "fuse_k", "whole_max", "persist_max")
+    rows = [{**{x: getattr(e, x) for x in keys}, "device_ms": e.device_ms} for e in out[:k.value]]
+    return {x: getattr(o, x) for x in keys}, rows
 
 
 def qs_batch_wait(b: int, timeout_ms: int = -1):

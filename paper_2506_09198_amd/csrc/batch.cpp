@@ -224,18 +224,21 @@ qs_status capture_fused(qs_batch b)
     return QS_OK;
 }
 
-int whole_max(int dt)
+int default_whole_max(int dt) { return dt == QS_C128 ? 12 : 13; } // 64 KiB of LDS
+int default_persist_max(int dt) { return dt == QS_C128 ? 15 : 16; }
+
+int whole_max(int dt, int opt)
 {
+    if (opt > 0) return opt;
     const int e = env_int("QS_BATCH_WHOLE_MAX", 0);
-    if (e > 0) return e;
-    return dt == QS_C128 ? 12 : 13; // 64 KiB of LDS
+    return e > 0 ? e : default_whole_max(dt);
 }
 
-int persist_max(int dt)
+int persist_max(int dt, int opt)
 {
+    if (opt > 0) return opt;
     const int e = env_int("QS_BATCH_PERSIST_MAX", 0);
-    if (e > 0) return e;
-    return dt == QS_C128 ? 15 : 16;
+    return e > 0 ? e : default_persist_max(dt);
 }
 
 } // namespace
@@ -255,6 +258,10 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     if (o.mode != 0 && o.mode != 1) return set_err(QS_ERR_ARG, "unknown batch mode %d", o.mode);
     if (o.streams <= 0) o.streams = 8;
     if (o.streams > 64) return set_err(QS_ERR_ARG, "streams=%d > 64", o.streams);
+    if (o.whole_max < 0 || o.whole_max > default_whole_max(o.dtype))
+        return set_err(QS_ERR_ARG, "whole_max=%d outside [0, %d]", o.whole_max, default_whole_max(o.dtype));
+    if (o.persist_max < 0 || o.persist_max > 20 || (o.persist_max > 0 && o.persist_max < o.whole_max))
+        return set_err(QS_ERR_ARG, "persist_max=%d outside [whole_max, 20]", o.persist_max);
     for (int i = 0; i < count; ++i) {
         const qs_circuit& c = circuits[i];
         if (c.n < 1 || c.n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "circuit %d: n=%d outside [1, %d]", i, c.n, QS_MAX_QUBITS);
@@ -338,10 +345,15 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
             release(b);
             return st;
         }
-        if (c.n <= whole_max(b->dt)) {
+        // a circuit smaller than its class's tile (possible when whole_max is
+        // set below the tile size) runs whole in LDS: n < m <= 13 fits there
+        const bool in_persist = c.n <= persist_max(b->dt, o.persist_max);
+        const int class_m = in_persist ? (persist_m ? persist_m : std::min(po.m, 13))
+                                       : (stream_m ? stream_m : std::min(po.m, 13));
+        if (c.n <= whole_max(b->dt, o.whole_max) || c.n < class_m) {
             cls[i] = C_WHOLE;
             po.m = c.n;
-        } else if (c.n <= persist_max(b->dt)) {
+        } else if (in_persist) {
             cls[i] = C_PERSIST;
             if (persist_m == 0) persist_m = std::min(po.m, 13);
             po.m = persist_m;
@@ -695,20 +707,19 @@ qs_status qs_batch_tune(const qs_circuit* sample, int count, qs_batch_opts* opts
     if (!sample || count <= 0 || !opts) return set_err(QS_ERR_ARG, "empty sample or null options");
     if (opts->mode != 0) return set_err(QS_ERR_ARG, "tuning needs mode 0 (fused)");
     const int dt = opts->dtype == 0 ? QS_C128 : opts->dtype;
-    std::vector<std::pair<int, int>> cand;
-    for (int m = 10; m <= 12; ++m) {
-        cand.push_back({m, 0});
-        if (dt == QS_C64) {
-            cand.push_back({m, 4});
-            cand.push_back({m, 5});
-        }
-    }
+    const int w0 = default_whole_max(dt), p0 = default_persist_max(dt);
+    struct Cand {
+        int m, f, w, p;
+    };
     double best = -1.0;
-    int bm = 0, bf = 0, k = 0;
-    for (auto& c : cand) {
+    Cand bc{0, 0, w0, p0};
+    int k = 0;
+    auto time_one = [&](const Cand& c) -> qs_status {
         qs_batch_opts o = *opts;
-        o.tile_qubits = c.first;
-        o.fuse_k = c.second;
+        o.tile_qubits = c.m;
+        o.fuse_k = c.f;
+        o.whole_max = c.w;
+        o.persist_max = c.p;
         o.graph = 0;
         qs_batch b = nullptr;
         qs_status st = qs_batch_submit(sample, count, &o, &b);
@@ -721,16 +732,33 @@ qs_status qs_batch_tune(const qs_circuit* sample, int count, qs_batch_opts* opts
         }
         qs_batch_release(b);
         if (st != QS_OK) return st;
-        if (out && k < max_out) out[k] = qs_tune_entry{c.first, c.second, t};
+        if (out && k < max_out) out[k] = qs_tune_entry{c.m, c.f, c.w, c.p, t};
         ++k;
         if (best < 0 || t < best) {
             best = t;
-            bm = c.first;
-            bf = c.second;
+            bc = c;
         }
+        return QS_OK;
+    };
+    // stage 1: tile size and fused width at the default classes
+    for (int m = 10; m <= 12; ++m)
+        for (int f : {0, 4, 5}) {
+            if (f != 0 && dt != QS_C64) continue;
+            qs_status st = time_one(Cand{m, f, w0, p0});
+            if (st != QS_OK) return st;
+        }
+    // stage 2: workgroup classes around the defaults, at the best stage-1 setting
+    const Cand s1 = bc;
+    const Cand stage2[] = {{s1.m, s1.f, w0 - 1, p0}, {s1.m, s1.f, w0, p0 - 2}, {s1.m, s1.f, w0, p0 - 1},
+                           {s1.m, s1.f, w0, p0 + 1}, {s1.m, s1.f, w0, p0 + 2}};
+    for (const Cand& c : stage2) {
+        qs_status st = time_one(c);
+        if (st != QS_OK) return st;
     }
-    opts->tile_qubits = bm;
-    opts->fuse_k = bf;
+    opts->tile_qubits = bc.m;
+    opts->fuse_k = bc.f;
+    opts->whole_max = bc.w;
+    opts->persist_max = bc.p;
     if (n_out) *n_out = k;
     return QS_OK;
 }

@@ -414,10 +414,13 @@ def test_batch_tune(qs, dt):
     a batch with the tuned options matches the oracle."""
     sample = [W.rqc_chain(n, 8, 100 + n) for n in (14, 15, 16, 17, 18)] + [W.qft(n, n) for n in (15, 17)]
     best, rows = qs.qs_batch_tune(sample, dtype=dt)
-    expect = 9 if dt == 1 else 3
+    expect = (9 if dt == 1 else 3) + 5  # tile x fusion, then five workgroup-class variants
     assert len(rows) == expect and all(r["device_ms"] > 0 for r in rows)
-    assert (best["tile_qubits"], best["fuse_k"]) in [(r["tile_qubits"], r["fuse_k"]) for r in rows]
-    assert min(rows, key=lambda r: r["device_ms"])["tile_qubits"] == best["tile_qubits"]
+    keys = ("tile_qubits", "fuse_k", "whole_max", "persist_max")
+    fastest = min(rows, key=lambda r: r["device_ms"])
+    assert tuple(best[k] for k in keys) == tuple(fastest[k] for k in keys)
+    stage1 = min(rows[:expect - 5], key=lambda r: r["device_ms"])
+    assert all((r["tile_qubits"], r["fuse_k"]) == (stage1["tile_qubits"], stage1["fuse_k"]) for r in rows[expect - 5:])
     b = qs.qs_batch_submit(sample, dtype=dt, mode=0, **best)
     try:
         qs.qs_batch_wait(b)
@@ -456,3 +459,22 @@ def test_batch_probabilities_and_norm(qs, dt):
     with pytest.raises(qs.QSError):
         qs.qs_batch_probabilities(b, 0, list(range(circs[0].n + 1)))
     qs.qs_batch_release(b)
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("whole,persist", [(8, 12), (3, 9), (11, 18)])
+def test_batch_workgroup_classes(qs, dt, whole, persist):
+    """Non-default class boundaries (whole-in-LDS / persistent / pass-major),
+    including a whole-circuit limit below the tile size, match the oracle."""
+    circs = _batch_mix(6)
+    b = qs.qs_batch_submit(circs, dtype=dt, mode=0, whole_max=whole, persist_max=persist)
+    try:
+        qs.qs_batch_wait(b)
+        for i, c in enumerate(circs):
+            _check(qs.qs_batch_download(b, i, dt), oracle.run_circuit(c), dt, f"classes {whole}/{persist} {c.name}")
+    finally:
+        qs.qs_batch_release(b)
+    with pytest.raises(qs.QSError):
+        qs.qs_batch_submit(circs, dtype=dt, mode=0, whole_max=14)
+    with pytest.raises(qs.QSError):
+        qs.qs_batch_submit(circs, dtype=dt, mode=0, whole_max=10, persist_max=9)
