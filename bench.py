@@ -619,6 +619,15 @@ def run_serve(a, qs, torch, W):
     # saturated throughput with nothing alongside: the first requests all at once
     alone = _serve_stream(qs, circs[:sat_n], np.zeros(sat_n), dt)
     _log(f"serve saturated, alone: {alone['circuits_per_s']:.1f} circuits/s")
+    # the same requests as one fused batch: what the device does without the loop
+    t0 = time.perf_counter()
+    bb = qs.qs_batch_submit(circs[:sat_n], dtype=dt, mode=0)
+    qs.qs_batch_wait(bb)
+    t_b = time.perf_counter() - t0
+    as_batch = {"circuits_per_s": sat_n / t_b, "end_to_end_ms": 1e3 * t_b,
+                "device_ms": qs.qs_batch_get_stats(bb)["device_ms"]}
+    qs.qs_batch_release(bb)
+    _log(f"serve: the same {sat_n} requests as one batch: {as_batch['circuits_per_s']:.1f} circuits/s")
     big, hook, sat = None, None, alone
     if nb > 0:
         big = _BigJob(qs, torch, W, nb, max_blocks=a.big_blocks)
@@ -645,7 +654,8 @@ def run_serve(a, qs, torch, W):
                                 "register blocks, run forward and back for the whole stream" if nb else ""),
                    "requests": count, "qps": qps})
     out.update({"latency_ms": {"p50": main["p50_ms"], "p99": main["p99_ms"]}, "stream": main,
-                "saturated": sat, "saturated_alone": alone, "big_circuit": big, "qps_sweep": sweep or None})
+                "saturated": sat, "saturated_alone": alone, "same_requests_as_batch": as_batch,
+                "big_circuit": big, "qps_sweep": sweep or None})
     if big:
         ach = big["pass_gbs_algorithmic"]
         out["roofline"] = {"bound": "hbm", "kernel": f"tile passes of the n={nb} circuit (beside the stream)",

@@ -49,7 +49,12 @@ struct qs_batch_s {
         size_t persist_l0 = 0, stream_l0 = 0;
         int persist_count = 0, stream_count = 0, persist_m = 0, stream_m = 0;
         std::vector<std::pair<size_t, std::pair<int, uint32_t>>> rounds; // (entry offset, (count, blocks))
-        bool any_full = false;
+        // which launches need the full tile kernel (a pass with k >= 3 ops,
+        // fused blocks or ops outside segments); the others take the lean one,
+        // which holds fewer registers
+        std::vector<uint8_t> whole_full; // per whole group
+        bool persist_full = false;
+        std::vector<uint8_t> round_full; // per round
         const BatchCirc* dcirc = nullptr;
         const BatchPass* dpass = nullptr;
         const TileOp* dops = nullptr;
@@ -164,16 +169,17 @@ qs_status enqueue_fused(qs_batch b, bool mark)
             (void)hipEventDestroy(ev);
         }
     }
-    for (auto& g : S.whole_groups) {
+    for (size_t gi = 0; gi < S.whole_groups.size(); ++gi) {
+        const auto& g = S.whole_groups[gi];
         st = launched(launch_batch_whole(b->dt, g.first, b->arena, S.dcirc, S.dlist + g.second.first, g.second.second,
-                                         S.dpass, S.dops, S.dmats, S.any_full, s0),
+                                         S.dpass, S.dops, S.dmats, S.whole_full[gi] != 0, s0),
                       "batch whole launch");
         if (st != QS_OK) return st;
     }
     if (!S.whole_groups.empty()) mk(0, s0);
     if (S.persist_count > 0) {
         st = launched(launch_batch_persist(b->dt, S.persist_m, b->arena, S.dcirc, S.dlist + S.persist_l0,
-                                           S.persist_count, S.dpass, S.dops, S.dmats, S.any_full, s1),
+                                           S.persist_count, S.dpass, S.dops, S.dmats, S.persist_full, s1),
                       "batch persistent launch");
         if (st != QS_OK) return st;
         mk(1, s1);
@@ -181,7 +187,7 @@ qs_status enqueue_fused(qs_batch b, bool mark)
     for (size_t r = 0; r < S.rounds.size(); ++r) {
         st = launched(launch_batch_round(b->dt, S.stream_m, b->arena, S.dcirc, S.dpass, S.dops, S.dmats,
                                          S.dents + S.rounds[r].first, S.rounds[r].second.first,
-                                         S.rounds[r].second.second, S.any_full, sr),
+                                         S.rounds[r].second.second, S.round_full[r] != 0, sr),
                       "batch round launch");
         if (st != QS_OK) return st;
     }
@@ -450,7 +456,8 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         release(b);
         return st;
     }
-    std::vector<uint8_t> needs_full(count, 0);
+    std::vector<uint8_t> needs_full(count, 0);             // any pass of circuit i
+    std::vector<uint8_t> pass_full((size_t)pass0[count], 0); // per pass (global index)
     parallel_for(count, [&](int i) {
         double* M = (double*)(b->hbuf + o_mats) + mat0[i];
         if (b->mode == 1) {
@@ -482,7 +489,9 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
                 t.moff += (uint64_t)mat0[i];
                 *T++ = t;
             }
-            needs_full[i] |= ops_need_full(p.ops.data(), p.ops.size(), p.m);
+            const bool f = ops_need_full(p.ops.data(), p.ops.size(), p.m);
+            pass_full[(size_t)pass0[i] + j] = f;
+            needs_full[i] |= f;
             op += (int64_t)p.ops.size();
         }
         std::vector<PlanPass>().swap(passes);
@@ -528,8 +537,16 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         S.stream_count = stream_count;
         S.stream_m = stream_m;
         S.rounds = rounds;
-        S.any_full = false; // any pass needs the full tile kernel
-        for (uint8_t f : needs_full) S.any_full |= f != 0;
+        S.whole_full.assign(whole_groups.size(), 0);
+        for (size_t gi = 0; gi < whole_groups.size(); ++gi)
+            for (int k = 0; k < whole_groups[gi].second.second; ++k)
+                S.whole_full[gi] |= needs_full[lists[whole_groups[gi].second.first + k]];
+        S.persist_full = false;
+        for (int k = 0; k < persist_count; ++k) S.persist_full |= needs_full[lists[persist_l0 + k]] != 0;
+        S.round_full.assign(rounds.size(), 0);
+        for (size_t r = 0; r < rounds.size(); ++r)
+            for (int k = 0; k < rounds[r].second.first; ++k)
+                S.round_full[r] |= pass_full[(size_t)rents[rounds[r].first + k].pass];
         S.dcirc = dcirc;
         S.dpass = dpass;
         S.dops = dops;

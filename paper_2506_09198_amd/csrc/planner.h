@@ -221,19 +221,25 @@ hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCir
 // Round entries: blocks [first_block, first_block + 2^(n - M)) apply pass
 // `pass` to the request's state.  Whole entries (n <= M): one block runs the
 // request's single pass on a basis state built in LDS.
+// Byte offsets into the server's state pool (psi) and plan pool (the rest),
+// which the kernels receive as restrict arguments: with the op tables
+// reached from a restrict base the compiler keeps descriptor and matrix loads
+// scalar, as in the single-circuit tile kernel (loading the pointers from the
+// entry instead made every op a vector load and doubled the registers).
 struct ServeEntry {
-    void* psi;
-    const BatchPass* pass;
-    const TileOp* ops;     // base the pass's op0 indexes
-    const double* mats;    // base the ops' moff index
+    uint64_t psi_off;
+    uint64_t pass_off;     // UINT64_MAX: no pass (a whole circuit without gates)
+    uint64_t ops_off;      // base the pass's op0 indexes
+    uint64_t mats_off;     // base the ops' moff index
     uint64_t basis;
     uint32_t first_block;
     int32_t n;
 };
 
-hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool full,
-                              hipStream_t st);
-hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool full, hipStream_t st);
+hipError_t launch_serve_round(int dt, int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                              uint32_t nblocks, bool full, hipStream_t st);
+hipError_t launch_serve_whole(int dt, int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                              bool full, hipStream_t st);
 
 qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats);
 qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int tile_qubits, PlanOpts& po);

@@ -84,6 +84,8 @@ struct Req {
     uint64_t p_off = 0, p_bytes = 0;
     std::vector<char> plan_host; // kept until the request finishes (async upload source)
     int npass = 0, next_pass = 0;
+    std::vector<uint8_t> pass_full; // pass j needs the full tile kernel
+    bool any_full = false;
     bool whole = false, whole_launched = false;
     int64_t last_round = -1;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -118,7 +120,6 @@ struct qs_server_s {
     std::vector<uint64_t> active;
     std::deque<qs_result> completed;
     std::chrono::steady_clock::time_point t0;
-    bool any_full = false;
     qs_server_stats stats;
 };
 
@@ -247,7 +248,9 @@ qs_status admit_one(qs_server s, Req& r)
         d.op0 = (int)to.size();
         d.nops = (int)p.ops.size();
         for (auto& t : p.ops) to.push_back(t);
-        s->any_full |= ops_need_full(p.ops.data(), p.ops.size(), p.m); // sticky: the full kernel from then on
+        const bool f = ops_need_full(p.ops.data(), p.ops.size(), p.m);
+        r.pass_full.push_back(f);
+        r.any_full |= f;
         bp.push_back(d);
     }
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
@@ -321,36 +324,39 @@ bool build_round(qs_server s)
     if (!sl) return false;
     std::vector<ServeEntry> whole_e, round_e;
     std::vector<int> whole_n;
+    std::vector<uint8_t> whole_f; // per whole entry: needs the full kernel
+    bool round_f = false;
     std::vector<uint64_t> ids;
     uint32_t blocks = 0;
     for (uint64_t id : s->active) {
         Req& r = s->reqs[id];
-        const char* pbase = s->plan + r.p_off;
         if (r.whole) {
             if (r.whole_launched) continue;
             ServeEntry en;
             std::memset(&en, 0, sizeof en);
-            en.psi = s->pool + r.s_off;
-            en.pass = r.npass ? (const BatchPass*)(pbase + r.passes_off) : nullptr;
-            en.ops = (const TileOp*)(pbase + r.ops_off);
-            en.mats = (const double*)(pbase + r.mats_off);
+            en.psi_off = r.s_off;
+            en.pass_off = r.npass ? r.p_off + r.passes_off : ~0ull;
+            en.ops_off = r.p_off + r.ops_off;
+            en.mats_off = r.p_off + r.mats_off;
             en.basis = r.basis;
             en.n = r.n;
             whole_e.push_back(en);
             whole_n.push_back(r.n);
+            whole_f.push_back(r.any_full);
             ids.push_back(id);
         } else if (r.next_pass < r.npass || (r.npass == 0 && r.last_round < 0)) {
             if (r.npass > 0) {
                 ServeEntry en;
                 std::memset(&en, 0, sizeof en);
-                en.psi = s->pool + r.s_off;
-                en.pass = (const BatchPass*)(pbase + r.passes_off) + r.next_pass;
-                en.ops = (const TileOp*)(pbase + r.ops_off);
-                en.mats = (const double*)(pbase + r.mats_off);
+                en.psi_off = r.s_off;
+                en.pass_off = r.p_off + r.passes_off + (uint64_t)r.next_pass * sizeof(BatchPass);
+                en.ops_off = r.p_off + r.ops_off;
+                en.mats_off = r.p_off + r.mats_off;
                 en.n = r.n;
                 en.first_block = blocks;
                 blocks += 1u << (r.n - s->m);
                 round_e.push_back(en);
+                round_f |= r.pass_full[(size_t)r.next_pass] != 0;
             }
             ids.push_back(id);
         }
@@ -386,12 +392,13 @@ bool build_round(qs_server s)
     if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "round upload: %s", hipGetErrorString(e));
     for (size_t i = 0; i < order.size() && st == QS_OK;) {
         size_t j = i;
-        while (j < order.size() && whole_n[order[j]] == whole_n[order[i]]) ++j;
+        bool full = false;
+        while (j < order.size() && whole_n[order[j]] == whole_n[order[i]]) full |= whole_f[order[j++]] != 0;
         if (inject_fault_now()) {
             st = set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
             break;
         }
-        e = launch_serve_whole(s->dt, whole_n[order[i]], sl->dev + i, (int)(j - i), s->any_full, s->st);
+        e = launch_serve_whole(s->dt, whole_n[order[i]], s->pool, s->plan, sl->dev + i, (int)(j - i), full, s->st);
         s->stats.launches += 1;
         if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "whole launch: %s", hipGetErrorString(e));
         i = j;
@@ -400,8 +407,8 @@ bool build_round(qs_server s)
         if (inject_fault_now()) {
             st = set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
         } else {
-            e = launch_serve_round(s->dt, s->m, sl->dev + whole_e.size(), (int)round_e.size(), blocks, s->any_full,
-                                   s->st);
+            e = launch_serve_round(s->dt, s->m, s->pool, s->plan, sl->dev + whole_e.size(), (int)round_e.size(), blocks,
+                                   round_f, s->st);
             s->stats.launches += 1;
             if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "round launch: %s", hipGetErrorString(e));
         }

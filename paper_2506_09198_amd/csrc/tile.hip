@@ -961,7 +961,8 @@ static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const Batc
 
 template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
-k_serve_round(const ServeEntry* __restrict__ entries, int nentries)
+k_serve_round(char* __restrict__ pool, const char* __restrict__ plan, const ServeEntry* __restrict__ entries,
+              int nentries)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
@@ -977,21 +978,22 @@ k_serve_round(const ServeEntry* __restrict__ entries, int nentries)
             hi = mid - 1;
     }
     const ServeEntry& en = entries[lo];
-    const BatchPass& bp = *en.pass;
-    V* psi = (V*)en.psi;
+    const BatchPass& bp = *(const BatchPass*)(plan + en.pass_off);
+    V* psi = (V*)(pool + en.psi_off);
     build_hoff(hoff, M, bp.L, bp.q);
     __syncthreads();
     const uint64_t base = ins_bits((uint64_t)(blockIdx.x - en.first_block), bp.ip);
     const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
     tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
     __syncthreads();
-    tile_ops<R, M, FULL>(tile, base, en.ops + bp.op0, bp.nops, en.mats);
+    tile_ops<R, M, FULL>(tile, base, (const TileOp*)(plan + en.ops_off) + bp.op0, bp.nops,
+                         (const double*)(plan + en.mats_off));
     tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
 }
 
 template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
-k_serve_whole(const ServeEntry* __restrict__ entries)
+k_serve_whole(char* __restrict__ pool, const char* __restrict__ plan, const ServeEntry* __restrict__ entries)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
@@ -1007,12 +1009,17 @@ k_serve_whole(const ServeEntry* __restrict__ entries)
     }
     if (threadIdx.x == 0) hoff[0] = 0;
     __syncthreads();
-    if (en.pass) tile_ops<R, M, FULL>(tile, 0, en.ops + en.pass->op0, en.pass->nops, en.mats);
-    tile_store<R, M>((V*)en.psi, 0, M, hoff, tile, M >= 4 ? 1 : 0);
+    if (en.pass_off != ~0ull) {
+        const BatchPass& bp = *(const BatchPass*)(plan + en.pass_off);
+        tile_ops<R, M, FULL>(tile, 0, (const TileOp*)(plan + en.ops_off) + bp.op0, bp.nops,
+                             (const double*)(plan + en.mats_off));
+    }
+    tile_store<R, M>((V*)(pool + en.psi_off), 0, M, hoff, tile, M >= 4 ? 1 : 0);
 }
 
 template <typename R, int M, bool FULL>
-static hipError_t launch_serve_round_m(const ServeEntry* entries, int nentries, uint32_t nblocks, hipStream_t st)
+static hipError_t launch_serve_round_m(char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                                       uint32_t nblocks, hipStream_t st)
 {
     const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
     const size_t lds = lds_max > 163840 ? 163840 : lds_max;
@@ -1025,12 +1032,13 @@ static hipError_t launch_serve_round_m(const ServeEntry* entries, int nentries, 
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_serve_round<R, M, FULL>), dim3(nblocks), dim3(256), lds, st, entries, nentries);
+    hipLaunchKernelGGL((k_serve_round<R, M, FULL>), dim3(nblocks), dim3(256), lds, st, pool, plan, entries, nentries);
     return hipGetLastError();
 }
 
 template <typename R, int M, bool FULL>
-static hipError_t launch_serve_whole_m(const ServeEntry* entries, int nentries, hipStream_t st)
+static hipError_t launch_serve_whole_m(char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                                       hipStream_t st)
 {
     const size_t lds = sizeof(typename CT<R>::V) * (1ull << M) + 16;
     if (lds > 65536) {
@@ -1042,7 +1050,7 @@ static hipError_t launch_serve_whole_m(const ServeEntry* entries, int nentries, 
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_serve_whole<R, M, FULL>), dim3(nentries), dim3(256), lds, st, entries);
+    hipLaunchKernelGGL((k_serve_whole<R, M, FULL>), dim3(nentries), dim3(256), lds, st, pool, plan, entries);
     return hipGetLastError();
 }
 
@@ -1252,11 +1260,12 @@ hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCir
 }
 
 template <typename R, bool FULL>
-static hipError_t serve_round_r(int M, const ServeEntry* entries, int nentries, uint32_t nblocks, hipStream_t st)
+static hipError_t serve_round_r(int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                                uint32_t nblocks, hipStream_t st)
 {
     switch (M) {
 #define QS_SRCASE(MM) \
-    case MM: return launch_serve_round_m<R, MM, FULL>(entries, nentries, nblocks, st);
+    case MM: return launch_serve_round_m<R, MM, FULL>(pool, plan, entries, nentries, nblocks, st);
         QS_SRCASE(9) QS_SRCASE(10) QS_SRCASE(11) QS_SRCASE(12) QS_SRCASE(13)
 #undef QS_SRCASE
     default: return hipErrorInvalidValue;
@@ -1264,11 +1273,12 @@ static hipError_t serve_round_r(int M, const ServeEntry* entries, int nentries, 
 }
 
 template <typename R, bool FULL>
-static hipError_t serve_whole_r(int M, const ServeEntry* entries, int nentries, hipStream_t st)
+static hipError_t serve_whole_r(int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                                hipStream_t st)
 {
     switch (M) {
 #define QS_SWCASE(MM) \
-    case MM: return launch_serve_whole_m<R, MM, FULL>(entries, nentries, st);
+    case MM: return launch_serve_whole_m<R, MM, FULL>(pool, plan, entries, nentries, st);
         QS_SWCASE(1) QS_SWCASE(2) QS_SWCASE(3) QS_SWCASE(4) QS_SWCASE(5) QS_SWCASE(6) QS_SWCASE(7)
         QS_SWCASE(8) QS_SWCASE(9) QS_SWCASE(10) QS_SWCASE(11) QS_SWCASE(12) QS_SWCASE(13)
 #undef QS_SWCASE
@@ -1276,25 +1286,26 @@ static hipError_t serve_whole_r(int M, const ServeEntry* entries, int nentries, 
     }
 }
 
-hipError_t launch_serve_round(int dt, int M, const ServeEntry* entries, int nentries, uint32_t nblocks, bool full,
-                              hipStream_t st)
+hipError_t launch_serve_round(int dt, int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                              uint32_t nblocks, bool full, hipStream_t st)
 {
     if (nentries <= 0 || nblocks == 0) return hipSuccess;
     if (dt == QS_C128)
-        return full ? serve_round_r<double, true>(M, entries, nentries, nblocks, st)
-                  : serve_round_r<double, false>(M, entries, nentries, nblocks, st);
-    return full ? serve_round_r<float, true>(M, entries, nentries, nblocks, st)
-              : serve_round_r<float, false>(M, entries, nentries, nblocks, st);
+        return full ? serve_round_r<double, true>(M, pool, plan, entries, nentries, nblocks, st)
+                  : serve_round_r<double, false>(M, pool, plan, entries, nentries, nblocks, st);
+    return full ? serve_round_r<float, true>(M, pool, plan, entries, nentries, nblocks, st)
+              : serve_round_r<float, false>(M, pool, plan, entries, nentries, nblocks, st);
 }
 
-hipError_t launch_serve_whole(int dt, int M, const ServeEntry* entries, int nentries, bool full, hipStream_t st)
+hipError_t launch_serve_whole(int dt, int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
+                              bool full, hipStream_t st)
 {
     if (nentries <= 0) return hipSuccess;
     if (dt == QS_C128)
-        return full ? serve_whole_r<double, true>(M, entries, nentries, st)
-                  : serve_whole_r<double, false>(M, entries, nentries, st);
-    return full ? serve_whole_r<float, true>(M, entries, nentries, st)
-              : serve_whole_r<float, false>(M, entries, nentries, st);
+        return full ? serve_whole_r<double, true>(M, pool, plan, entries, nentries, st)
+                  : serve_whole_r<double, false>(M, pool, plan, entries, nentries, st);
+    return full ? serve_whole_r<float, true>(M, pool, plan, entries, nentries, st)
+              : serve_whole_r<float, false>(M, pool, plan, entries, nentries, st);
 }
 
 hipError_t launch_tile_pass(void* psi, int dt, int n, const PlanPass& pass, const TileOp* dops,
