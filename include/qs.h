@@ -170,7 +170,7 @@ typedef struct {
     int32_t fuse_k;      /* max qubits of a fused dense block; 0 = default */
     int32_t tile_qubits; /* qubits held in LDS per tile; 0 = default */
     int32_t max_blocks;  /* cap on the workgroups of each tile-pass launch (they stride over
-                            the tiles); 0 = default (2048).  A lower cap leaves compute units
+                            the tiles); 0 = default (65536).  A lower cap leaves compute units
                             to other streams, e.g. a serving loop beside a long run, at the
                             cost of this run's speed */
     int32_t remap;       /* 0 = auto: an uncontrolled SWAP gate becomes a relabeling of qubits
