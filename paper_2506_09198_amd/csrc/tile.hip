@@ -883,34 +883,47 @@ template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_batch_round(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const BatchPass* __restrict__ passes,
               const TileOp* __restrict__ ops, const double* __restrict__ mats,
-              const RoundEntry* __restrict__ entries, int nentries)
+              const RoundEntry* __restrict__ entries, int nentries, uint32_t ntiles)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
     extern __shared__ __align__(16) unsigned char smem[];
     V* tile = (V*)smem;
     uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
-    // the entry owning this block: last one with first_block <= blockIdx.x
-    int lo = 0, hi = nentries - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (entries[mid].first_block <= blockIdx.x)
-            lo = mid;
-        else
-            hi = mid - 1;
+    // blocks loop over the round's tiles (numbered across its entries)
+    for (uint32_t g = blockIdx.x; g < ntiles; g += gridDim.x) {
+        // the entry owning tile g: last one with first_block <= g
+        int lo = 0, hi = nentries - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (entries[mid].first_block <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const RoundEntry& en = entries[lo];
+        const BatchCirc& c = circs[en.circ];
+        const BatchPass& bp = passes[en.pass];
+        V* psi = (V*)(arena + c.psi_off);
+        build_hoff(hoff, M, bp.L, bp.q);
+        __syncthreads();
+        const uint64_t base = ins_bits((uint64_t)(g - en.first_block), bp.ip);
+        const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
+        tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
+        __syncthreads();
+        tile_ops<R, M, FULL>(tile, base, ops + bp.op0, bp.nops, mats);
+        tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
+        __syncthreads(); // the next tile rewrites hoff and the tile
     }
-    const RoundEntry& en = entries[lo];
-    const BatchCirc& c = circs[en.circ];
-    const BatchPass& bp = passes[en.pass];
-    V* psi = (V*)(arena + c.psi_off);
-    build_hoff(hoff, M, bp.L, bp.q);
-    __syncthreads();
-    const uint64_t base = ins_bits((uint64_t)(blockIdx.x - en.first_block), bp.ip);
-    const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
-    tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
-    __syncthreads();
-    tile_ops<R, M, FULL>(tile, base, ops + bp.op0, bp.nops, mats);
-    tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
+}
+
+// Grid of the round kernels: blocks loop over tiles, as in the single-circuit
+// tile pass (65536 blocks measured best there).
+static unsigned round_grid(uint32_t ntiles)
+{
+    static const int cap = env_int("QS_ROUND_GRID_CAP", 65536);
+    const uint32_t c = cap > 0 ? (uint32_t)cap : 65536u;
+    return ntiles < c ? ntiles : c;
 }
 
 template <typename V>
@@ -954,41 +967,44 @@ static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const Batc
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_batch_round<R, M, FULL>), dim3(nblocks), dim3(256), lds, st, arena, circs, passes, ops, mats,
-                       entries, nentries);
+    hipLaunchKernelGGL((k_batch_round<R, M, FULL>), dim3(round_grid(nblocks)), dim3(256), lds, st, arena, circs, passes,
+                       ops, mats, entries, nentries, nblocks);
     return hipGetLastError();
 }
 
 template <typename R, int M, bool FULL>
 __global__ void __launch_bounds__(256)
 k_serve_round(char* __restrict__ pool, const char* __restrict__ plan, const ServeEntry* __restrict__ entries,
-              int nentries)
+              int nentries, uint32_t ntiles)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
     extern __shared__ __align__(16) unsigned char smem[];
     V* tile = (V*)smem;
     uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
-    int lo = 0, hi = nentries - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (entries[mid].first_block <= blockIdx.x)
-            lo = mid;
-        else
-            hi = mid - 1;
+    for (uint32_t g = blockIdx.x; g < ntiles; g += gridDim.x) {
+        int lo = 0, hi = nentries - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (entries[mid].first_block <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const ServeEntry& en = entries[lo];
+        const BatchPass& bp = *(const BatchPass*)(plan + en.pass_off);
+        V* psi = (V*)(pool + en.psi_off);
+        build_hoff(hoff, M, bp.L, bp.q);
+        __syncthreads();
+        const uint64_t base = ins_bits((uint64_t)(g - en.first_block), bp.ip);
+        const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
+        tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
+        __syncthreads();
+        tile_ops<R, M, FULL>(tile, base, (const TileOp*)(plan + en.ops_off) + bp.op0, bp.nops,
+                             (const double*)(plan + en.mats_off));
+        tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
+        __syncthreads(); // the next tile rewrites hoff and the tile
     }
-    const ServeEntry& en = entries[lo];
-    const BatchPass& bp = *(const BatchPass*)(plan + en.pass_off);
-    V* psi = (V*)(pool + en.psi_off);
-    build_hoff(hoff, M, bp.L, bp.q);
-    __syncthreads();
-    const uint64_t base = ins_bits((uint64_t)(blockIdx.x - en.first_block), bp.ip);
-    const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
-    tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
-    __syncthreads();
-    tile_ops<R, M, FULL>(tile, base, (const TileOp*)(plan + en.ops_off) + bp.op0, bp.nops,
-                         (const double*)(plan + en.mats_off));
-    tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
 }
 
 template <typename R, int M, bool FULL>
@@ -1032,7 +1048,8 @@ static hipError_t launch_serve_round_m(char* pool, const char* plan, const Serve
             set = true;
         }
     }
-    hipLaunchKernelGGL((k_serve_round<R, M, FULL>), dim3(nblocks), dim3(256), lds, st, pool, plan, entries, nentries);
+    hipLaunchKernelGGL((k_serve_round<R, M, FULL>), dim3(round_grid(nblocks)), dim3(256), lds, st, pool, plan, entries,
+                       nentries, nblocks);
     return hipGetLastError();
 }
 
