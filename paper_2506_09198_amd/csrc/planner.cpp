@@ -969,11 +969,16 @@ static int default_tile_qubits(int dt)
     return 11; // measured best for both types on the random chain and QFT circuits
 }
 
+// Qubits 0..L-1 are forced into every tile, so tiles load and store runs of
+// 2^L amplitudes.  Measured on the 32-qubit chain circuit and QFT with
+// 11-qubit tiles: L = 4 for complex128 (256-byte runs; 3 % faster than 5) and
+// L = 5 for complex64 (256-byte runs; 8 % faster than 6) -- fewer forced
+// qubits leave more room for gate qubits, so passes are fewer.
 static int default_low_qubits(int dt)
 {
     const int e = env_int("QS_TILE_LOW", -1);
     if (e >= 0) return e;
-    return dt == QS_C128 ? 5 : 6;
+    return dt == QS_C128 ? 4 : 5;
 }
 
 static qs_status plan_opts(int dt, const qs_op* ops, int64_t n_ops, const qs_run_opts& o, PlanOpts& po)
