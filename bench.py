@@ -120,13 +120,16 @@ def cpu_baseline_sweep(n_cpu: int) -> dict:
 
     c = W.gate_microbench(n_cpu)
     ops, mats = c.arrays()
-    psi = W.random_state(n_cpu, 2)
-    t0 = time.perf_counter()
-    oracle.run(n_cpu, ops, mats, psi)
-    dt = time.perf_counter() - t0
-    return {"value": _updates(n_cpu, ops) / dt, "unit": "amp-updates/s", "cores": oracle.num_threads(),
+    psi = np.ascontiguousarray(W.random_state(n_cpu, 2), dtype=np.complex128)
+    passes, dt = 0, 0.0
+    while passes < 4 and (passes == 0 or dt < 10.0):  # about 10-30 s of host work
+        t0 = time.perf_counter()
+        oracle.run_inplace(n_cpu, ops, mats, psi)
+        dt += time.perf_counter() - t0
+        passes += 1
+    return {"value": passes * _updates(n_cpu, ops) / dt, "unit": "amp-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"gate sweep at n={n_cpu} complex128 ({len(ops)} gates, one pass, {dt:.1f} s)"}
+            "sample": f"gate sweep at n={n_cpu} complex128 ({len(ops)} gates, {passes} passes, {dt:.1f} s)"}
 
 
 def cpu_baseline_circuits(n_cpu: int) -> dict:
@@ -300,7 +303,7 @@ def run_sweep(a, qs, torch, W):
         "diag_sweep": diag,
     })
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_sweep(a.cpu_n or 26)
+        out["cpu_baseline"] = cpu_baseline_sweep(a.cpu_n or 28)
     return out
 
 

@@ -96,6 +96,18 @@ def run(n: int, ops: np.ndarray, mats: np.ndarray, psi: np.ndarray | None = None
     return psi
 
 
+def run_inplace(n: int, ops: np.ndarray, mats: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """As run(), but applies the ops to psi itself (C-contiguous complex128,
+    2^n amplitudes) without copying it first."""
+    assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.size == 1 << n
+    mats = np.ascontiguousarray(mats, dtype=np.float64)
+    if len(ops):
+        ops = np.ascontiguousarray(ops)
+        assert ops.dtype.itemsize == 64
+        lib().orc_run(n, _dp(psi), ops.ctypes.data, len(ops), _dp(mats) if mats.size else None)
+    return psi
+
+
 def run_circuit(circ, psi: np.ndarray | None = None) -> np.ndarray:
     ops, mats = circ.arrays()
     return run(circ.n, ops, mats, psi, circ.init_basis)
