@@ -211,20 +211,20 @@ static int env_slog()
     return v;
 }
 
-// Slots per lane by register count (about 4 amplitudes in flight per lane by
-// default; QS_PPL_H<NH> overrides for tuning).
+// Slots per lane by the number of high targets (QS_PPL_H<NH> overrides for
+// tuning).
 template <typename R, int K, int NH>
 static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
 {
     static int ppl_env = env_int(NH == 0 ? "QS_PPL_H0" : (NH == 1 ? "QS_PPL_H1" : "QS_PPL_H2"), 0);
-    // Measured on MI355X (n=30 c128, every target): 4 slots without high
-    // targets; one high target (1q, or 2q with the other target low): 1 slot
-    // while its partner is less than 16 MiB away (t < 20), 2 beyond (150-300
-    // GB/s either way); two high targets: 1 slot, except both at bit 18 or
-    // above, where 2 slots recover 10-15% (their four streams are megabytes
-    // apart).
+    // Measured on MI355X (n=30 c128, every target): 8 slots without high
+    // targets (2-3 % over 4); one high target (1q, or 2q with the other
+    // target low): 1 slot while its partner is less than 16 MiB away
+    // (t < 20), 2 beyond (150-300 GB/s either way); two high targets: 1 slot,
+    // except both at bit 18 or above, where 2 slots recover 10-15% (their
+    // four streams are megabytes apart).
     using V = typename CT<R>::V;
-    int ppl = NH == 0 ? 4
+    int ppl = NH == 0 ? 8
               : NH == 1 ? (ga.roff[1] * sizeof(V) < (16ull << 20) ? 1 : 2)
                         : (ga.roff[1] >= (1ull << 18) && ga.roff[2] >= (1ull << 18) ? 2 : 1);
     if (ppl_env > 0) ppl = ppl_env;
@@ -235,12 +235,18 @@ static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
         ga.nblocks = (ga.C + 256 * P - 1) / (256 * P);
         launch_gate_p<R, K, NH, P>(psi, ga, nt, st);
     };
-    if (ppl == 1)
+    if (ppl == 1) {
         go(std::integral_constant<int, 1>());
-    else if (ppl == 4)
+    } else if (ppl == 4) {
         go(std::integral_constant<int, 4>());
-    else
+    } else if (ppl == 8) {
+        if constexpr (NH == 0)
+            go(std::integral_constant<int, 8>());
+        else
+            go(std::integral_constant<int, 4>());
+    } else {
         go(std::integral_constant<int, 2>());
+    }
 }
 
 template <typename R>
