@@ -471,6 +471,33 @@ qs_status qs_trace_enable(qs_state s, int on);
 /* Wait for traced work and copy up to `max` records; *count = records copied. */
 qs_status qs_trace_read(qs_state s, qs_trace_rec* out, int max, int* count);
 
+/* ------------------------------------------------------------------ launch knobs */
+
+/* Launch knobs that change how work is spread over the GPU, never what is
+ * computed: every setting gives bitwise the same results.  Each starts at its
+ * built-in default, or at its environment variable (in brackets) when that is
+ * set when the library first reads a knob.
+ *   gate_grid_cap     [QS_GATE_GRID_CAP]  workgroups of one per-gate or diagonal
+ *                                         launch, 1..2^22 (default 2^22); the
+ *                                         workgroups loop over the rest
+ *   tile_grid_cap     [QS_TILE_GRID_CAP]  workgroups of a tile pass (65536)
+ *   round_grid_cap    [QS_ROUND_GRID_CAP] workgroups of a batch / serving round (65536)
+ *   aux_grid_cap      [QS_GRID_CAP]       workgroups of init and dense k-qubit kernels (16384)
+ *   nontemporal       [QS_NT]             1 = streaming loads/stores where whole lines are written
+ *   slot_spread_log2  [QS_SLOG]           per-gate kernel: counter distance of a lane's slots (11)
+ *   slots_no_high, slots_one_high, slots_two_high  [QS_PPL_H0/H1/H2]
+ *                                         per-gate kernel: slots per lane for gates with 0, 1 or
+ *                                         2 targets at bit 6 or above (1, 2, 4 or 8; 0 = built-in
+ *                                         table)
+ *   diag_spread_log2  [QS_DIAG_SLOG]      diagonal kernel slot distance (11)
+ *   perm_run_log2     [QS_PERM_RUN]       restore pass run length (0 = built-in)
+ * qs_tunable_set stores `value` (value < 0: back to the default / environment
+ * value); QS_ERR_ARG for an unknown name or a value outside the knob's range.
+ * Knobs are process-wide and may be changed from any thread; a launch being
+ * set up concurrently may still use the old value. */
+qs_status qs_tunable_set(const char* name, int64_t value);
+qs_status qs_tunable_get(const char* name, int64_t* value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -148,6 +148,8 @@ def _load():
         "qs_server_destroy": ([vp], i32),
         "qs_trace_enable": ([vp, i32], i32),
         "qs_trace_read": ([vp, vp, i32, ctypes.POINTER(i32)], i32),
+        "qs_tunable_set": ([ctypes.c_char_p, ctypes.c_int64], i32),
+        "qs_tunable_get": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -226,6 +228,37 @@ def qs_get_info(s: int):
     n, dt, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_void_p()
     _check(lib.qs_get_info(ctypes.c_void_p(s), ctypes.byref(n), ctypes.byref(dt), ctypes.byref(p)))
     return n.value, dt.value, p.value
+
+
+def qs_tunable_set(name: str, value: int):
+    """Set a launch knob (value < 0 restores its default / environment value)."""
+    _check(lib.qs_tunable_set(name.encode(), int(value)))
+
+
+def qs_tunable_get(name: str) -> int:
+    v = ctypes.c_int64()
+    _check(lib.qs_tunable_get(name.encode(), ctypes.byref(v)))
+    return v.value
+
+
+class tunables:
+    """Context manager that sets launch knobs and restores them on exit:
+    ``with tunables(gate_grid_cap=3, tile_grid_cap=2): ...``."""
+
+    def __init__(self, **knobs):
+        self.knobs = knobs
+        self.saved = {}
+
+    def __enter__(self):
+        for k, v in self.knobs.items():
+            self.saved[k] = qs_tunable_get(k)
+            qs_tunable_set(k, v)
+        return self
+
+    def __exit__(self, *exc):
+        for k, v in self.saved.items():
+            qs_tunable_set(k, v)
+        return False
 
 
 def qs_init_basis(s: int, x: int):

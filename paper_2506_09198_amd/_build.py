@@ -34,7 +34,8 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 # unrolled code, each with compile-time register indices.  LLVM's CFG
 # sinking/hoisting would merge those copies into one with a runtime index,
 # which moves the register array to scratch memory.
-EXTRA = {"tile.hip": ["-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-simplifycfg-hoist-common=false"]}
+_NOSINK = ["-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-simplifycfg-hoist-common=false"]
+EXTRA = {"tile.hip": _NOSINK, "tile_batch.hip": _NOSINK, "tile_serve.hip": _NOSINK}
 
 
 def _compile(src: str) -> str:

@@ -78,10 +78,11 @@ template <typename R, int PPL>
 void launch_diag_t(void* psi, DiagArgs& a, hipStream_t st)
 {
     using V = typename CT<R>::V;
-    static const int sl = env_int("QS_DIAG_SLOG", 11);
+    const int sl = (int)tun(T_DIAG_SLOG);
     a.slog = a.C >= ((1ull << sl) * PPL) ? sl : 8;
     a.nblocks = (a.C + 256 * PPL - 1) / (256 * PPL);
-    const unsigned g = (unsigned)(a.nblocks < (1ull << 22) ? a.nblocks : (1ull << 22));
+    const uint64_t cap = (uint64_t)tun(T_GATE_GRID_CAP);
+    const unsigned g = (unsigned)(a.nblocks < cap ? a.nblocks : cap);
     if (a.C >= 64)
         hipLaunchKernelGGL((k_diag<R, PPL, true>), dim3(g), dim3(256), 0, st, (V*)psi, a);
     else

@@ -26,17 +26,13 @@ InsertPlan make_insert_plan(uint64_t mask)
     return p;
 }
 
-static int grid_cap()
-{
-    static int cap = env_int("QS_GRID_CAP", 256 * 64);
-    return cap;
-}
+static uint64_t grid_cap() { return (uint64_t)tun(T_AUX_GRID_CAP); }
 
 static unsigned blocks_for(uint64_t items, uint64_t per_block)
 {
     uint64_t b = (items + per_block - 1) / per_block;
     if (b < 1) b = 1;
-    if (b > (uint64_t)grid_cap()) b = grid_cap();
+    if (b > grid_cap()) b = grid_cap();
     return (unsigned)b;
 }
 

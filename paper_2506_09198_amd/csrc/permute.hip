@@ -16,6 +16,7 @@
 // workgroup loads tiles t and t' (runs of 2^K consecutive amplitudes) into
 // LDS and writes each back permuted into the other, so every access is
 // coalesced and each amplitude is read and written once.
+#include <algorithm>
 #include <cstring>
 
 #include "device_common.h"
@@ -98,7 +99,7 @@ hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipSt
     // 30 qubits (QFT restore): 256-byte runs are best -- Kr = 5 for complex64
     // (2.7 TB/s; Kr = 6 needs 64 KiB of LDS per block and drops to 1.1),
     // Kr = 4 for complex128 (3.3 TB/s against 3.0 at Kr = 5).
-    static const int kenv = env_int("QS_PERM_RUN", 0);
+    const int kenv = (int)tun(T_PERM_RUN);
     const int Kr = (kenv >= 4 && kenv <= (dt == QS_C128 ? 5 : 6)) ? kenv : (dt == QS_C128 ? 4 : 5);
     const int K = n < Kr ? n : Kr;
     uint64_t T = 0;
@@ -118,7 +119,9 @@ hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipSt
         }
     a.ip = make_insert_plan(T);
     a.ntiles = 1ull << (n - a.nt);
-    const unsigned g = (unsigned)(a.ntiles < (1ull << 20) ? a.ntiles : (1ull << 20));
+    // up to 2^20 workgroups (fewer with a lower gate_grid_cap); they loop over the tile pairs
+    const uint64_t cap = std::min<uint64_t>(1ull << 20, (uint64_t)tun(T_GATE_GRID_CAP));
+    const unsigned g = (unsigned)(a.ntiles < cap ? a.ntiles : cap);
     if (dt == QS_C128) {
         if (Kr == 4)
             hipLaunchKernelGGL((k_bit_involution<double2, 4>), dim3(g), dim3(256), 0, st, (double2*)psi, a);

@@ -81,8 +81,29 @@ uint64_t reduce_scratch_doubles(int n, int m);
 hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m,
                                 double* part, double* dev_out, hipStream_t st);
 
-// Environment-tunable launch knobs (read once).
+// Environment variable as an int (dflt when unset or empty).
 int env_int(const char* name, int dflt);
+
+// Launch knobs (tunables.cpp): default, else the environment variable read on
+// first use, else the value last given to qs_tunable_set.
+enum Tun {
+    T_GATE_GRID_CAP,   // workgroups of a per-gate / diagonal launch (they loop beyond it)
+    T_TILE_GRID_CAP,   // workgroups of a tile pass
+    T_ROUND_GRID_CAP,  // workgroups of a batch / serving round
+    T_AUX_GRID_CAP,    // workgroups of init, dense k-qubit and other grid-stride kernels
+    T_NT,              // non-temporal loads/stores where whole lines are written
+    T_SLOG,            // per-gate kernel: log2 of the counter distance between a lane's slots
+    T_PPL_H0,          // per-gate kernel: slots per lane (0 = built-in table) without high targets,
+    T_PPL_H1,          //   with one high target,
+    T_PPL_H2,          //   with two
+    T_DIAG_SLOG,       // diagonal kernel: log2 slot distance
+    T_PERM_RUN,        // restore pass: log2 run length (0 = built-in choice)
+    T_COUNT
+};
+int64_t tun(Tun id);
+// Opt a kernel in to `bytes` of dynamic LDS on the current device (no-op up
+// to 64 KiB; remembered per kernel and device; thread-safe).
+hipError_t lds_optin(const void* fn, size_t bytes);
 
 inline size_t amp_bytes(int dt) { return dt == QS_C128 ? 16 : 8; }
 

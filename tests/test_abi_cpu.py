@@ -180,3 +180,22 @@ def test_unitarity_check_is_opt_in(qs, monkeypatch):
         qs.qs_plan_circuit(3, qs.QS_C128, ops, bad)
     assert e.value.status == qs.QS_ERR_ARG and "unitary" in qs.qs_last_error()
     qs.qs_plan_circuit(3, qs.QS_C128, ops, mats)  # the real gates pass
+
+
+def test_tunables_roundtrip_and_validation():
+    import paper_2506_09198_amd as qs
+
+    d = qs.qs_tunable_get("gate_grid_cap")
+    qs.qs_tunable_set("gate_grid_cap", 7)
+    assert qs.qs_tunable_get("gate_grid_cap") == 7
+    with qs.tunables(gate_grid_cap=3, tile_grid_cap=2):
+        assert qs.qs_tunable_get("gate_grid_cap") == 3 and qs.qs_tunable_get("tile_grid_cap") == 2
+    assert qs.qs_tunable_get("gate_grid_cap") == 7
+    qs.qs_tunable_set("gate_grid_cap", -1)
+    assert qs.qs_tunable_get("gate_grid_cap") == d
+    with pytest.raises(qs.QSError):
+        qs.qs_tunable_set("gate_grid_cap", 0)
+    with pytest.raises(qs.QSError):
+        qs.qs_tunable_set("slots_one_high", 9)
+    with pytest.raises(qs.QSError):
+        qs.qs_tunable_set("no_such_knob", 1)

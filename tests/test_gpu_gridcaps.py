@@ -1,0 +1,158 @@
+"""Block-loop paths against the oracle, and grid-size independence.
+
+Every looping kernel (per-gate and diagonal gates, tile passes, batch and
+serving rounds, the restore pass, grid-stride helpers) is driven with its
+workgroup cap forced down to a few blocks, so that each workgroup walks many
+chunks, tiles or entries.  Each run is compared element by element with the
+FP64 oracle, and runs under different caps must agree bit for bit: every
+amplitude is produced by exactly one lane from the same inputs in the same
+order whatever the grid, so the grid can change nothing (the race guard of
+the batch and serving rounds)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+CAPS = [1, 3, 5, None]  # None = library default
+
+
+@pytest.fixture(scope="module")
+def qs():
+    import paper_2506_09198_amd as qs
+
+    assert qs.qs_device_count() >= 1, "no HIP device visible"
+    return qs
+
+
+def _check(got, want, dt, what):
+    got = got.astype(np.complex128)
+    err = float(np.max(np.abs(got - want)))
+    if dt == 2:
+        assert err <= TOL128, f"{what}: max abs err {err:.3e}"
+    else:
+        fid = abs(np.vdot(want, got)) ** 2
+        assert fid >= 1 - 1e-6 and err <= 2e-5, f"{what}: fidelity {fid!r} err {err:.3e}"
+
+
+def _knobs(cap):
+    if cap is None:
+        return {}
+    return {"gate_grid_cap": cap, "tile_grid_cap": cap, "round_grid_cap": cap, "aux_grid_cap": cap}
+
+
+CIRCS = {
+    "rqc16": lambda: W.rqc_chain(16, 8, 21),
+    "qft17": lambda: W.qft(17, 70001),
+    "grover14": lambda: W.grover(14, 9999),
+    "bench16": lambda: W.gate_microbench(16, far=7),
+    "u3cnot15": lambda: W.random_u3_cnot(15, 120, seed=4),
+}
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+@pytest.mark.parametrize("name", list(CIRCS))
+@pytest.mark.parametrize("mode,tq", [(1, 0), (0, 0), (0, 9)])
+def test_circuit_block_loops(qs, dt, name, mode, tq):
+    c = CIRCS[name]()
+    n = c.n
+    ops, mats = c.arrays()
+    psi0 = W.random_state(n, 31) if name in ("rqc16", "bench16") else None
+    want = oracle.run(n, ops, mats, psi0, c.init_basis)
+    outs = []
+    for cap in CAPS:
+        with qs.tunables(**_knobs(cap)):
+            with qs.State.create(n, dt) as s:
+                if psi0 is not None:
+                    s.upload(psi0)
+                else:
+                    s.init_basis(c.init_basis)
+                s.run(ops, mats, mode=mode, tile_qubits=tq)
+                got = s.download()
+        _check(got, want, dt, f"{name} mode={mode} tq={tq} cap={cap}")
+        outs.append(got)
+    for cap, o in zip(CAPS[1:], outs[1:]):
+        assert o.tobytes() == outs[0].tobytes(), f"{name}: cap {cap} differs bitwise from cap {CAPS[0]}"
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_restore_pass_block_loop(qs, dt):
+    """The QFT with SWAP relabeling forced ends with restore passes; with a
+    grid of 1-5 workgroups they loop over every tile pair."""
+    n = 16
+    c = W.qft(n, 4242)
+    ops, mats = c.arrays()
+    assert len(qs.qs_plan_restore(n, dt, ops, mats)) >= 1
+    want = oracle.run_circuit(c)
+    outs = []
+    for cap in CAPS:
+        with qs.tunables(**_knobs(cap)):
+            with qs.State.create(n, dt) as s:
+                s.init_basis(c.init_basis)
+                s.run(ops, mats, mode=0)
+                got = s.download()
+        _check(got, want, dt, f"qft16 remap cap={cap}")
+        outs.append(got)
+    assert all(o.tobytes() == outs[0].tobytes() for o in outs[1:])
+
+
+def _mix():
+    # n 17/18 are pass-major (one block per tile per round); smaller ones take
+    # the whole-in-LDS and persistent classes
+    return [W.rqc_chain(18, 6, 5), W.qft(17, 12345), W.grover(17, 777), W.rqc_chain(17, 9, 8),
+            W.qft(11, 99), W.rqc_chain(14, 5, 3), W.grover(12, 1000)]
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_batch_round_block_loop(qs, dt):
+    circs = _mix()
+    wants = [oracle.run_circuit(c) for c in circs]
+    outs = []
+    for cap in CAPS:
+        with qs.tunables(**_knobs(cap)):
+            b = qs.qs_batch_submit(circs, dtype=dt, mode=0)
+            try:
+                qs.qs_batch_wait(b)
+                got = [qs.qs_batch_download(b, i, dt) for i in range(len(circs))]
+            finally:
+                qs.qs_batch_release(b)
+        for c, g, w in zip(circs, got, wants):
+            _check(g, w, dt, f"batch {c.name} cap={cap}")
+        outs.append(got)
+    for got in outs[1:]:
+        for c, a, b in zip(circs, got, outs[0]):
+            assert a.tobytes() == b.tobytes(), c.name
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_serving_round_block_loop(qs, dt):
+    import time
+
+    circs = _mix()
+    wants = [oracle.run_circuit(c) for c in circs]
+    outs = []
+    for cap in CAPS:
+        with qs.tunables(**_knobs(cap)):
+            srv = qs.qs_server_create(dtype=dt, hbm_budget=1 << 30)
+            try:
+                ids = [qs.qs_server_submit(srv, c) for c in circs]
+                done = {}
+                t_end = time.time() + 60
+                while len(done) < len(ids):
+                    for r in qs.qs_server_poll(srv):
+                        done[r["id"]] = r
+                    assert time.time() < t_end, "serving loop did not finish"
+                    time.sleep(0.0005)
+                assert all(done[i]["status"] == 0 for i in ids)
+                got = [qs.qs_server_download(srv, i, dt) for i in ids]
+            finally:
+                qs.qs_server_destroy(srv)
+        for c, g, w in zip(circs, got, wants):
+            _check(g, w, dt, f"serve {c.name} cap={cap}")
+        outs.append(got)
+    for got in outs[1:]:
+        for c, a, b in zip(circs, got, outs[0]):
+            assert a.tobytes() == b.tobytes(), c.name
