@@ -62,6 +62,8 @@ def _args():
                    help="serve: workgroup cap of the large circuit's passes (0 = library default), which "
                         "leaves compute units to the request stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--no-side", action="store_true",
+                   help="sweep: skip the compact batch and serving legs that follow the timed sweep")
     p.add_argument("--cpu-n", type=int, default=0, help="qubits of the oracle sample (0 = workload default)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run 3 torch copies of 4 GiB (reference for HBM byte counters) and exit")
@@ -112,6 +114,68 @@ def _roofline(kinds, traffic=None):
 
 
 # ------------------------------------------------------------------ CPU legs
+
+def host_cpu() -> dict:
+    """Model, sockets and cores of the host (lscpu), and the CPUs this process may use."""
+    import subprocess
+
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except (OSError, subprocess.SubprocessError):
+        txt = ""
+    keys = {"Model name": "model", "Socket(s)": "sockets", "Core(s) per socket": "cores_per_socket",
+            "Thread(s) per core": "threads_per_core", "CPU(s)": "cpus", "NUMA node(s)": "numa_nodes"}
+    for line in txt.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in keys and keys[k.strip()] not in info:
+            info[keys[k.strip()]] = v.strip()
+    try:
+        info["physical_cores"] = int(info["sockets"]) * int(info["cores_per_socket"])
+    except (KeyError, ValueError):
+        pass
+    info["usable_cpus"] = len(os.sched_getaffinity(0))
+    return info
+
+
+def cpu_baseline_gates(n_cpu: int = 30, reps_all: int = 5, reps_one: int = 3) -> dict:
+    """The FP64 oracle on a bounded sample of the gate sweep at the GPU's size:
+    six of its gates (U3 on t = 0, 15, 29; Haar 4x4 on (0,1), (14,15), (7,22))
+    on a 2^30 complex128 state, timed per pass with all the threads the host
+    gives this process and with one thread (U3 on t = 15 only); min and median
+    of the repeated passes (the paper reports the minimum of 10)."""
+    import oracle
+    import workloads as W
+
+    circ = W.gate_microbench(n_cpu)
+    pick = [g for g in circ.gates if not g[2] and (g[0] in ((0,), (15,), (29,), (0, 1), (14, 15), (7, 22)))]
+    psi = np.full(1 << n_cpu, 2.0 ** (-n_cpu / 2), dtype=np.complex128)  # timing does not depend on the values
+    threads_all = oracle.num_threads()
+
+    def passes(gates, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            for tg, u, cm, cv in gates:
+                oracle.apply_op(n_cpu, psi, tg, u, cm, cv)
+            ts.append(time.perf_counter() - t0)
+        upd = len(gates) * float(1 << n_cpu)
+        return {"threads": oracle.num_threads(), "reps": reps, "min_s": min(ts), "median_s": float(np.median(ts)),
+                "amp_updates_per_s_best": upd / min(ts), "amp_updates_per_s_median": upd / float(np.median(ts))}
+
+    try:
+        allc = passes(pick, reps_all)
+        oracle.set_threads(1)
+        one = passes([g for g in pick if g[0] == (15,)], reps_one)
+    finally:
+        oracle.set_threads(threads_all)
+    del psi
+    return {"value": allc["amp_updates_per_s_best"], "unit": "amp-updates/s", "cores": allc["threads"],
+            "kind": "oracle", "host": host_cpu(), "all_threads": allc, "one_thread": one,
+            "sample": f"{len(pick)} gates of the sweep (U3 on t=0,15,29; Haar 4x4 on (0,1),(14,15),(7,22)) on the "
+                      f"same n={n_cpu} complex128 size, {reps_all} passes with {allc['threads']} threads (value = "
+                      f"best pass) and U3 on t=15 x{reps_one} with 1 thread"}
+
 
 def cpu_baseline_sweep(n_cpu: int) -> dict:
     """The FP64 oracle on the same gate sweep at n_cpu qubits (bounded sample)."""
@@ -219,6 +283,31 @@ def diag_sweep(qs, s, n, S, reps=3, seed=13):
                     "128-byte line (bit 3, complex128) read whole lines"}
 
 
+CEILING_SCHEDULES = ((1, 8), (2, 11), (2, 14), (4, 11))
+
+
+def ceiling_probe(qs, s, reps=3):
+    """In-place read-modify-write ceiling on the same buffer: every 16-byte
+    word read and written back once by the library's probe kernel, in the
+    per-gate kernel's schedule family (slots per lane, slot spread); the best
+    schedule's GB/s (2 x buffer bytes / launch time)."""
+    qs.qs_trace_enable(s.h, True)
+    for slots, sl in CEILING_SCHEDULES:
+        for _ in range(reps):
+            qs.qs_probe_inplace(s.h, slots, sl)
+    recs = qs.qs_trace_read(s.h, 1 << 10)
+    qs.qs_trace_enable(s.h, False)
+    gbs = np.array([float(b) / float(m) / 1e6 for b, m in zip(recs["bytes"], recs["ms"])]).reshape(-1, reps)
+    best = gbs.max(axis=1)
+    i = int(np.argmax(best))
+    return {"gbs": float(best[i]), "schedule": {"slots": CEILING_SCHEDULES[i][0],
+                                                "spread_log2": CEILING_SCHEDULES[i][1]},
+            "per_schedule_gbs": {f"{a}x2^{b}": round(float(g)) for (a, b), g in zip(CEILING_SCHEDULES, best)},
+            "bytes_per_launch": int(recs["bytes"][0]),
+            "note": "in-place read+write of every 16-byte word of the 16 GiB state (qs_probe_inplace), best of "
+                    f"{reps} per schedule"}
+
+
 def per_target_table(gates, recs, steps):
     """GB/s per target index (median over the timed steps) for each gate of
     the sweep: 1q by target; 2q by first target, adjacent (t, t+1) and far
@@ -279,9 +368,12 @@ def run_sweep(a, qs, torch, W):
     qs.qs_trace_enable(s.h, False)
     norm = s.norm()
     diag = diag_sweep(qs, s, n, S) if a.mode == "pergate" else None
+    ceiling = ceiling_probe(qs, s)
     s.close()
     kinds = _kinds(qs, recs)
     rl = _roofline(kinds)
+    rl["ceiling_gbs"] = ceiling["gbs"]
+    rl["frac_vs_ceiling"] = rl["achieved"] / ceiling["gbs"]
     per_target = per_target_table(gates, recs, a.steps) if a.mode == "pergate" else None
     if a.mode == "pergate":
         rl["traffic"] = measured_traffic(rl["kernel"], f"gate_sweep_n{n}_{a.dtype}")
@@ -300,11 +392,85 @@ def run_sweep(a, qs, torch, W):
         "event_coverage": sum(d["ms"] for d in kinds.values()) / (elapsed * 1e3),
         "norm_minus_1": norm - 1.0,
         "per_target_gbs": per_target,
+        "inplace_ceiling": ceiling,
         "diag_sweep": diag,
     })
+    del psi
+    torch.cuda.empty_cache()
+    if a.mode == "pergate" and not a.no_side:
+        out["batch"] = compact_batch(a, qs, W)
+        out["serve"] = compact_serve(a, qs, W)
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline_sweep(a.cpu_n or 28)
+        out["cpu_baseline"] = cpu_baseline_gates(a.cpu_n or n)
     return out
+
+
+def compact_batch(a, qs, W, count=1024, steps=3, warm=1):
+    """Batched circuits (the 4096-circuit mix's recipe, first 1024 circuits of
+    seed 7): the fused complex64 batch against the plain per-gate complex128
+    path on 8 streams, both with the same warm-up and timed runs (medians),
+    with a closed-form and oracle check of sampled results."""
+    import oracle
+
+    circs = W.circuit_mix(count, 7)
+    arrs = [(c.n, *c.arrays(), c.init_basis) for c in circs]
+
+    def leg(dt, mode, streams):
+        for _ in range(warm):
+            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams)
+            qs.qs_batch_wait(b)
+            qs.qs_batch_release(b)
+        e2e, dev, keep = [], [], None
+        for i in range(steps):
+            t0 = time.perf_counter()
+            b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode, streams=streams)
+            qs.qs_batch_wait(b)
+            e2e.append(time.perf_counter() - t0)
+            dev.append(qs.qs_batch_get_stats(b)["device_ms"])
+            if i == steps - 1:
+                keep = b
+            else:
+                qs.qs_batch_release(b)
+        return {"circuits_per_s": count / float(np.median(e2e)), "end_to_end_ms": 1e3 * float(np.median(e2e)),
+                "device_ms": float(np.median(dev)), "runs": steps, "warmup": warm}, keep
+
+    fused, b64 = leg(qs.QS_C64, 0, 0)
+    _log(f"batch (compact) c64 fused: {fused['circuits_per_s']:.0f} circuits/s")
+    rng = np.random.default_rng(3)
+    order = rng.permutation(count)
+    closed = [i for i in order if circs[i].n <= 16 and _closed_form(circs[i]) is not None][:16]
+    chains = [i for i in order if circs[i].n <= 14 and circs[i].name.startswith("rqc")][:4]
+    fmin, emax = 1.0, 0.0
+    for i in closed + chains:
+        got = qs.qs_batch_download(b64, int(i), qs.QS_C64).astype(np.complex128)
+        want = _closed_form(circs[i]) if i in closed else oracle.run_circuit(circs[i])
+        fmin = min(fmin, abs(np.vdot(want, got)) ** 2)
+        emax = max(emax, float(np.max(np.abs(got - want))))
+    qs.qs_batch_release(b64)
+    pergate, b = leg(qs.QS_C128, 1, 8)
+    qs.qs_batch_release(b)
+    _log(f"batch (compact) c128 per-gate 8 streams: {pergate['circuits_per_s']:.0f} circuits/s")
+    return {"circuits": count, "c64_fused": fused, "c128_pergate_8streams": pergate,
+            "ratio": fused["circuits_per_s"] / pergate["circuits_per_s"],
+            "check": {"closed_form_circuits": len(closed), "oracle_circuits": len(chains),
+                      "min_fidelity": fmin, "max_abs_err": emax},
+            "note": "first 1024 circuits of the 4096-circuit mix (seed 7); --workload batch runs all 4096"}
+
+
+def compact_serve(a, qs, W, count=120):
+    """Serving: Poisson stream of requests (n log-uniform in [8, 28], seed 8),
+    complex64, at 0.7x the saturated rate measured on the first 60 requests
+    submitted at once; nothing else on the GPU (--workload serve adds the
+    34-qubit circuit beside the stream)."""
+    circs = W.circuit_mix(count, 8, n_lo=8, n_hi=28)
+    dt = qs.QS_C64
+    sat = _serve_stream(qs, circs[:60], np.zeros(60), dt)
+    qps = 0.7 * sat["circuits_per_s"]
+    main = _serve_stream(qs, circs, W.poisson_arrivals(count, qps, 8), dt)
+    _log(f"serve (compact) at {qps:.1f} qps: p50 {main['p50_ms']:.1f} ms p99 {main['p99_ms']:.1f} ms")
+    return {"requests": count, "qps": qps, "circuits_per_s": main["circuits_per_s"], "p50_ms": main["p50_ms"],
+            "p99_ms": main["p99_ms"], "failed": main["failed"], "saturated_circuits_per_s": sat["circuits_per_s"],
+            "note": "no large circuit beside the stream here; --workload serve runs it beside n=34"}
 
 
 def _fidelity(torch, ref, x):

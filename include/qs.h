@@ -249,6 +249,7 @@ qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out);
 /* Squared norm sum |psi_i|^2 in FP64 (the m = 0 case).  Blocking. */
 qs_status qs_norm(qs_state s, double* out);
 
+
 /* Expectation value <psi|P|psi> of the Pauli string P = i^w X^x Z^z with
  * w = popcount(x_mask & z_mask): X on the qubits of x_mask, Z on those of
  * z_mask, Y = iXZ on qubits in both.  Summed in FP64 in a fixed order as
@@ -461,7 +462,8 @@ typedef struct {
 
 enum {
     QS_K_INIT = 0, QS_K_1Q_HI = 1, QS_K_1Q_LO = 2, QS_K_2Q = 3, QS_K_KQ = 4,
-    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7, QS_K_DIAG = 8, QS_K_PERM = 9
+    QS_K_TILE = 5, QS_K_MFMA = 6, QS_K_REDUCE = 7, QS_K_DIAG = 8, QS_K_PERM = 9,
+    QS_K_PROBE = 10, QS_K_SAMPLE = 11
 };
 
 /* Start (on != 0) or stop recording HIP events around every launch on the
@@ -470,6 +472,18 @@ qs_status qs_trace_enable(qs_state s, int on);
 
 /* Wait for traced work and copy up to `max` records; *count = records copied. */
 qs_status qs_trace_read(qs_state s, qs_trace_rec* out, int max, int* count);
+
+/* Measurement helper, not a step of the method: the memory ceiling that every
+ * gate pass is bounded by.  Reads every 16-byte word of the state's amplitude
+ * buffer and writes it back in place, unchanged (bitwise, whatever the
+ * buffer holds), enqueued on the state's stream like a gate (a traced launch
+ * of class QS_K_PROBE with bytes = 2 x the buffer).  The schedule is the
+ * per-gate kernel's: a workgroup of 256 lanes per chunk of 256 x `slots`
+ * words, a lane's slots 2^spread_log2 words apart (slots 1, 2, 4 or 8;
+ * spread_log2 8..30), non-temporal loads and stores; the per-gate kernel's
+ * occupancy and chunk-order knobs (gate_lds_pad, gate_xcd_swizzle) apply.
+ * QS_ERR_ARG for other values. */
+qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
 
 /* ------------------------------------------------------------------ launch knobs */
 
@@ -491,6 +505,13 @@ qs_status qs_trace_read(qs_state s, qs_trace_rec* out, int max, int* count);
  *                                         table)
  *   diag_spread_log2  [QS_DIAG_SLOG]      diagonal kernel slot distance (11)
  *   perm_run_log2     [QS_PERM_RUN]       restore pass run length (0 = built-in)
+ *   gate_xcd_swizzle  [QS_GATE_XCD]       per-gate kernel chunk order: 0 = workgroup order,
+ *                                         1 = each of the 8 XCDs walks a contiguous eighth
+ *   gate_lds_pad      [QS_GATE_LDS_PAD]   per-gate kernel: unused LDS bytes per workgroup
+ *                                         (0..65536), which caps workgroups per CU
+ *   gate_low_in_regs  [QS_GATE_LOW_HIGH]  per-gate kernel: targets below bit 6 held in a lane's
+ *                                         registers instead of exchanged by shuffles (0 none,
+ *                                         1 those at or above the 128-byte line, 2 all)
  * qs_tunable_set stores `value` (value < 0: back to the default / environment
  * value); QS_ERR_ARG for an unknown name or a value outside the knob's range.
  * Knobs are process-wide and may be changed from any thread; a launch being

@@ -58,6 +58,7 @@ def lib():
             L.orc_norm2.argtypes = [ctypes.c_int, dp]
             L.orc_norm2.restype = ctypes.c_double
             L.orc_num_threads.restype = ctypes.c_int
+            L.orc_set_threads.argtypes = [ctypes.c_int]
             L.orc_expect_pauli.argtypes = [ctypes.c_int, dp, ctypes.c_uint64, ctypes.c_uint64, dp]
             L.orc_sample.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int64, ctypes.c_void_p]
             assert L.orc_op_size() == 64
@@ -72,6 +73,11 @@ def _dp(a: np.ndarray):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads of the OpenMP loops from now on (the results do not depend on it)."""
+    lib().orc_set_threads(int(t))
 
 
 def basis(n: int, x: int = 0) -> np.ndarray:

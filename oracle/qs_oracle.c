@@ -169,6 +169,18 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads for the parallel loops that follow (timing only: the loops split
+ * disjoint groups, so the result does not depend on it). */
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* Expectation value of a Pauli string.  P = i^w X^x Z^z with w = |x & z|
  * (X on the bits of x, Z on the bits of z, Y = iXZ on bits in both), so
  * P|k> = i^w (-1)^{|k & z|} |k ^ x> and

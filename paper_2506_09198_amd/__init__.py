@@ -23,7 +23,8 @@ QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_DEVICE, QS_ERR_BUSY, QS_ERR_UNSUPPORTED, Q
 QS_C64, QS_C128 = 1, 2
 QS_MAX_QUBITS = 34
 QS_MAX_FUSED = 6
-KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce", 8: "diag", 9: "perm"}
+KIND_NAMES = {0: "init", 1: "1q_hi", 2: "1q_lo", 3: "2q", 4: "kq", 5: "tile", 6: "mfma", 7: "reduce", 8: "diag", 9: "perm",
+              10: "probe", 11: "sample"}
 
 TRACE_DTYPE = np.dtype([("kind", "<i4"), ("n", "<i4"), ("t0", "<i4"), ("t1", "<i4"), ("nctrl", "<i4"),
                         ("dtype", "<i4"), ("bytes", "<u8"), ("updates", "<u8"), ("ms", "<f4"),
@@ -148,6 +149,7 @@ def _load():
         "qs_server_destroy": ([vp], i32),
         "qs_trace_enable": ([vp, i32], i32),
         "qs_trace_read": ([vp, vp, i32, ctypes.POINTER(i32)], i32),
+        "qs_probe_inplace": ([vp, i32, i32], i32),
         "qs_tunable_set": ([ctypes.c_char_p, ctypes.c_int64], i32),
         "qs_tunable_get": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], i32),
     }
@@ -590,6 +592,12 @@ def qs_trace_read(s: int, max_records: int = 1 << 16) -> np.ndarray:
     c = ctypes.c_int()
     _check(lib.qs_trace_read(ctypes.c_void_p(s), ctypes.c_void_p(out.ctypes.data), max_records, ctypes.byref(c)))
     return out[: c.value]
+
+
+def qs_probe_inplace(s: int, slots: int = 4, spread_log2: int = 11):
+    """Enqueue the in-place read-modify-write ceiling probe over the state's
+    buffer (leaves it unchanged; timed through the trace as kind "probe")."""
+    _check(lib.qs_probe_inplace(ctypes.c_void_p(s), int(slots), int(spread_log2)))
 
 
 # ------------------------------------------------------------------ convenience

@@ -86,6 +86,7 @@ struct GateArgs {
     uint32_t cm_lo, cv_lo;
     uint32_t lowmask;    // lane bits of the low targets
     int32_t slog;        // log2 of the slot spread S
+    int32_t xcd;         // chunk order: 0 = block order, 1 = each XCD a contiguous eighth
     uint64_t roff[4];    // register r -> index offset (high-target bits of r)
     int32_t srcl[4];     // member m -> lane bits of its low targets
     int32_t hreg[4];     // member m -> register holding it
@@ -118,7 +119,11 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t S = 1ull << ga.slog;
     const uint64_t spb = S >> 8;
-    for (uint64_t b = blockIdx.x; b < ga.nblocks; b += gridDim.x) {
+    for (uint64_t bb = blockIdx.x; bb < ga.nblocks; bb += gridDim.x) {
+    // Workgroups are dispatched to the 8 XCDs round-robin; with xcd set the
+    // chunk of workgroup bb is (bb mod 8) * nblocks/8 + bb/8 (nblocks is a
+    // multiple of 8 then), a bijection on the chunks.
+    const uint64_t b = ga.xcd ? (bb & 7) * (ga.nblocks >> 3) + (bb >> 3) : bb;
     const uint64_t base = (b / spb) * (S * PPL) + (b % spb) * 256 + threadIdx.x;
 
     double2 x[PPL][NR];
@@ -182,37 +187,30 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
     }
 }
 
-static int env_nt()
-{
-    static int v = env_int("QS_NT", 1);
-    return v;
-}
-
 template <typename R, int K, int NH, int PPL>
 static void launch_gate_p(void* psi, const GateArgs& ga, bool nt, hipStream_t st)
 {
     using V = typename CT<R>::V;
-    // One block per counter chunk; beyond 2^22 blocks (2^32 threads would
-    // overflow the dispatch size) the blocks loop over the remaining chunks.
-    const unsigned g = (unsigned)(ga.nblocks < (1ull << 22) ? ga.nblocks : (1ull << 22));
+    // One block per counter chunk up to the cap (at most 2^22: 2^32 threads
+    // would overflow the dispatch size); beyond it the blocks loop over the
+    // remaining chunks.
+    const uint64_t cap = (uint64_t)tun(T_GATE_GRID_CAP);
+    const unsigned g = (unsigned)(ga.nblocks < cap ? ga.nblocks : cap);
+    const size_t pad = (size_t)tun(T_GATE_LDS_PAD); // unused LDS: fewer workgroups per CU
+    const void* fn = nt ? (const void*)k_gate<R, K, NH, PPL, true> : (const void*)k_gate<R, K, NH, PPL, false>;
+    if (lds_optin(fn, pad) != hipSuccess) return;
     if (nt)
-        hipLaunchKernelGGL((k_gate<R, K, NH, PPL, true>), dim3(g), dim3(256), 0, st, (V*)psi, ga);
+        hipLaunchKernelGGL((k_gate<R, K, NH, PPL, true>), dim3(g), dim3(256), pad, st, (V*)psi, ga);
     else
-        hipLaunchKernelGGL((k_gate<R, K, NH, PPL, false>), dim3(g), dim3(256), 0, st, (V*)psi, ga);
+        hipLaunchKernelGGL((k_gate<R, K, NH, PPL, false>), dim3(g), dim3(256), pad, st, (V*)psi, ga);
 }
 
-static int env_slog()
-{
-    static int v = env_int("QS_SLOG", 11);
-    return v;
-}
-
-// Slots per lane by the number of high targets (QS_PPL_H<NH> overrides for
-// tuning).
+// Slots per lane by the number of high targets (the slots_* knobs override
+// the built-in table).
 template <typename R, int K, int NH>
 static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
 {
-    static int ppl_env = env_int(NH == 0 ? "QS_PPL_H0" : (NH == 1 ? "QS_PPL_H1" : "QS_PPL_H2"), 0);
+    const int ppl_env = (int)tun(NH == 0 ? T_PPL_H0 : (NH == 1 ? T_PPL_H1 : T_PPL_H2));
     // Measured on MI355X (n=30 c128, every target): 8 slots without high
     // targets (2-3 % over 4); one high target (1q, or 2q with the other
     // target low): 1 slot while its partner is less than 16 MiB away
@@ -226,9 +224,10 @@ static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
     if (ppl_env > 0) ppl = ppl_env;
     auto go = [&](auto pplc) {
         constexpr int P = decltype(pplc)::value;
-        const int sl = env_slog();
+        const int sl = (int)tun(T_SLOG);
         ga.slog = (ga.C >= ((1ull << sl) * P)) ? sl : 8;
         ga.nblocks = (ga.C + 256 * P - 1) / (256 * P);
+        ga.xcd = (tun(T_GATE_XCD) && ga.nblocks % 8 == 0) ? 1 : 0;
         launch_gate_p<R, K, NH, P>(psi, ga, nt, st);
     };
     if (ppl == 1) {
@@ -259,11 +258,17 @@ static hipError_t apply_gate_t(void* psi, int n, int K, const int* t, const doub
     for (int i = 0; i < 2 * D * D; ++i) ga.U[i] = U[i];
     const uint64_t linemask = (1ull << LINE_BITS) - 1;
     const uint64_t cm_ins = cm & ~linemask;
-    // lane bits: the lowest 6 positions not taken by inserted controls
+    // lane bits: the lowest 6 positions not taken by inserted controls (or,
+    // with the low-in-registers knob, by targets held in registers)
+    const int lowhigh = (int)tun(T_GATE_LOW_HIGH);
+    uint64_t reg_low = 0;
+    if (lowhigh)
+        for (int j = 0; j < K; ++j)
+            if (t[j] < 6 && (lowhigh == 2 || t[j] >= LINE_BITS)) reg_low |= 1ull << t[j];
     int lanepos[6];
     int nl = 0;
     for (int q = 0; q < 64 && nl < 6; ++q)
-        if (!((cm_ins >> q) & 1)) lanepos[nl++] = q;
+        if (!(((cm_ins | reg_low) >> q) & 1)) lanepos[nl++] = q;
     uint64_t himask = 0;
     int nh = 0;
     uint32_t lowmask = 0;
@@ -300,16 +305,25 @@ static hipError_t apply_gate_t(void* psi, int n, int K, const int* t, const doub
         ga.srcl[m] = sl;
         ga.hreg[m] = hr;
     }
-    // controls below LINE_BITS are lane bits l == q (no insertion below them)
-    ga.cm_lo = (uint32_t)(cm & linemask);
-    ga.cv_lo = (uint32_t)(cv & linemask);
+    // Controls below LINE_BITS are tested per lane: control position q sits at
+    // the lane bit l with lanepos[l] == q (q < 4 is never inserted, and at
+    // most two targets below it are, so it is among the six lane positions).
+    ga.cm_lo = ga.cv_lo = 0;
+    for (int l = 0; l < 6; ++l) {
+        const int q = lanepos[l];
+        if (q < LINE_BITS && ((cm >> q) & 1)) {
+            ga.cm_lo |= 1u << l;
+            if ((cv >> q) & 1) ga.cv_lo |= 1u << l;
+        }
+    }
     ga.cv_hi = cv & ~linemask;
     ga.ip = make_insert_plan(himask | cm_ins);
     const int nins = nh + __builtin_popcountll(cm_ins);
     ga.C = 1ull << (n - nins);
     // Non-temporal stores only when each store instruction writes whole lines:
-    // no lane skips its store (no per-amplitude controls) and full waves.
-    const bool nt = env_nt() && ga.cm_lo == 0 && ga.C >= 64;
+    // no lane skips its store (no per-amplitude controls), no register target
+    // inside a line, and full waves.
+    const bool nt = tun(T_NT) && ga.cm_lo == 0 && (reg_low & linemask) == 0 && ga.C >= 64;
     if (K == 1) {
         if (nh == 0)
             launch_gate_k<R, 1, 0>(psi, ga, nt, st);

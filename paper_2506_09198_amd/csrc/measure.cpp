@@ -33,6 +33,18 @@ qs_status scratch(qs_state s, uint64_t need)
     return QS_OK;
 }
 
+// Trace record of a read-only pass over `amps` amplitudes of the state.
+qs_trace_rec read_rec(qs_state s, uint64_t amps)
+{
+    qs_trace_rec r;
+    std::memset(&r, 0, sizeof r);
+    r.n = s->n;
+    r.t0 = r.t1 = -1;
+    r.dtype = s->dt;
+    r.bytes = amps * amp_bytes(s->dt);
+    return r;
+}
+
 } // namespace
 
 extern "C" qs_status qs_expect_pauli(qs_state s, uint64_t x_mask, uint64_t z_mask, double* out)
@@ -46,10 +58,15 @@ extern "C" qs_status qs_expect_pauli(qs_state s, uint64_t x_mask, uint64_t z_mas
     if ((st = scratch(s, need)) != QS_OK) return st;
     double* part = s->red_part;
     double* dout = s->red_part + need - 2;
-    hipError_t e = launch_pauli_expect(s->d, s->dt, s->n, x_mask, z_mask, part, dout, s->st);
-    if (e != hipSuccess) return fail_device(s, e, "Pauli expectation launch");
+    st = traced_launch(s, read_rec(s, 1ull << s->n),
+                       [&](int* kind) {
+                           *kind = QS_K_REDUCE;
+                           return launch_pauli_expect(s->d, s->dt, s->n, x_mask, z_mask, part, dout, s->st);
+                       },
+                       "Pauli expectation launch");
+    if (st != QS_OK) return st;
     double sum[2];
-    e = hipMemcpyAsync(sum, dout, sizeof sum, hipMemcpyDeviceToHost, s->st);
+    hipError_t e = hipMemcpyAsync(sum, dout, sizeof sum, hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return fail_device(s, e, "Pauli expectation download");
     double re = sum[0], im = sum[1];
@@ -75,10 +92,15 @@ extern "C" qs_status qs_sample(qs_state s, const double* u, int64_t shots, uint6
     const uint64_t nch = reduce_scratch_doubles(s->n, 0);
     if ((st = scratch(s, nch + 1)) != QS_OK) return st;
     double* part = s->red_part;
-    hipError_t e = launch_probabilities(s->d, s->dt, s->n, nullptr, 0, part, part + nch, s->st);
-    if (e != hipSuccess) return fail_device(s, e, "sampling chunk sums");
+    st = traced_launch(s, read_rec(s, 1ull << s->n),
+                       [&](int* kind) {
+                           *kind = QS_K_REDUCE;
+                           return launch_probabilities(s->d, s->dt, s->n, nullptr, 0, part, part + nch, s->st);
+                       },
+                       "sampling chunk sums");
+    if (st != QS_OK) return st;
     std::vector<double> ch(nch);
-    e = hipMemcpyAsync(ch.data(), part, nch * sizeof(double), hipMemcpyDeviceToHost, s->st);
+    hipError_t e = hipMemcpyAsync(ch.data(), part, nch * sizeof(double), hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return fail_device(s, e, "sampling chunk download");
     // compensated inclusive prefix over the chunks
@@ -115,7 +137,22 @@ extern "C" qs_status qs_sample(qs_state s, const double* u, int64_t shots, uint6
         return st;
     }
     e = hipMemcpyAsync(dreq, req.data(), rb, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = launch_sample_chunks(s->d, s->dt, s->n, dreq, shots, dout, s->st);
+    if (e == hipSuccess) {
+        // one wave per shot reads its chunk: min(4096, 2^n) amplitudes per shot
+        const uint64_t csize = s->n < 12 ? (1ull << s->n) : 4096;
+        st = traced_launch(s, read_rec(s, csize * (uint64_t)shots),
+                           [&](int* kind) {
+                               *kind = QS_K_SAMPLE;
+                               return launch_sample_chunks(s->d, s->dt, s->n, dreq, shots, dout, s->st);
+                           },
+                           "sampling launch");
+        if (st != QS_OK) {
+            (void)hipStreamSynchronize(s->st);
+            dev_free(dreq, rb);
+            dev_free(dout, ob);
+            return st;
+        }
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     dev_free(dreq, rb);

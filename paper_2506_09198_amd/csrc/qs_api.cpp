@@ -546,11 +546,8 @@ qs_status qs_apply_diag(qs_state s, const int* targets, int k, const double* dia
     return apply_diag_internal(s, p, targets[0], k > 1 ? targets[1] : -1, cm);
 }
 
-qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out)
+static qs_status check_measured(qs_state s, const int* qubits, int m)
 {
-    qs_status st = check_live(s);
-    if (st != QS_OK) return st;
-    if (!out) return set_err(QS_ERR_ARG, "null output");
     if (m < 0 || m > 24 || m > s->n) return set_err(QS_ERR_ARG, "m=%d outside [0, min(24, n)]", m);
     if (m > 0 && !qubits) return set_err(QS_ERR_ARG, "null qubit list");
     uint64_t seen = 0;
@@ -559,6 +556,15 @@ qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out)
         if ((seen >> qubits[j]) & 1) return set_err(QS_ERR_ARG, "duplicate qubit %d", qubits[j]);
         seen |= 1ull << qubits[j];
     }
+    return QS_OK;
+}
+
+qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out)
+{
+    qs_status st = check_live(s);
+    if (st != QS_OK) return st;
+    if (!out) return set_err(QS_ERR_ARG, "null output");
+    if ((st = check_measured(s, qubits, m)) != QS_OK) return st;
     const uint64_t need = reduce_scratch_doubles(s->n, m) + (1ull << m);
     if (need > s->red_cap) {
         hipError_t e = hipStreamSynchronize(s->st);
@@ -595,6 +601,27 @@ qs_status qs_sync(qs_state s)
     hipError_t e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return fail_device(s, e, "hipStreamSynchronize");
     return QS_OK;
+}
+
+qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2)
+{
+    qs_status st = check_live(s);
+    if (st != QS_OK) return st;
+    if (slots != 1 && slots != 2 && slots != 4 && slots != 8)
+        return set_err(QS_ERR_ARG, "slots=%d: expected 1, 2, 4 or 8", slots);
+    if (spread_log2 < 8 || spread_log2 > 30) return set_err(QS_ERR_ARG, "spread_log2=%d outside [8, 30]", spread_log2);
+    if (s->bytes % 16) return set_err(QS_ERR_ARG, "state of %llu bytes is not whole 16-byte words",
+                                      (unsigned long long)s->bytes);
+    qs_trace_rec rec = make_rec(s, -1, -1, 0);
+    rec.bytes = 2 * s->bytes;
+    rec.updates = 0;
+    return traced_launch(
+        s, rec,
+        [&](int* kind) {
+            *kind = QS_K_PROBE;
+            return launch_probe_inplace(s->d, s->bytes, slots, spread_log2, 0, s->st);
+        },
+        "probe launch");
 }
 
 qs_status qs_trace_enable(qs_state s, int on)

@@ -81,6 +81,10 @@ uint64_t reduce_scratch_doubles(int n, int m);
 hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m,
                                 double* part, double* dev_out, hipStream_t st);
 
+// In-place read-modify-write of `bytes` (16-byte words, each XORed with
+// `mask`): the memory ceiling probe.  slots 1/2/4/8, slog 8..30.
+hipError_t launch_probe_inplace(void* dev, uint64_t bytes, int slots, int slog, uint64_t mask, hipStream_t st);
+
 // Environment variable as an int (dflt when unset or empty).
 int env_int(const char* name, int dflt);
 
@@ -98,6 +102,10 @@ enum Tun {
     T_PPL_H2,          //   with two
     T_DIAG_SLOG,       // diagonal kernel: log2 slot distance
     T_PERM_RUN,        // restore pass: log2 run length (0 = built-in choice)
+    T_GATE_XCD,        // per-gate kernel: 1 = each XCD walks a contiguous eighth of the chunks
+    T_GATE_LDS_PAD,    // per-gate kernel and probe: extra LDS bytes per workgroup (limits occupancy)
+    T_GATE_LOW_HIGH,   // per-gate kernel: targets below bit 6 held in registers (1: at or above the
+                       //   128-byte line bit, 2: all) instead of exchanged by shuffles
     T_COUNT
 };
 int64_t tun(Tun id);

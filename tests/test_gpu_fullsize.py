@@ -8,7 +8,15 @@ or on properties that hold at any size (closed forms, echo, norm).
   (complex128 1e-12; complex64 estimated infidelity <= 1e-6), random chain
   circuit followed by its inverse returns |0..0> (echo);
 - 4096-circuit batch: sampled circuits against the oracle or closed forms;
-- serving mix beside a 34-qubit complex64 random circuit (echo + norm).
+- 32-qubit random chain circuit gate by gate in complex128 (the per-gate
+  kernels' block loops): every gate's outputs on sampled indices against the
+  oracle's per-amplitude definition; the tile-pass runs (complex128, complex64
+  with register blocks and with 5-qubit matrix-core blocks) are then compared
+  on samples with that result, which shares no tile or fusion code;
+- the deepest 20-22-qubit chain circuits of the 4096-circuit batch against the
+  full oracle;
+- serving mix beside a 34-qubit complex64 random circuit run as the bench runs
+  it (echo + norm).
 """
 import math
 import time
@@ -99,7 +107,61 @@ def test_qft_n32_closed_form_sampled(qs, dt, fuse):
         assert infid <= 1e-6, infid
 
 
-@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 5)])
+def _gather(t, idx):
+    import torch
+
+    return t[torch.from_numpy(np.asarray(idx, dtype=np.uint64).astype(np.int64)).to(t.device)].cpu().numpy()
+
+
+def test_rqc_n32_c128_pergate_sampled_and_tile_anchors(qs):
+    """Config 3A gate by gate (complex128, 64 GiB): each gate's outputs on 256
+    sampled indices against the oracle's definition, from the GPU state just
+    before that gate.  The per-gate result then anchors the tile-pass runs of
+    the same circuit on 4096 samples: complex128 within 1e-12, complex64
+    (register blocks, and 5-qubit matrix-core blocks) with an estimated
+    infidelity below 1e-6."""
+    import torch
+
+    n = 32
+    c = W.rqc_chain(n, 20, 5)
+    ops, mats = c.arrays()
+    psi = torch.zeros(1 << n, dtype=torch.complex128, device="cuda")
+    psi[0] = 1
+    torch.cuda.synchronize()
+    s = qs.State.from_torch(psi)
+    rng = np.random.default_rng(32)
+    worst = 0.0
+    for g, (tg, u, cm, cv) in enumerate(c.gates):
+        idx = rng.integers(0, 1 << n, size=256, dtype=np.uint64)
+        want = oracle.outputs_at(idx, tg, u, cm, cv, lambda j: _gather(psi, j))
+        if len(tg) == 1:
+            qs.qs_apply_1q(s.h, tg[0], u, cm, cv)
+        else:
+            qs.qs_apply_2q(s.h, tg[0], tg[1], u, cm, cv)
+        s.sync()
+        err = float(np.max(np.abs(_gather(psi, idx) - want)))
+        worst = max(worst, err)
+        assert err <= 1e-12, f"gate {g} targets {tg} ctrl {cm:#x}: {err:.3e}"
+    assert abs(s.norm() - 1.0) < 1e-11
+    s.close()
+    ys = np.random.default_rng(33).integers(0, 1 << n, size=4096, dtype=np.uint64)
+    ref = _gather(psi, ys)
+    N = float(1 << n)
+    for dt, fuse in ((2, 0), (1, 0), (1, 5)):
+        with qs.State.create(n, dt) as t:
+            t.run(ops, mats, mode=0, fuse_k=fuse)
+            got = np.array([t.download(int(v), 1)[0] for v in ys], dtype=np.complex128)
+        d = got - ref
+        if dt == 2:
+            assert float(np.max(np.abs(d))) <= 1e-12, (dt, fuse, float(np.max(np.abs(d))))
+        else:
+            infid = N * float(np.mean(np.abs(d) ** 2))  # estimate of 1 - F from samples
+            assert infid <= 1e-6, (dt, fuse, infid)
+    del psi
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5)])
 def test_rqc_n32_echo(qs, dt, fuse):
     n = 32
     c = W.rqc_chain(n, 20, 5)
@@ -142,23 +204,40 @@ def _fid_ok(got, want, dt):
     return abs(np.vdot(want, got)) ** 2 >= 1 - 1e-6
 
 
+def _deepest_chains(circs, per_n=1):
+    """Indices of the deepest chain circuits at each of n = 20, 21, 22 (the
+    pass-major class's longest runs, up to ~6600 gates)."""
+    out = []
+    for n in (20, 21, 22):
+        cand = [i for i, c in enumerate(circs) if c.n == n and c.name.startswith("rqc")]
+        cand.sort(key=lambda i: -len(circs[i]))
+        out += cand[:per_n]
+    return out
+
+
 def test_batch_4096_sampled(qs):
     circs = W.circuit_mix(4096, 7)
     arrs = [(c.n, *c.arrays(), c.init_basis) for c in circs]
     rng = np.random.default_rng(3)
     pick = [i for i in rng.permutation(len(circs)) if circs[i].n <= 14 or not circs[i].name.startswith("rqc")][:24]
+    deep = _deepest_chains(circs)
+    assert len(deep) == 3 and min(len(circs[i]) for i in deep) > 5000
+    wants = {i: _expected(circs[i]) for i in pick + deep}  # deep chains: full oracle, seconds each
     for dt, mode in ((1, 0), (2, 0), (2, 1)):
         b = qs.qs_batch_submit(arrs, dtype=dt, mode=mode)
         try:
             qs.qs_batch_wait(b)
-            for i in pick:
+            for i in pick + deep:
                 got = qs.qs_batch_download(b, int(i), dt)
-                assert _fid_ok(got, _expected(circs[i]), dt), (dt, mode, circs[i].name)
+                assert _fid_ok(got, wants[i], dt), (dt, mode, circs[i].name)
         finally:
             qs.qs_batch_release(b)
 
 
 def test_serving_beside_n34_c64(qs):
+    """The 34-qubit complex64 circuit as the serving bench runs it (register
+    blocks, no matrix-core fusion, 256-workgroup cap), forward while the
+    request stream is served, then its inverse."""
     import torch
 
     big = W.rqc_chain(34, 24, 9)
@@ -169,7 +248,7 @@ def test_serving_beside_n34_c64(qs):
     psi[0] = 1
     torch.cuda.synchronize()
     bs = qs.State.from_torch(psi, stream=side.cuda_stream)
-    bs.run(bops, bmats, mode=0, fuse_k=5)  # enqueued on its own stream; serving runs meanwhile
+    bs.run(bops, bmats, mode=0, fuse_k=0, max_blocks=256)  # own stream; serving runs meanwhile
     srv = qs.qs_server_create(dtype=1, hbm_budget=24 << 30)
     try:
         rng = np.random.default_rng(8)
@@ -196,7 +275,7 @@ def test_serving_beside_n34_c64(qs):
             assert _fid_ok(qs.qs_server_download(srv, rid, 1), _expected(c), 1), c.name
     finally:
         qs.qs_server_destroy(srv)
-    bs.run(iops, imats, mode=0, fuse_k=5)
+    bs.run(iops, imats, mode=0, fuse_k=0, max_blocks=256)
     bs.sync()
     a0 = complex(psi[0].item())
     nrm = bs.norm()
