@@ -249,6 +249,23 @@ qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out);
 /* Squared norm sum |psi_i|^2 in FP64 (the m = 0 case).  Blocking. */
 qs_status qs_norm(qs_state s, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * marginal probabilities of qs_probabilities -- same kernels, same summation
+ * order, so bitwise the same numbers -- without any allocation.  dev_out:
+ * DEVICE memory for 2^m doubles, caller-owned.  The work is enqueued on the
+ * state's stream and the call returns at once (nothing is copied to the host
+ * and nothing waits); read dev_out after that stream.  The partial sums live
+ * in one fixed scratch array per GPU (2^22 doubles = 32 MiB, held by the
+ * library until the process ends), so the call calls no hipMalloc/hipFree or
+ * allocating routine: QS_ERR_ARG when the reduction would need more than that
+ * (2^(n-12) partial sums for m <= n - 12, else 2^m: every n <= 34 with
+ * m <= 22 fits), or for a NULL dev_out or the qubit list errors of
+ * qs_probabilities.  Every call on one GPU shares that array, and each call
+ * overwrites all of it that it reads, so calls need no clearing between them;
+ * calls that overlap on one GPU (different streams, or different threads)
+ * race and must be ordered by the caller. */
+qs_status qs_probabilities_noalloc(qs_state s, const int* qubits, int m, double* dev_out);
 
 /* Expectation value <psi|P|psi> of the Pauli string P = i^w X^x Z^z with
  * w = popcount(x_mask & z_mask): X on the qubits of x_mask, Z on those of

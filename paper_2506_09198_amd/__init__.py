@@ -129,6 +129,7 @@ def _load():
         "qs_sample": ([vp, dp, ctypes.c_int64, ctypes.c_void_p], i32),
         "qs_probabilities": ([vp, ctypes.POINTER(i32), i32, dp], i32),
         "qs_norm": ([vp, dp], i32),
+        "qs_probabilities_noalloc": ([vp, ctypes.POINTER(i32), i32, vp], i32),
         "qs_sync": ([vp], i32),
         "qs_batch_submit": ([ctypes.POINTER(_Circuit), i32, ctypes.POINTER(_BatchOpts), ctypes.POINTER(vp)], i32),
         "qs_batch_wait": ([vp, i32], i32),
@@ -431,6 +432,14 @@ def qs_norm(s: int) -> float:
     v = ctypes.c_double()
     _check(lib.qs_norm(ctypes.c_void_p(s), ctypes.byref(v)))
     return v.value
+
+
+def qs_probabilities_noalloc(s: int, qubits, dev_out: int):
+    """Enqueue the marginal probabilities into device memory at address
+    ``dev_out`` (2^m doubles) without any allocation; returns at once."""
+    q = np.ascontiguousarray(list(qubits), dtype=np.int32)
+    _check(lib.qs_probabilities_noalloc(ctypes.c_void_p(s), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(q),
+                                        ctypes.c_void_p(int(dev_out))))
 
 
 def qs_sync(s: int):

@@ -342,6 +342,16 @@ int qs_device_count(void)
     return c;
 }
 
+// Look up the no-allocation scratch of the state's device once, when a state
+// is first created there, so that qs_probabilities_noalloc finds it resolved.
+// A failure here is not the new state's: the entry point retries and reports.
+static void resolve_noalloc_scratch(int dev)
+{
+    double* p = nullptr;
+    uint64_t c = 0;
+    if (noalloc_scratch(dev, &p, &c) != hipSuccess) (void)hipGetLastError();
+}
+
 static qs_status new_state(int n, qs_dtype dt, qs_state* out)
 {
     if (!out) return set_err(QS_ERR_ARG, "null output pointer");
@@ -361,6 +371,7 @@ qs_status qs_create(int n, qs_dtype dt, qs_state* out)
     s->dt = dt;
     s->bytes = (1ull << n) * amp_bytes(dt);
     (void)hipGetDevice(&s->dev);
+    resolve_noalloc_scratch(s->dev);
     st = dev_alloc(&s->d, s->bytes, "state");
     if (st != QS_OK) {
         delete s;
@@ -407,6 +418,7 @@ qs_status qs_create_external(int n, qs_dtype dt, void* dev_ptr, uint64_t bytes, 
     s->st = (hipStream_t)stream;
     s->own_stream = false;
     (void)hipGetDevice(&s->dev);
+    resolve_noalloc_scratch(s->dev);
     *out = s;
     return QS_OK;
 }
@@ -593,6 +605,28 @@ qs_status qs_probabilities(qs_state s, const int* qubits, int m, double* out)
 }
 
 qs_status qs_norm(qs_state s, double* out) { return qs_probabilities(s, nullptr, 0, out); }
+
+qs_status qs_probabilities_noalloc(qs_state s, const int* qubits, int m, double* dev_out)
+{
+    qs_status st = check_live(s);
+    if (st != QS_OK) return st;
+    if (!dev_out) return set_err(QS_ERR_ARG, "null device output");
+    if ((st = check_measured(s, qubits, m)) != QS_OK) return st;
+    double* part = nullptr;
+    uint64_t cap = 0;
+    const hipError_t e0 = noalloc_scratch(s->dev, &part, &cap);
+    if (e0 != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(QS_ERR_DEVICE, "no-allocation scratch lookup: %s", hipGetErrorString(e0));
+    }
+    const uint64_t need = reduce_scratch_doubles(s->n, m);
+    if (need > cap)
+        return set_err(QS_ERR_ARG, "n=%d, m=%d needs %llu doubles of scratch; the fixed scratch holds %llu", s->n, m,
+                       (unsigned long long)need, (unsigned long long)cap);
+    const hipError_t e = launch_probabilities(s->d, s->dt, s->n, qubits, m, part, dev_out, s->st);
+    if (e != hipSuccess) return fail_device(s, e, "probabilities launch");
+    return QS_OK;
+}
 
 qs_status qs_sync(qs_state s)
 {

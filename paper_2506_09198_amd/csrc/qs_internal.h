@@ -78,6 +78,10 @@ struct SampleReq {
 hipError_t launch_sample_chunks(const void* psi, int dt, int n, const SampleReq* req, int64_t shots, uint64_t* out,
                                 hipStream_t st);
 uint64_t reduce_scratch_doubles(int n, int m);
+// The fixed per-device reduction scratch of the no-allocation entry points:
+// its address on device `dev` (which must be current; resolved once per
+// device, then cached) and its size in doubles.
+hipError_t noalloc_scratch(int dev, double** ptr, uint64_t* doubles);
 hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m,
                                 double* part, double* dev_out, hipStream_t st);
 

@@ -8,11 +8,25 @@
 //           lane a fixed strided subsequence, then a fixed LDS tree) into
 //           part[o * nch + chunk];
 //   pass 2: one block per outcome sums part[o * nch .. + nch) the same way.
+#include <mutex>
+
 #include "device_common.h"
 
 namespace qs {
 
+// Device scratch for callers that cannot allocate (qs_probabilities_noalloc):
+// the per-chunk partial sums of one reduction go here instead of into a
+// buffer the library allocates.  2^22 doubles (32 MiB) cover every state the
+// library takes (n <= 34) for m <= 22 measured qubits.  Each GPU holds its own
+// copy until the process ends; calls that overlap on one GPU share it and race.
+constexpr uint64_t kNoAllocScratchDoubles = 1ull << 22;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
 
 constexpr int kRT = 256;        // threads per reduction block
 constexpr int kChunkLog2 = 12;  // CH = 4096 rest indices per block
@@ -207,6 +221,23 @@ hipError_t launch_sample_chunks(const void* psi, int dt, int n, const SampleReq*
         hipLaunchKernelGGL(k_sample_chunk<float2>, dim3((unsigned)g), dim3(kRT), 0, st, (const float2*)psi, csize,
                            req, shots, out);
     return hipGetLastError();
+}
+
+hipError_t noalloc_scratch(int dev, double** ptr, uint64_t* doubles)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        // The array's name is a host-side handle; its address on this
+        // device comes from the runtime (the caller made `dev` current).
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = p;
+    }
+    *ptr = (double*)g_scratch_dev[dev];
+    *doubles = kNoAllocScratchDoubles;
+    return hipSuccess;
 }
 
 uint64_t reduce_scratch_doubles(int n, int m)
