@@ -283,27 +283,30 @@ def diag_sweep(qs, s, n, S, reps=3, seed=13):
                     "128-byte line (bit 3, complex128) read whole lines"}
 
 
-CEILING_SCHEDULES = ((1, 8), (2, 11), (2, 14), (4, 11))
+# (slots per lane, log2 slot spread, workgroups per CU; 0 = no cap)
+CEILING_SCHEDULES = ((1, 8, 0), (1, 8, 6), (2, 11, 0), (2, 11, 3), (2, 14, 3), (2, 14, 4), (4, 11, 2))
 
 
 def ceiling_probe(qs, s, reps=3):
     """In-place read-modify-write ceiling on the same buffer: every 16-byte
     word read and written back once by the library's probe kernel, in the
-    per-gate kernel's schedule family (slots per lane, slot spread); the best
-    schedule's GB/s (2 x buffer bytes / launch time)."""
-    qs.qs_trace_enable(s.h, True)
-    for slots, sl in CEILING_SCHEDULES:
-        for _ in range(reps):
-            qs.qs_probe_inplace(s.h, slots, sl)
-    recs = qs.qs_trace_read(s.h, 1 << 10)
-    qs.qs_trace_enable(s.h, False)
-    gbs = np.array([float(b) / float(m) / 1e6 for b, m in zip(recs["bytes"], recs["ms"])]).reshape(-1, reps)
+    per-gate kernel's schedule family (slots per lane, slot spread,
+    workgroups per CU); the best schedule's GB/s (2 x buffer bytes / launch
+    time)."""
+    recs = []
+    for slots, sl, wg in CEILING_SCHEDULES:
+        with qs.tunables(gate_wg_per_cu=wg):
+            qs.qs_trace_enable(s.h, True)
+            for _ in range(reps):
+                qs.qs_probe_inplace(s.h, slots, sl)
+            recs.append(qs.qs_trace_read(s.h, 64))
+            qs.qs_trace_enable(s.h, False)
+    gbs = np.array([[float(b) / float(m) / 1e6 for b, m in zip(r["bytes"], r["ms"])] for r in recs])
     best = gbs.max(axis=1)
     i = int(np.argmax(best))
-    return {"gbs": float(best[i]), "schedule": {"slots": CEILING_SCHEDULES[i][0],
-                                                "spread_log2": CEILING_SCHEDULES[i][1]},
-            "per_schedule_gbs": {f"{a}x2^{b}": round(float(g)) for (a, b), g in zip(CEILING_SCHEDULES, best)},
-            "bytes_per_launch": int(recs["bytes"][0]),
+    return {"gbs": float(best[i]), "schedule": dict(zip(("slots", "spread_log2", "wg_per_cu"), CEILING_SCHEDULES[i])),
+            "per_schedule_gbs": {f"{a}x2^{b}/wg{c}": round(float(g)) for (a, b, c), g in zip(CEILING_SCHEDULES, best)},
+            "bytes_per_launch": int(recs[0]["bytes"][0]),
             "note": "in-place read+write of every 16-byte word of the 16 GiB state (qs_probe_inplace), best of "
                     f"{reps} per schedule"}
 

@@ -293,16 +293,39 @@ qs_status qs_sync(qs_state s);
 
 typedef struct qs_batch_s* qs_batch;
 
-/* One circuit of a batch: n qubits, initial basis state, op table and matrix
- * pool exactly as for qs_run_circuit. */
+/* What a batch or served circuit writes to its `out` when it completes. */
+enum {
+    QS_WANT_NONE = 0,  /* nothing (results stay in the batch / server until read) */
+    QS_WANT_STATE = 1, /* the final state: 2^n amplitudes in the batch / server dtype */
+    QS_WANT_PROBS = 2, /* |psi_i|^2 for every index i: 2^n doubles (n <= 24) */
+    QS_WANT_NORM = 3   /* sum of |psi_i|^2: one double */
+};
+
+/* One circuit of a batch or serving request: n qubits, its initial state, op
+ * table and matrix pool exactly as for qs_run_circuit, and the result it
+ * delivers on completion.
+ * - Initial state: the basis state |init_basis>, or, when init_state is not
+ *   NULL, the 2^n amplitudes at init_state: DEVICE memory on the batch's or
+ *   server's GPU, in its dtype, caller-owned; it is read on the device, so
+ *   it must stay valid and unchanged until qs_batch_wait returns (and for
+ *   every qs_batch_replay) or until the served request has finished.
+ *   init_basis is ignored then.
+ * - Result: with want != QS_WANT_NONE, `out` (HOST memory, caller-owned, of
+ *   the size QS_WANT_* names) receives the result: for a batch, each time
+ *   qs_batch_wait returns QS_OK; for a served request, before qs_server_poll
+ *   reports it finished.  The per-circuit queries (qs_batch_download,
+ *   qs_batch_probabilities, qs_batch_norm, qs_server_download) stay
+ *   available either way. */
 typedef struct {
     int32_t n;
-    int32_t rsv0;
+    int32_t want;           /* QS_WANT_* */
     uint64_t init_basis;
     const qs_op* ops;
     int64_t n_ops;
     const double* mats;
     int64_t n_mats;
+    const void* init_state; /* NULL = start from |init_basis> */
+    void* out;              /* host buffer for `want` (NULL when want == QS_WANT_NONE) */
 } qs_circuit;
 
 typedef struct {
@@ -438,7 +461,10 @@ typedef struct {
 qs_status qs_server_create(const qs_server_opts* opts, qs_server* out);
 
 /* Queue a request (validated and copied; the caller's tables may be freed).
- * QS_ERR_OOM at once if its state could never fit the budget. */
+ * QS_ERR_OOM at once if its state could never fit the budget.  A request
+ * whose plan (passes, ops and fused matrices, known once it is planned at
+ * admission) is larger than the whole plan_budget finishes with status
+ * QS_ERR_ARG instead of waiting in the queue. */
 qs_status qs_server_submit(qs_server s, const qs_circuit* c, uint64_t* id);
 
 /* One scheduler tick: retire finished rounds, admit queued requests that fit,
@@ -498,7 +524,7 @@ qs_status qs_trace_read(qs_state s, qs_trace_rec* out, int max, int* count);
  * per-gate kernel's: a workgroup of 256 lanes per chunk of 256 x `slots`
  * words, a lane's slots 2^spread_log2 words apart (slots 1, 2, 4 or 8;
  * spread_log2 8..30), non-temporal loads and stores; the per-gate kernel's
- * occupancy and chunk-order knobs (gate_lds_pad, gate_xcd_swizzle) apply.
+ * occupancy and chunk-order knobs (gate_wg_per_cu, gate_xcd_swizzle) apply.
  * QS_ERR_ARG for other values. */
 qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
 
@@ -522,13 +548,17 @@ qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
  *                                         table)
  *   diag_spread_log2  [QS_DIAG_SLOG]      diagonal kernel slot distance (11)
  *   perm_run_log2     [QS_PERM_RUN]       restore pass run length (0 = built-in)
- *   gate_xcd_swizzle  [QS_GATE_XCD]       per-gate kernel chunk order: 0 = workgroup order,
- *                                         1 = each of the 8 XCDs walks a contiguous eighth
- *   gate_lds_pad      [QS_GATE_LDS_PAD]   per-gate kernel: unused LDS bytes per workgroup
- *                                         (0..65536), which caps workgroups per CU
+ *   gate_xcd_swizzle  [QS_GATE_XCD]       per-gate kernel chunk order: 0 = built-in rule,
+ *                                         1 = workgroup order, 2 = each of the 8 XCDs walks a
+ *                                         contiguous eighth of the chunks
+ *   gate_wg_per_cu    [QS_GATE_WG_PER_CU] per-gate kernel (and qs_probe_inplace): workgroups
+ *                                         per CU, capped through unused LDS (0 = built-in rule
+ *                                         for gates, no cap for the probe; 8 and more: no cap
+ *                                         in effect)
  *   gate_low_in_regs  [QS_GATE_LOW_HIGH]  per-gate kernel: targets below bit 6 held in a lane's
  *                                         registers instead of exchanged by shuffles (0 none,
- *                                         1 those at or above the 128-byte line, 2 all)
+ *                                         1 = default: those at or above the 128-byte line,
+ *                                         2 all)
  * qs_tunable_set stores `value` (value < 0: back to the default / environment
  * value); QS_ERR_ARG for an unknown name or a value outside the knob's range.
  * Knobs are process-wide and may be changed from any thread; a launch being

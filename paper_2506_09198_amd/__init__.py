@@ -39,9 +39,12 @@ class QSError(RuntimeError):
 
 
 class _Circuit(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("rsv0", ctypes.c_int32), ("init_basis", ctypes.c_uint64),
+    _fields_ = [("n", ctypes.c_int32), ("want", ctypes.c_int32), ("init_basis", ctypes.c_uint64),
                 ("ops", ctypes.c_void_p), ("n_ops", ctypes.c_int64), ("mats", ctypes.c_void_p),
-                ("n_mats", ctypes.c_int64)]
+                ("n_mats", ctypes.c_int64), ("init_state", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+QS_WANT_NONE, QS_WANT_STATE, QS_WANT_PROBS, QS_WANT_NORM = 0, 1, 2, 3
 
 
 class _BatchOpts(ctypes.Structure):
@@ -447,17 +450,28 @@ def qs_sync(s: int):
 
 
 def _circuit_array(circuits):
+    """Circuits as qs_circuit records.  Each item is a workloads.Circuit, a
+    tuple (n, ops, mats, basis), or (n, ops, mats, basis, init_state, want,
+    out): init_state a device address (int; 0 = start from |basis>), want a
+    QS_WANT_* value and out a C-contiguous numpy array that receives it (the
+    caller keeps it alive until the result is written)."""
     keep, arr = [], (_Circuit * max(1, len(circuits)))()
     for i, c in enumerate(circuits):
+        init, want, out = 0, QS_WANT_NONE, None
         if hasattr(c, "arrays"):
             n, (ops, mats), basis = c.n, c.arrays(), c.init_basis
+        elif len(c) == 7:
+            n, ops, mats, basis, init, want, out = c
         else:
             n, ops, mats, basis = c
         ops = np.ascontiguousarray(ops)
         mats = np.ascontiguousarray(mats, dtype=np.float64)
         keep.append((ops, mats))
-        arr[i] = _Circuit(n, 0, int(basis), ops.ctypes.data if len(ops) else 0, len(ops),
-                          mats.ctypes.data if mats.size else 0, mats.size)
+        if out is not None and not out.flags.c_contiguous:
+            raise ValueError("result buffer must be C-contiguous")
+        arr[i] = _Circuit(n, int(want), int(basis), ops.ctypes.data if len(ops) else 0, len(ops),
+                          mats.ctypes.data if mats.size else 0, mats.size, int(init or 0),
+                          out.ctypes.data if out is not None else 0)
     return keep, arr
 
 
@@ -540,16 +554,10 @@ def qs_server_create(dtype: int = QS_C128, hbm_budget: int = 0, rounds_ahead: in
 
 
 def qs_server_submit(srv: int, circ) -> int:
-    if hasattr(circ, "arrays"):
-        n, (ops, mats), basis = circ.n, circ.arrays(), circ.init_basis
-    else:
-        n, ops, mats, basis = circ
-    ops = np.ascontiguousarray(ops)
-    mats = np.ascontiguousarray(mats, dtype=np.float64)
-    c = _Circuit(n, 0, int(basis), ops.ctypes.data if len(ops) else 0, len(ops), mats.ctypes.data if mats.size else 0,
-                 mats.size)
+    """Queue one request (a circuit in any form _circuit_array takes)."""
+    keep, arr = _circuit_array([circ])
     rid = ctypes.c_uint64()
-    _check(lib.qs_server_submit(ctypes.c_void_p(srv), ctypes.byref(c), ctypes.byref(rid)))
+    _check(lib.qs_server_submit(ctypes.c_void_p(srv), ctypes.byref(arr[0]), ctypes.byref(rid)))
     return rid.value
 
 

@@ -66,6 +66,12 @@ struct qs_batch_s {
     hipGraphExec_t gexec = nullptr;
     double* red = nullptr; // reduction scratch for qs_batch_probabilities
     uint64_t red_cap = 0;  // doubles
+    // initial states given by the caller (circuit, device source), copied into
+    // the arena before every run; results delivered to host buffers on
+    // completion (circuit, want, out), once per run
+    std::vector<std::pair<int, const void*>> init_src;
+    std::vector<std::pair<int, std::pair<int, void*>>> wants;
+    bool delivered = false;
 };
 
 namespace {
@@ -154,13 +160,21 @@ qs_status enqueue_fused(qs_batch b, bool mark)
         (void)hipEventRecord(b->cls_done[k], s);
     };
     qs_status st = QS_OK;
-    if (S.stream_count > 0) {
-        // zero the arena and set the streamed circuits' basis amplitudes before
-        // any other stream writes a state into it
-        hipError_t e = launch_batch_init(b->dt, b->arena, b->arena_bytes, S.dcirc, S.dlist + S.stream_l0,
-                                         S.stream_count, s0);
-        b->stats.launches += 2;
-        if (e != hipSuccess) return bfail(b, e, "batch init launch");
+    if (S.stream_count > 0 || !b->init_src.empty()) {
+        // zero the arena and set the streamed circuits' basis amplitudes, then
+        // copy the given initial states in, before any other stream reads or
+        // writes a state there
+        if (S.stream_count > 0) {
+            hipError_t e = launch_batch_init(b->dt, b->arena, b->arena_bytes, S.dcirc, S.dlist + S.stream_l0,
+                                             S.stream_count, s0);
+            b->stats.launches += 2;
+            if (e != hipSuccess) return bfail(b, e, "batch init launch");
+        }
+        for (const auto& is : b->init_src) {
+            hipError_t e = hipMemcpyAsync(b->arena + b->off[is.first], is.second, amp_bytes(b->dt) << b->n[is.first],
+                                          hipMemcpyDeviceToDevice, s0);
+            if (e != hipSuccess) return bfail(b, e, "initial state copy");
+        }
         hipEvent_t ev;
         if (hipEventCreate(&ev) == hipSuccess) {
             (void)hipEventRecord(ev, s0);
@@ -271,7 +285,11 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     for (int i = 0; i < count; ++i) {
         const qs_circuit& c = circuits[i];
         if (c.n < 1 || c.n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "circuit %d: n=%d outside [1, %d]", i, c.n, QS_MAX_QUBITS);
-        if (c.init_basis >= (1ull << c.n)) return set_err(QS_ERR_ARG, "circuit %d: basis state out of range", i);
+        if (!c.init_state && c.init_basis >= (1ull << c.n))
+            return set_err(QS_ERR_ARG, "circuit %d: basis state out of range", i);
+        if (c.want < QS_WANT_NONE || c.want > QS_WANT_NORM) return set_err(QS_ERR_ARG, "circuit %d: want=%d", i, c.want);
+        if (c.want != QS_WANT_NONE && !c.out) return set_err(QS_ERR_ARG, "circuit %d: want without an output", i);
+        if (c.want == QS_WANT_PROBS && c.n > 24) return set_err(QS_ERR_ARG, "circuit %d: QS_WANT_PROBS needs n <= 24", i);
         qs_status st = validate_circuit(c.n, c.ops, c.n_ops, c.mats, c.n_mats);
         if (st != QS_OK) return set_err(st, "circuit %d: %s", i, qs_last_error());
     }
@@ -342,8 +360,10 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         const qs_circuit& c = circuits[i];
         std::memset(&bc[i], 0, sizeof(BatchCirc));
         bc[i].psi_off = b->off[i];
-        bc[i].basis = c.init_basis;
+        bc[i].basis = c.init_state ? kLoadInitial : c.init_basis;
         bc[i].n = c.n;
+        if (c.init_state) b->init_src.push_back({i, c.init_state});
+        if (c.want != QS_WANT_NONE) b->wants.push_back({i, {c.want, c.out}});
         if (b->mode == 1) continue;
         PlanOpts& po = popts[i];
         st = plan_opts_for(b->dt, c.ops, c.n_ops, o.fuse_k, o.tile_qubits, po);
@@ -560,7 +580,11 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
             const qs_circuit& c = circuits[i];
             hipStream_t s = b->st[i % NS];
             void* psi = b->arena + b->off[i];
-            st = launched(launch_init_basis(psi, b->dt, c.n, c.init_basis, s), "batch init launch");
+            if (c.init_state)
+                st = launched(hipMemcpyAsync(psi, c.init_state, amp_bytes(b->dt) << c.n, hipMemcpyDeviceToDevice, s),
+                              "initial state copy");
+            else
+                st = launched(launch_init_basis(psi, b->dt, c.n, c.init_basis, s), "batch init launch");
             for (int64_t g = 0; g < c.n_ops && st == QS_OK; ++g) {
                 const qs_op& op = c.ops[g];
                 const double* U = c.mats + op.moff;
@@ -594,7 +618,54 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
     return QS_OK;
 }
 
+} // extern "C"
+
+namespace {
+
+qs_status wait_done(qs_batch b, int timeout_ms);
+qs_status download_one(qs_batch b, int i, void* host);
+qs_status probs_one(qs_batch b, int i, const int* qubits, int m, double* out);
+
+// The wanted results of a finished run, written once per run.
+qs_status deliver(qs_batch b)
+{
+    if (b->delivered) return QS_OK;
+    std::vector<int> all;
+    for (const auto& w : b->wants) {
+        const int i = w.first, want = w.second.first;
+        void* out = w.second.second;
+        qs_status st = QS_OK;
+        if (want == QS_WANT_STATE) {
+            st = download_one(b, i, out);
+        } else if (want == QS_WANT_PROBS) {
+            all.resize((size_t)b->n[i]);
+            for (int q = 0; q < b->n[i]; ++q) all[(size_t)q] = q;
+            st = probs_one(b, i, all.data(), b->n[i], (double*)out);
+        } else if (want == QS_WANT_NORM) {
+            st = probs_one(b, i, nullptr, 0, (double*)out);
+        }
+        if (st != QS_OK) return st;
+    }
+    b->delivered = true;
+    return QS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
 qs_status qs_batch_wait(qs_batch b, int timeout_ms)
+{
+    qs_status st = wait_done(b, timeout_ms);
+    if (st != QS_OK) return st;
+    return deliver(b);
+}
+
+} // extern "C"
+
+namespace {
+
+qs_status wait_done(qs_batch b, int timeout_ms)
 {
     if (!b) return set_err(QS_ERR_ARG, "null batch handle");
     if (b->failed) return set_err(QS_ERR_DEVICE, "batch is in the failed state");
@@ -624,6 +695,38 @@ qs_status qs_batch_wait(qs_batch b, int timeout_ms)
     return QS_OK;
 }
 
+qs_status download_one(qs_batch b, int i, void* host)
+{
+    hipError_t e = hipMemcpy(host, b->arena + b->off[i], amp_bytes(b->dt) << b->n[i], hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bfail(b, e, "batch download");
+    return QS_OK;
+}
+
+qs_status probs_one(qs_batch b, int i, const int* qubits, int m, double* out)
+{
+    const int n = b->n[i];
+    const uint64_t need = reduce_scratch_doubles(n, m) + (1ull << m);
+    qs_status st;
+    if (need > b->red_cap) {
+        if (b->red) dev_free(b->red, b->red_cap * sizeof(double));
+        b->red = nullptr;
+        b->red_cap = 0;
+        if ((st = dev_alloc((void**)&b->red, need * sizeof(double), "batch reduction scratch")) != QS_OK) return st;
+        b->red_cap = need;
+    }
+    double* dout = b->red + reduce_scratch_doubles(n, m);
+    hipStream_t s0 = b->st[0];
+    hipError_t e = launch_probabilities(b->arena + b->off[i], b->dt, n, qubits, m, b->red, dout, s0);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) << m, hipMemcpyDeviceToHost, s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(s0);
+    if (e != hipSuccess) return bfail(b, e, "batch probabilities");
+    return QS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
 qs_status qs_batch_state(qs_batch b, int i, void** dev_ptr, int* n)
 {
     if (!b) return set_err(QS_ERR_ARG, "null batch handle");
@@ -638,11 +741,9 @@ qs_status qs_batch_download(qs_batch b, int i, void* host)
     if (!b) return set_err(QS_ERR_ARG, "null batch handle");
     if (i < 0 || i >= b->count) return set_err(QS_ERR_ARG, "circuit index %d outside [0, %d)", i, b->count);
     if (!host) return set_err(QS_ERR_ARG, "null host buffer");
-    qs_status st = qs_batch_wait(b, -1);
+    qs_status st = wait_done(b, -1);
     if (st != QS_OK) return st;
-    hipError_t e = hipMemcpy(host, b->arena + b->off[i], amp_bytes(b->dt) << b->n[i], hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return bfail(b, e, "batch download");
-    return QS_OK;
+    return download_one(b, i, host);
 }
 
 qs_status qs_batch_probabilities(qs_batch b, int i, const int* qubits, int m, double* out)
@@ -659,23 +760,9 @@ qs_status qs_batch_probabilities(qs_batch b, int i, const int* qubits, int m, do
         if ((seen >> qubits[j]) & 1) return set_err(QS_ERR_ARG, "duplicate qubit %d", qubits[j]);
         seen |= 1ull << qubits[j];
     }
-    qs_status st = qs_batch_wait(b, -1);
+    qs_status st = wait_done(b, -1);
     if (st != QS_OK) return st;
-    const uint64_t need = reduce_scratch_doubles(n, m) + (1ull << m);
-    if (need > b->red_cap) {
-        if (b->red) dev_free(b->red, b->red_cap * sizeof(double));
-        b->red = nullptr;
-        b->red_cap = 0;
-        if ((st = dev_alloc((void**)&b->red, need * sizeof(double), "batch reduction scratch")) != QS_OK) return st;
-        b->red_cap = need;
-    }
-    double* dout = b->red + reduce_scratch_doubles(n, m);
-    hipStream_t s0 = b->st[0];
-    hipError_t e = launch_probabilities(b->arena + b->off[i], b->dt, n, qubits, m, b->red, dout, s0);
-    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(double) << m, hipMemcpyDeviceToHost, s0);
-    if (e == hipSuccess) e = hipStreamSynchronize(s0);
-    if (e != hipSuccess) return bfail(b, e, "batch probabilities");
-    return QS_OK;
+    return probs_one(b, i, qubits, m, out);
 }
 
 qs_status qs_batch_norm(qs_batch b, int i, double* out) { return qs_batch_probabilities(b, i, nullptr, 0, out); }
@@ -699,8 +786,9 @@ qs_status qs_batch_replay(qs_batch b)
 {
     if (!b) return set_err(QS_ERR_ARG, "null batch handle");
     if (b->mode != 0) return set_err(QS_ERR_UNSUPPORTED, "replay needs a fused (mode 0) batch");
-    qs_status st = qs_batch_wait(b, -1);
+    qs_status st = wait_done(b, -1);
     if (st != QS_OK) return st;
+    b->delivered = false;
     hipStream_t s0 = b->st[0];
     hipError_t e = hipEventRecord(b->t0, s0);
     if (e != hipSuccess) return bfail(b, e, "hipEventRecord");

@@ -10,6 +10,7 @@
 //                  amplitudes whatever the targets.
 //   k_kq_lds       dense gate on k <= 6 targets: groups of 2^k amplitudes are
 //                  staged through LDS with the matrix, one output per lane.
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 
@@ -75,10 +76,14 @@ hipError_t launch_init_basis(void* psi, int dt, int n, uint64_t x, hipStream_t s
 // bit 6 are tested per amplitude (the whole wave still takes part in the
 // shuffles); controls at bit 6 or above are inserted into the counter.
 //
-// Memory schedule (measured on MI355X for in-place read-modify-write): one
-// counter chunk per block (no grid-stride loop), a lane's PPL slots spread S
-// = 2^11 counter steps apart, non-temporal loads and stores when every store
-// instruction writes whole lines.
+// Memory schedule (measured on MI355X for in-place read-modify-write; see
+// gate_sched below): one counter chunk per block (no grid-stride loop), a
+// lane's PPL slots spread S = 2^11 counter steps apart, non-temporal loads
+// and stores when every store instruction writes whole lines, occupancy
+// capped through unused LDS, and an optional XCD-contiguous chunk order.
+// Targets below bit 6 but at or above the 128-byte line are held in
+// registers like high ones (each load instruction then still covers whole
+// lines); only targets inside a line are exchanged by shuffles.
 struct GateArgs {
     uint64_t C;          // counter range
     uint64_t cv_hi;      // control values at positions >= 6
@@ -187,8 +192,18 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
     }
 }
 
+// LDS bytes a workgroup must hold so that at most `wg` fit on one CU (160 KiB
+// of LDS per CU on gfx950): just over a (wg+1)-th of it, so wg + 1 do not fit
+// and wg do.  The unused part caps the kernel's occupancy.
+size_t pad_for_wg_per_cu(int wg, size_t static_lds)
+{
+    if (wg <= 0) return 0;
+    const size_t per = 163840 / ((size_t)wg + 1) + 64;
+    return per > static_lds ? per - static_lds : 0;
+}
+
 template <typename R, int K, int NH, int PPL>
-static void launch_gate_p(void* psi, const GateArgs& ga, bool nt, hipStream_t st)
+static hipError_t launch_gate_p(void* psi, const GateArgs& ga, bool nt, int wg_per_cu, hipStream_t st)
 {
     using V = typename CT<R>::V;
     // One block per counter chunk up to the cap (at most 2^22: 2^32 threads
@@ -196,52 +211,92 @@ static void launch_gate_p(void* psi, const GateArgs& ga, bool nt, hipStream_t st
     // remaining chunks.
     const uint64_t cap = (uint64_t)tun(T_GATE_GRID_CAP);
     const unsigned g = (unsigned)(ga.nblocks < cap ? ga.nblocks : cap);
-    const size_t pad = (size_t)tun(T_GATE_LDS_PAD); // unused LDS: fewer workgroups per CU
+    constexpr size_t kStatic = 2 * (1 << K) * (1 << K) * sizeof(double); // the matrix in LDS
+    const size_t pad = pad_for_wg_per_cu(wg_per_cu, kStatic);
     const void* fn = nt ? (const void*)k_gate<R, K, NH, PPL, true> : (const void*)k_gate<R, K, NH, PPL, false>;
-    if (lds_optin(fn, pad) != hipSuccess) return;
+    hipError_t e = lds_optin(fn, pad);
+    if (e != hipSuccess) return e;
     if (nt)
         hipLaunchKernelGGL((k_gate<R, K, NH, PPL, true>), dim3(g), dim3(256), pad, st, (V*)psi, ga);
     else
         hipLaunchKernelGGL((k_gate<R, K, NH, PPL, false>), dim3(g), dim3(256), pad, st, (V*)psi, ga);
+    return hipGetLastError();
 }
 
-// Slots per lane by the number of high targets (the slots_* knobs override
-// the built-in table).
+// The memory schedule of one gate: slots per lane, workgroups per CU (0 = as
+// many as fit) and chunk order.  Measured on MI355X at n=30 (16 GiB complex128
+// and 8 GiB complex64 states) over every target, in-place:
+// - the bytes of loads in flight per CU, not occupancy as such, set the rate:
+//   about 32 KiB per CU for two-stream gates (one high target) and 48 KiB for
+//   four-stream ones (two high targets) give 6.2-6.8 TB/s, while full
+//   occupancy keeps two to three times that in flight and thrashes DRAM pages
+//   (5.4-6.1 TB/s for complex128, 3-4.4 TB/s for complex64 at a workgroup
+//   count sized for complex128).  Without high targets (every member inside
+//   a 64-amplitude run, exchanged by shuffles) the shuffle latency wants 8
+//   slots per lane and about 96 KiB in flight.  So workgroups per CU =
+//   target bytes / (256 lanes x slots x 2^NH members x amplitude bytes);
+// - every XCD walking its own contiguous eighth of the chunks beats
+//   workgroup order on most target distances (by up to 25 % for pairs 8-32
+//   MiB apart); which order wins for a given distance varies between boxes
+//   (the physical placement of the buffer differs), so XCD order is taken
+//   throughout, except without high targets (a single stream);
+// - states that fit the 256 MB Infinity Cache keep full occupancy and
+//   workgroup order (their traffic does not reach the DRAM pages).
+// The slots_*, gate_wg_per_cu and gate_xcd_swizzle knobs override the rule.
+struct GateSched {
+    int ppl, wg, xcd;
+};
+
 template <typename R, int K, int NH>
-static void launch_gate_k(void* psi, GateArgs& ga, bool nt, hipStream_t st)
+static GateSched gate_sched(uint64_t state_bytes)
 {
-    const int ppl_env = (int)tun(NH == 0 ? T_PPL_H0 : (NH == 1 ? T_PPL_H1 : T_PPL_H2));
-    // Measured on MI355X (n=30 c128, every target): 8 slots without high
-    // targets (2-3 % over 4); one high target (1q, or 2q with the other
-    // target low): 1 slot while its partner is less than 16 MiB away
-    // (t < 20), 2 beyond (150-300 GB/s either way); two high targets: 1 slot,
-    // except both at bit 18 or above, where 2 slots recover 10-15% (their
-    // four streams are megabytes apart).
     using V = typename CT<R>::V;
-    int ppl = NH == 0 ? 8
-              : NH == 1 ? (ga.roff[1] * sizeof(V) < (16ull << 20) ? 1 : 2)
-                        : (ga.roff[1] >= (1ull << 18) && ga.roff[2] >= (1ull << 18) ? 2 : 1);
-    if (ppl_env > 0) ppl = ppl_env;
+    GateSched g;
+    uint64_t target; // bytes of loads in flight per CU
+    if (NH == 0) {
+        g = {8, 0, 0};
+        target = 96 << 10;
+    } else if (NH == 1) {
+        const bool shuffled = K == 2; // the other target is exchanged by shuffles
+        g = {shuffled ? 2 : 1, 0, 1};
+        target = shuffled ? (48 << 10) : (32 << 10);
+    } else {
+        g = {1, 0, 1};
+        target = 48 << 10;
+    }
+    if (state_bytes >= (512ull << 20)) {
+        const uint64_t per_wg = 256ull * (uint64_t)g.ppl * (1ull << NH) * sizeof(V);
+        g.wg = (int)std::min<uint64_t>(8, std::max<uint64_t>(1, target / per_wg));
+    } else {
+        g.wg = 0;
+        g.xcd = 0;
+    }
+    const int ppl_k = (int)tun(NH == 0 ? T_PPL_H0 : (NH == 1 ? T_PPL_H1 : T_PPL_H2));
+    if (ppl_k > 0) g.ppl = ppl_k;
+    const int wg_k = (int)tun(T_GATE_WG_PER_CU);
+    if (wg_k > 0) g.wg = wg_k;
+    const int xcd_k = (int)tun(T_GATE_XCD);
+    if (xcd_k > 0) g.xcd = xcd_k - 1;
+    return g;
+}
+
+template <typename R, int K, int NH>
+static hipError_t launch_gate_k(void* psi, GateArgs& ga, bool nt, uint64_t state_bytes, hipStream_t st)
+{
+    const GateSched gs = gate_sched<R, K, NH>(state_bytes);
     auto go = [&](auto pplc) {
         constexpr int P = decltype(pplc)::value;
         const int sl = (int)tun(T_SLOG);
         ga.slog = (ga.C >= ((1ull << sl) * P)) ? sl : 8;
         ga.nblocks = (ga.C + 256 * P - 1) / (256 * P);
-        ga.xcd = (tun(T_GATE_XCD) && ga.nblocks % 8 == 0) ? 1 : 0;
-        launch_gate_p<R, K, NH, P>(psi, ga, nt, st);
+        ga.xcd = (gs.xcd && ga.nblocks % 8 == 0) ? 1 : 0;
+        return launch_gate_p<R, K, NH, P>(psi, ga, nt, gs.wg, st);
     };
-    if (ppl == 1) {
-        go(std::integral_constant<int, 1>());
-    } else if (ppl == 4) {
-        go(std::integral_constant<int, 4>());
-    } else if (ppl == 8) {
-        if constexpr (NH == 0)
-            go(std::integral_constant<int, 8>());
-        else
-            go(std::integral_constant<int, 4>());
-    } else {
-        go(std::integral_constant<int, 2>());
-    }
+    if (gs.ppl == 1) return go(std::integral_constant<int, 1>());
+    if (gs.ppl == 2) return go(std::integral_constant<int, 2>());
+    if constexpr (NH == 0)
+        if (gs.ppl >= 8) return go(std::integral_constant<int, 8>());
+    return go(std::integral_constant<int, 4>());
 }
 
 template <typename R>
@@ -324,20 +379,12 @@ static hipError_t apply_gate_t(void* psi, int n, int K, const int* t, const doub
     // no lane skips its store (no per-amplitude controls), no register target
     // inside a line, and full waves.
     const bool nt = tun(T_NT) && ga.cm_lo == 0 && (reg_low & linemask) == 0 && ga.C >= 64;
-    if (K == 1) {
-        if (nh == 0)
-            launch_gate_k<R, 1, 0>(psi, ga, nt, st);
-        else
-            launch_gate_k<R, 1, 1>(psi, ga, nt, st);
-    } else {
-        if (nh == 0)
-            launch_gate_k<R, 2, 0>(psi, ga, nt, st);
-        else if (nh == 1)
-            launch_gate_k<R, 2, 1>(psi, ga, nt, st);
-        else
-            launch_gate_k<R, 2, 2>(psi, ga, nt, st);
-    }
-    return hipGetLastError();
+    const uint64_t sb = (1ull << n) * sizeof(R) * 2;
+    if (K == 1)
+        return nh == 0 ? launch_gate_k<R, 1, 0>(psi, ga, nt, sb, st) : launch_gate_k<R, 1, 1>(psi, ga, nt, sb, st);
+    if (nh == 0) return launch_gate_k<R, 2, 0>(psi, ga, nt, sb, st);
+    if (nh == 1) return launch_gate_k<R, 2, 1>(psi, ga, nt, sb, st);
+    return launch_gate_k<R, 2, 2>(psi, ga, nt, sb, st);
 }
 
 hipError_t launch_apply_1q(void* psi, int dt, int n, int t, const double* U, uint64_t cm, uint64_t cv,

@@ -178,9 +178,13 @@ struct BatchPass {
 };
 
 // Circuit descriptor in device memory.
+// BatchCirc / ServeEntry basis value meaning "the initial state is already in
+// place" (copied in from the caller); a real basis index is below 2^34.
+constexpr uint64_t kLoadInitial = ~0ull;
+
 struct BatchCirc {
     uint64_t psi_off; // byte offset of the state inside the batch arena
-    uint64_t basis;   // initial basis state
+    uint64_t basis;   // initial basis state, or kLoadInitial
     int32_t n;
     int32_t pass0, npass;
     int32_t rsv;
@@ -231,7 +235,7 @@ struct ServeEntry {
     uint64_t pass_off;     // UINT64_MAX: no pass (a whole circuit without gates)
     uint64_t ops_off;      // base the pass's op0 indexes
     uint64_t mats_off;     // base the ops' moff index
-    uint64_t basis;
+    uint64_t basis;        // initial basis state, or kLoadInitial
     uint32_t first_block;
     int32_t n;
 };

@@ -50,10 +50,11 @@ hipError_t launch_probe_k(void* dev, uint64_t n16, int slog, uint64_t mask, hipS
     const uint64_t nblocks = (n16 + 256 * SLOTS - 1) / (256 * SLOTS);
     const uint64_t cap = (uint64_t)tun(T_GATE_GRID_CAP);
     const unsigned g = (unsigned)(nblocks < cap ? nblocks : cap);
-    const size_t pad = (size_t)tun(T_GATE_LDS_PAD); // unused LDS: fewer workgroups per CU
+    // the per-gate kernel's occupancy knob applies (unused LDS: fewer workgroups per CU)
+    const size_t pad = pad_for_wg_per_cu((int)tun(T_GATE_WG_PER_CU), 0);
     hipError_t e = lds_optin((const void*)k_probe_rmw<SLOTS>, pad);
     if (e != hipSuccess) return e;
-    const int xcd = (tun(T_GATE_XCD) && nblocks % 8 == 0) ? 1 : 0;
+    const int xcd = (tun(T_GATE_XCD) == 2 && nblocks % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL(k_probe_rmw<SLOTS>, dim3(g), dim3(256), pad, st, (ulonglong2*)dev, n16, nblocks, slog, xcd,
                        mask);
     return hipGetLastError();

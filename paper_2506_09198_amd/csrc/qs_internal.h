@@ -106,8 +106,8 @@ enum Tun {
     T_PPL_H2,          //   with two
     T_DIAG_SLOG,       // diagonal kernel: log2 slot distance
     T_PERM_RUN,        // restore pass: log2 run length (0 = built-in choice)
-    T_GATE_XCD,        // per-gate kernel: 1 = each XCD walks a contiguous eighth of the chunks
-    T_GATE_LDS_PAD,    // per-gate kernel and probe: extra LDS bytes per workgroup (limits occupancy)
+    T_GATE_XCD,        // per-gate kernel chunk order: 0 rule, 1 workgroup order, 2 XCD-contiguous
+    T_GATE_WG_PER_CU,  // per-gate kernel and probe: workgroups per CU (0 rule; 8 and up: no cap in effect)
     T_GATE_LOW_HIGH,   // per-gate kernel: targets below bit 6 held in registers (1: at or above the
                        //   128-byte line bit, 2: all) instead of exchanged by shuffles
     T_COUNT
@@ -116,6 +116,8 @@ int64_t tun(Tun id);
 // Opt a kernel in to `bytes` of dynamic LDS on the current device (no-op up
 // to 64 KiB; remembered per kernel and device; thread-safe).
 hipError_t lds_optin(const void* fn, size_t bytes);
+// Unused LDS bytes that cap a kernel at `wg` workgroups per CU (0: none).
+size_t pad_for_wg_per_cu(int wg, size_t static_lds);
 
 inline size_t amp_bytes(int dt) { return dt == QS_C128 ? 16 : 8; }
 

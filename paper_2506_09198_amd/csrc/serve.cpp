@@ -75,7 +75,10 @@ enum { R_QUEUED = 0, R_ACTIVE = 1, R_DONE = 2, R_FAILED = 3, R_CANCELLED = 4 };
 struct Req {
     uint64_t id = 0;
     int n = 0;
-    uint64_t basis = 0;
+    uint64_t basis = 0;               // basis state, or kLoadInitial with init_state
+    const void* init_state = nullptr; // caller's device copy of the initial state
+    int want = QS_WANT_NONE;          // result written to `out` when the request is done
+    void* out = nullptr;
     std::vector<qs_op> ops;
     std::vector<double> mats;
     int state = R_QUEUED;
@@ -121,6 +124,11 @@ struct qs_server_s {
     std::deque<qs_result> completed;
     std::chrono::steady_clock::time_point t0;
     qs_server_stats stats;
+    // delivery of wanted results: own stream (the rounds' stream may hold
+    // rounds enqueued ahead) and reduction scratch
+    hipStream_t rst = nullptr;
+    double* red = nullptr;
+    uint64_t red_cap = 0; // doubles
 };
 
 namespace {
@@ -130,8 +138,56 @@ double now_ms(qs_server s)
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
+// Write a finished request's wanted result to its host buffer.  Its last
+// round has completed (its event was seen), so the state in the pool is final.
+qs_status deliver(qs_server s, const Req& r)
+{
+    hipError_t e = hipSuccess;
+    if (!s->rst) {
+        e = hipStreamCreateWithFlags(&s->rst, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            s->rst = nullptr;
+            (void)hipGetLastError();
+            return set_err(QS_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+    }
+    const char* psi = s->pool + r.s_off;
+    if (r.want == QS_WANT_STATE) {
+        e = hipMemcpyAsync(r.out, psi, amp_bytes(s->dt) << r.n, hipMemcpyDeviceToHost, s->rst);
+    } else {
+        const int m = r.want == QS_WANT_PROBS ? r.n : 0;
+        std::vector<int> q((size_t)m);
+        for (int j = 0; j < m; ++j) q[(size_t)j] = j;
+        const uint64_t need = reduce_scratch_doubles(r.n, m) + (1ull << m);
+        if (need > s->red_cap) {
+            if (s->red) dev_free(s->red, s->red_cap * sizeof(double));
+            s->red = nullptr;
+            s->red_cap = 0;
+            qs_status st = dev_alloc((void**)&s->red, need * sizeof(double), "serving reduction scratch");
+            if (st != QS_OK) return st;
+            s->red_cap = need;
+        }
+        double* dout = s->red + reduce_scratch_doubles(r.n, m);
+        e = launch_probabilities(psi, s->dt, r.n, q.data(), m, s->red, dout, s->rst);
+        if (e == hipSuccess) e = hipMemcpyAsync(r.out, dout, sizeof(double) << m, hipMemcpyDeviceToHost, s->rst);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->rst);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(QS_ERR_DEVICE, "result delivery: %s", hipGetErrorString(e));
+    }
+    return QS_OK;
+}
+
 void finish(qs_server s, Req& r, qs_status st, int state)
 {
+    if (state == R_DONE && r.want != QS_WANT_NONE) {
+        const qs_status d = deliver(s, r);
+        if (d != QS_OK) {
+            st = d;
+            state = R_FAILED;
+        }
+    }
     r.state = state;
     r.status = st;
     r.t_done = now_ms(s);
@@ -258,11 +314,26 @@ qs_status admit_one(qs_server s, Req& r)
     r.ops_off = al(bp.size() * sizeof(BatchPass));
     r.mats_off = al(r.ops_off + to.size() * sizeof(TileOp));
     r.p_bytes = al(r.mats_off + pool.size() * sizeof(double)) + 256;
+    if (r.p_bytes > s->ppool.size) {
+        // can never fit, however many requests finish: fail it, do not queue it forever
+        s->spool.release(r.s_off, r.s_bytes);
+        r.s_bytes = 0;
+        const unsigned long long pb = r.p_bytes;
+        r.p_bytes = 0;
+        return set_err(QS_ERR_ARG, "plan of %llu bytes can never fit the serving plan pool of %llu bytes", pb,
+                       (unsigned long long)s->ppool.size);
+    }
     if (!s->ppool.alloc(r.p_bytes, &r.p_off)) {
         s->spool.release(r.s_off, r.s_bytes);
         r.s_bytes = 0;
         r.p_bytes = 0;
         return QS_ERR_OOM;
+    }
+    if (r.init_state) {
+        // the caller's initial state into the pool, ahead of the request's rounds
+        hipError_t e0 = hipMemcpyAsync(s->pool + r.s_off, r.init_state, amp_bytes(s->dt) << r.n,
+                                       hipMemcpyDeviceToDevice, s->st);
+        if (e0 != hipSuccess) return set_err(QS_ERR_DEVICE, "initial state copy: %s", hipGetErrorString(e0));
     }
     r.plan_host.assign(r.p_bytes, 0);
     std::memcpy(r.plan_host.data() + r.passes_off, bp.data(), bp.size() * sizeof(BatchPass));
@@ -272,7 +343,7 @@ qs_status admit_one(qs_server s, Req& r)
     if (e != hipSuccess) return set_err(QS_ERR_DEVICE, "plan upload: %s", hipGetErrorString(e));
     r.npass = (int)passes.size();
     r.next_pass = 0;
-    if (!r.whole) {
+    if (!r.whole && !r.init_state) {
         // tile passes read the state from HBM: start it as |basis>
         if (inject_fault_now()) return set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
         e = launch_init_basis(s->pool + r.s_off, s->dt, r.n, r.basis, s->st);
@@ -511,7 +582,10 @@ qs_status qs_server_submit(qs_server s, const qs_circuit* c, uint64_t* id)
 {
     if (!s || !c || !id) return set_err(QS_ERR_ARG, "null argument");
     if (c->n < 1 || c->n > QS_MAX_QUBITS) return set_err(QS_ERR_ARG, "n=%d outside [1, %d]", c->n, QS_MAX_QUBITS);
-    if (c->init_basis >= (1ull << c->n)) return set_err(QS_ERR_ARG, "basis state out of range");
+    if (!c->init_state && c->init_basis >= (1ull << c->n)) return set_err(QS_ERR_ARG, "basis state out of range");
+    if (c->want < QS_WANT_NONE || c->want > QS_WANT_NORM) return set_err(QS_ERR_ARG, "want=%d", c->want);
+    if (c->want != QS_WANT_NONE && !c->out) return set_err(QS_ERR_ARG, "want without an output buffer");
+    if (c->want == QS_WANT_PROBS && c->n > 24) return set_err(QS_ERR_ARG, "QS_WANT_PROBS needs n <= 24");
     qs_status st = validate_circuit(c->n, c->ops, c->n_ops, c->mats, c->n_mats);
     if (st != QS_OK) return st;
     const uint64_t need = ((amp_bytes(s->dt) << c->n) + 255) & ~255ull;
@@ -521,7 +595,10 @@ qs_status qs_server_submit(qs_server s, const qs_circuit* c, uint64_t* id)
     Req r;
     r.id = s->next_id++;
     r.n = c->n;
-    r.basis = c->init_basis;
+    r.basis = c->init_state ? kLoadInitial : c->init_basis;
+    r.init_state = c->init_state;
+    r.want = c->want;
+    r.out = c->out;
     r.ops.assign(c->ops, c->ops + c->n_ops);
     r.mats.assign(c->mats, c->mats + c->n_mats);
     r.t_submit = now_ms(s);
@@ -640,6 +717,8 @@ qs_status qs_server_destroy(qs_server s)
         if (x.dev) dev_free(x.dev, (uint64_t)x.cap * sizeof(ServeEntry));
     }
     if (s->st) (void)hipStreamDestroy(s->st);
+    if (s->rst) (void)hipStreamDestroy(s->rst);
+    if (s->red) dev_free(s->red, s->red_cap * sizeof(double));
     if (s->pool) dev_free(s->pool, s->spool.size);
     if (s->plan) dev_free(s->plan, s->ppool.size);
     (void)hipGetLastError();

@@ -22,13 +22,18 @@ k_batch_whole(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
     uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
     const BatchCirc& c = circs[list[blockIdx.x]];
     V* psi = (V*)(arena + c.psi_off);
-    for (uint32_t e = threadIdx.x; e < E; e += 256) {
-        V v;
-        v.x = (e == c.basis) ? (R)1 : (R)0;
-        v.y = 0;
-        tile[QS_SW(e)] = v;
-    }
     if (threadIdx.x == 0) hoff[0] = 0;
+    if (c.basis == kLoadInitial) { // the caller's initial state, copied into the arena
+        __syncthreads();
+        tile_load<R, M>(psi, 0, M, hoff, tile, 0);
+    } else {
+        for (uint32_t e = threadIdx.x; e < E; e += 256) {
+            V v;
+            v.x = (e == c.basis) ? (R)1 : (R)0;
+            v.y = 0;
+            tile[QS_SW(e)] = v;
+        }
+    }
     __syncthreads();
     for (int p = 0; p < c.npass; ++p) {
         const BatchPass& bp = passes[c.pass0 + p];
@@ -51,12 +56,13 @@ k_batch_persist(char* __restrict__ arena, const BatchCirc* __restrict__ circs, c
     const BatchCirc& c = circs[list[blockIdx.x]];
     V* psi = (V*)(arena + c.psi_off);
     const uint64_t N = 1ull << c.n;
-    for (uint64_t i = threadIdx.x; i < N; i += 256) {
-        V v;
-        v.x = (i == c.basis) ? (R)1 : (R)0;
-        v.y = 0;
-        psi[i] = v;
-    }
+    if (c.basis != kLoadInitial) // else the caller's initial state is in place
+        for (uint64_t i = threadIdx.x; i < N; i += 256) {
+            V v;
+            v.x = (i == c.basis) ? (R)1 : (R)0;
+            v.y = 0;
+            psi[i] = v;
+        }
     __syncthreads(); // global writes of this block are visible to its own later loads
     const uint64_t ntiles = 1ull << (c.n - M);
     for (int p = 0; p < c.npass; ++p) {
@@ -138,6 +144,7 @@ k_batch_basis(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
 {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < count; i += gridDim.x * 256) {
         const BatchCirc& c = circs[list[i]];
+        if (c.basis == kLoadInitial) continue; // copied in after this kernel
         V v;
         v.x = 1;
         v.y = 0;

@@ -59,13 +59,18 @@ k_serve_whole(char* __restrict__ pool, const char* __restrict__ plan, const Serv
     V* tile = (V*)smem;
     uint32_t* hoff = (uint32_t*)(smem + sizeof(V) * E);
     const ServeEntry& en = entries[blockIdx.x];
-    for (uint32_t e = threadIdx.x; e < E; e += 256) {
-        V v;
-        v.x = (e == en.basis) ? (R)1 : (R)0;
-        v.y = 0;
-        tile[QS_SW(e)] = v;
-    }
     if (threadIdx.x == 0) hoff[0] = 0;
+    if (en.basis == kLoadInitial) { // the caller's initial state, copied into the pool
+        __syncthreads();
+        tile_load<R, M>((const V*)(pool + en.psi_off), 0, M, hoff, tile, 0);
+    } else {
+        for (uint32_t e = threadIdx.x; e < E; e += 256) {
+            V v;
+            v.x = (e == en.basis) ? (R)1 : (R)0;
+            v.y = 0;
+            tile[QS_SW(e)] = v;
+        }
+    }
     __syncthreads();
     if (en.pass_off != ~0ull) {
         const BatchPass& bp = *(const BatchPass*)(plan + en.pass_off);

@@ -38,9 +38,9 @@ const TunDef kTun[T_COUNT] = {
     {"slots_two_high", "QS_PPL_H2", 0, 0, 8},
     {"diag_spread_log2", "QS_DIAG_SLOG", 11, 8, 16},
     {"perm_run_log2", "QS_PERM_RUN", 0, 0, 6},
-    {"gate_xcd_swizzle", "QS_GATE_XCD", 0, 0, 1},
-    {"gate_lds_pad", "QS_GATE_LDS_PAD", 0, 0, 65536},
-    {"gate_low_in_regs", "QS_GATE_LOW_HIGH", 0, 0, 2},
+    {"gate_xcd_swizzle", "QS_GATE_XCD", 0, 0, 2},
+    {"gate_wg_per_cu", "QS_GATE_WG_PER_CU", 0, 0, 32},
+    {"gate_low_in_regs", "QS_GATE_LOW_HIGH", 1, 0, 2},
 };
 
 std::atomic<int64_t> g_val[T_COUNT];

@@ -1,6 +1,7 @@
 """C-ABI checks that need no GPU: the library loads, exports every entry point
 the header declares, rejects bad arguments before touching the device, and the
 host-side planner groups gates as designed."""
+import ctypes
 import os
 import re
 import subprocess
@@ -199,3 +200,23 @@ def test_tunables_roundtrip_and_validation():
         qs.qs_tunable_set("slots_one_high", 9)
     with pytest.raises(qs.QSError):
         qs.qs_tunable_set("no_such_knob", 1)
+
+
+def test_circuit_record_and_want_validation(qs):
+    """qs_circuit is 64 bytes (want, init_state and out after the original
+    fields); a wanted result needs a host buffer and a known kind; the
+    checks run before any device work."""
+    import workloads as W
+
+    assert ctypes.sizeof(qs._Circuit) == 64
+    c = W.qft(8, 1)
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_batch_submit([(c.n, *c.arrays(), 0, 0, qs.QS_WANT_STATE, None)])
+    assert e.value.status == qs.QS_ERR_ARG
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_batch_submit([(c.n, *c.arrays(), 0, 0, 7, np.zeros(1))])
+    assert e.value.status == qs.QS_ERR_ARG
+    big = W.qft(25, 0)
+    with pytest.raises(qs.QSError) as e:
+        qs.qs_batch_submit([(big.n, *big.arrays(), 0, 0, qs.QS_WANT_PROBS, np.zeros(1))])
+    assert e.value.status == qs.QS_ERR_ARG

@@ -156,3 +156,66 @@ def test_serving_round_block_loop(qs, dt):
     for got in outs[1:]:
         for c, a, b in zip(circs, got, outs[0]):
             assert a.tobytes() == b.tobytes(), c.name
+
+
+SCHEDULES = [
+    {},
+    {"gate_low_in_regs": 0},
+    {"gate_low_in_regs": 2},
+    {"gate_xcd_swizzle": 1},
+    {"gate_xcd_swizzle": 2},
+    {"gate_wg_per_cu": 1},
+    {"gate_wg_per_cu": 8},
+    {"slots_no_high": 1, "slots_one_high": 2, "slots_two_high": 4},
+    {"slots_no_high": 2, "slots_one_high": 4, "slots_two_high": 2},
+    {"gate_grid_cap": 3, "gate_xcd_swizzle": 2, "gate_low_in_regs": 2},
+]
+
+
+def _pergate_list(n, rng):
+    """Every 1q target with and without controls (including controls inside a
+    128-byte line), and 2q pairs: both inside a line, one inside, adjacent,
+    far, with controls."""
+    gates = []
+    for t in range(n):
+        gates.append(((t,), W.haar_unitary(2, rng), 0, 0))
+        for cm_bits in ((0,), (1,), (2, 5), (n - 1,)):
+            cs = [c for c in cm_bits if c != t and c < n]
+            if cs:
+                cm = sum(1 << c for c in cs)
+                gates.append(((t,), W.haar_unitary(2, rng), cm, cm & ~(1 << cs[0]) if len(cs) > 1 else cm))
+    for t0, t1 in ((0, 1), (1, 0), (0, 2), (2, 4), (3, 4), (5, 6), (0, n - 1), (n - 1, 4), (6, 7), (n - 2, n - 1)):
+        gates.append(((t0, t1), W.haar_unitary(4, rng), 0, 0))
+        others = [q for q in (0, 1, 3, 9) if q not in (t0, t1)]
+        cm = (1 << others[0]) | (1 << others[1])
+        gates.append(((t0, t1), W.haar_unitary(4, rng), cm, 1 << others[0]))
+    return gates
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+@pytest.mark.parametrize("n", [10, 16])
+def test_pergate_schedules(qs, dt, n):
+    """The per-gate kernel under every schedule knob (registers vs shuffles
+    for low targets, chunk order by XCD, workgroups per CU, slots per lane,
+    a looping grid) against the oracle, and bitwise the same across them."""
+    rng = np.random.default_rng(600 + n)
+    gates = _pergate_list(n, rng)
+    psi0 = W.random_state(n, 61)
+    want = psi0.copy()
+    for tg, u, cm, cv in gates:
+        oracle.apply_op(n, want, tg, u, cm, cv)
+    outs = []
+    for knobs in SCHEDULES:
+        with qs.tunables(**knobs):
+            with qs.State.create(n, dt) as s:
+                s.upload(psi0 if dt == 2 else psi0.astype(np.complex64))
+                for tg, u, cm, cv in gates:
+                    if len(tg) == 1:
+                        qs.qs_apply_1q(s.h, tg[0], u, cm, cv)
+                    else:
+                        qs.qs_apply_2q(s.h, tg[0], tg[1], u, cm, cv)
+                got = s.download()
+        _check(got, want, dt, f"n={n} {knobs}")
+        outs.append(got)
+    for knobs, o in zip(SCHEDULES[1:], outs[1:]):
+        assert o.tobytes() == outs[0].tobytes(), f"{knobs} differs bitwise from the default schedule"

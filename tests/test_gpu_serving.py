@@ -150,6 +150,23 @@ def test_server_rejects_oversize_and_cancels(qs):
         qs.qs_server_destroy(srv)
 
 
+def test_server_plan_larger_than_pool_fails(qs):
+    """A request whose plan can never fit the plan pool finishes with
+    QS_ERR_ARG instead of staying queued; a small one beside it is served."""
+    srv = qs.qs_server_create(dtype=2, hbm_budget=1 << 28, plan_budget=256 << 10)
+    try:
+        big = W.rqc_chain(18, 200, 3)  # ~5400 gates: hundreds of KiB of plan
+        small = W.qft(10, 77)
+        a = qs.qs_server_submit(srv, big)
+        b = qs.qs_server_submit(srv, small)
+        done = _drain(qs, srv, [a, b])
+        assert done[a]["status"] == qs.QS_ERR_ARG
+        assert done[b]["status"] == 0
+        _check(qs.qs_server_download(srv, b, 2), oracle.run_circuit(small), 2, "small beside the failed one")
+    finally:
+        qs.qs_server_destroy(srv)
+
+
 FAULT_SCRIPT = r"""
 import json, sys, time
 sys.path.insert(0, sys.argv[1])
