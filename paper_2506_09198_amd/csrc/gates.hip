@@ -226,20 +226,22 @@ static hipError_t launch_gate_p(void* psi, const GateArgs& ga, bool nt, int wg_p
 // The memory schedule of one gate: slots per lane, workgroups per CU (0 = as
 // many as fit) and chunk order.  Measured on MI355X at n=30 (16 GiB complex128
 // and 8 GiB complex64 states) over every target, in-place:
-// - the bytes of loads in flight per CU, not occupancy as such, set the rate:
-//   about 32 KiB per CU for two-stream gates (one high target) and 48 KiB for
-//   four-stream ones (two high targets) give 6.2-6.8 TB/s, while full
-//   occupancy keeps two to three times that in flight and thrashes DRAM pages
-//   (5.4-6.1 TB/s for complex128, 3-4.4 TB/s for complex64 at a workgroup
-//   count sized for complex128).  Without high targets (every member inside
-//   a 64-amplitude run, exchanged by shuffles) the shuffle latency wants 8
-//   slots per lane and about 96 KiB in flight.  So workgroups per CU =
-//   target bytes / (256 lanes x slots x 2^NH members x amplitude bytes);
+// - the bytes of loads in flight per CU, not occupancy as such, set the rate
+//   of the streaming cases: about 32 KiB per CU for two-stream gates (one
+//   high target) and 48 KiB for four-stream ones (two high targets) give
+//   6.1-6.8 TB/s, while full occupancy keeps two to three times that in
+//   flight and thrashes DRAM pages (5.4-6.1 TB/s for complex128; complex64
+//   at the complex128 workgroup counts drops to 3-4.4 TB/s, half the bytes in
+//   flight).  Gates whose members are exchanged by shuffles (a target inside
+//   a 128-byte line) are bound by the shuffle latency instead and want more
+//   waves: 3 workgroups of 8 slots (complex128), as many as fit (complex64).
+//   Complex128 / complex64 workgroups per CU: one high target 4 / 8, two
+//   high targets 3 / 6, shuffled 3 / 8;
 // - every XCD walking its own contiguous eighth of the chunks beats
 //   workgroup order on most target distances (by up to 25 % for pairs 8-32
 //   MiB apart); which order wins for a given distance varies between boxes
 //   (the physical placement of the buffer differs), so XCD order is taken
-//   throughout, except without high targets (a single stream);
+//   whenever a target is held in registers;
 // - states that fit the 256 MB Infinity Cache keep full occupancy and
 //   workgroup order (their traffic does not reach the DRAM pages).
 // The slots_*, gate_wg_per_cu and gate_xcd_swizzle knobs override the rule.
@@ -250,24 +252,17 @@ struct GateSched {
 template <typename R, int K, int NH>
 static GateSched gate_sched(uint64_t state_bytes)
 {
-    using V = typename CT<R>::V;
+    constexpr bool C128 = sizeof(R) == 8;
     GateSched g;
-    uint64_t target; // bytes of loads in flight per CU
-    if (NH == 0) {
-        g = {8, 0, 0};
-        target = 96 << 10;
-    } else if (NH == 1) {
-        const bool shuffled = K == 2; // the other target is exchanged by shuffles
-        g = {shuffled ? 2 : 1, 0, 1};
-        target = shuffled ? (48 << 10) : (32 << 10);
-    } else {
-        g = {1, 0, 1};
-        target = 48 << 10;
-    }
-    if (state_bytes >= (512ull << 20)) {
-        const uint64_t per_wg = 256ull * (uint64_t)g.ppl * (1ull << NH) * sizeof(V);
-        g.wg = (int)std::min<uint64_t>(8, std::max<uint64_t>(1, target / per_wg));
-    } else {
+    if (NH == 0)
+        g = {8, C128 ? 3 : 8, 0};
+    else if (NH == 1 && K == 2) // the other target is exchanged by shuffles
+        g = {2, C128 ? 3 : 8, 1};
+    else if (NH == 1)
+        g = {1, C128 ? 4 : 8, 1};
+    else
+        g = {1, C128 ? 3 : 6, 1};
+    if (state_bytes < (512ull << 20)) {
         g.wg = 0;
         g.xcd = 0;
     }
@@ -315,15 +310,20 @@ static hipError_t apply_gate_t(void* psi, int n, int K, const int* t, const doub
     const uint64_t cm_ins = cm & ~linemask;
     // lane bits: the lowest 6 positions not taken by inserted controls (or,
     // with the low-in-registers knob, by targets held in registers)
+    // With targets moved into registers, every other target at or above the
+    // line is kept out of the lane bits too (it would otherwise slide into
+    // the six lane positions and be exchanged by shuffles).
     const int lowhigh = (int)tun(T_GATE_LOW_HIGH);
-    uint64_t reg_low = 0;
+    uint64_t reg_low = 0, not_lane = 0;
     if (lowhigh)
-        for (int j = 0; j < K; ++j)
+        for (int j = 0; j < K; ++j) {
             if (t[j] < 6 && (lowhigh == 2 || t[j] >= LINE_BITS)) reg_low |= 1ull << t[j];
+            if (lowhigh == 2 || t[j] >= LINE_BITS) not_lane |= 1ull << t[j];
+        }
     int lanepos[6];
     int nl = 0;
     for (int q = 0; q < 64 && nl < 6; ++q)
-        if (!(((cm_ins | reg_low) >> q) & 1)) lanepos[nl++] = q;
+        if (!(((cm_ins | not_lane) >> q) & 1)) lanepos[nl++] = q;
     uint64_t himask = 0;
     int nh = 0;
     uint32_t lowmask = 0;
