@@ -7,7 +7,12 @@ Workloads (``--workload``), each printing ONE JSON line:
   (16 GiB) -- one seeded U3 on every target 0..29, then seeded Haar-random 4x4
   unitaries on adjacent pairs (t, t+1) and far pairs (t, t+15), each once
   uncontrolled and once with one control: 118 gates, one launch each, state
-  resident in HBM.  Value: amplitude-updates/s.
+  resident in HBM.  Value: amplitude-updates/s.  The same line carries, on
+  the same state, the diagonal-gate sweep, the read-only passes (norm,
+  marginals, expectation values, sampling) and the in-place ceiling probe,
+  then compact batch (1024 circuits: fused complex64 vs per-gate complex128)
+  and serving (p50/p99 latency, circuits/s) legs, and the oracle on the
+  host's cores with one and with all threads.
 - ``circuits``: 32-qubit random chain circuit (depth 20) and full QFT of a
   random basis state, complex64 in tile passes (register segments with fused
   register blocks), beside complex64 with 5-qubit fused blocks on matrix
@@ -311,6 +316,43 @@ def ceiling_probe(qs, s, reps=3):
                     f"{reps} per schedule"}
 
 
+def reductions(qs, s, n, S, reps=3, seed=17):
+    """The read-only passes over the same state: squared norm, marginal
+    probabilities over low / high / spread qubit sets, Pauli-string
+    expectation values, and sampling (chunk sums, then one wave per shot).
+    Kernel time from the library's HIP events; GB/s of the bytes each pass
+    reads (S x 2^n per full pass, S x 4096 per shot)."""
+    rng = np.random.default_rng(seed)
+    cases = [("norm", lambda: qs.qs_norm(s.h)),
+             ("probs_low_3", lambda: qs.qs_probabilities(s.h, [0, 1, 2])),
+             ("probs_high_3", lambda: qs.qs_probabilities(s.h, [n - 3, n - 2, n - 1])),
+             ("probs_spread_10", lambda: qs.qs_probabilities(s.h, list(range(0, n, 3))[:10])),
+             ("probs_low_16", lambda: qs.qs_probabilities(s.h, list(range(16)))),
+             ("expect_z_all", lambda: qs.qs_expect_pauli(s.h, 0, (1 << n) - 1)),
+             ("expect_xz_mixed", lambda: qs.qs_expect_pauli(s.h, 0x2AAAAAAA & ((1 << n) - 1),
+                                                           0x15555555 & ((1 << n) - 1))),
+             ("sample_100k", lambda: qs.qs_sample(s.h, rng.random(100000)))]
+    out = {}
+    for name, fn in cases:
+        fn()  # warm (scratch sized)
+        qs.qs_trace_enable(s.h, True)
+        for _ in range(reps):
+            fn()
+        recs = qs.qs_trace_read(s.h, 1 << 10)
+        qs.qs_trace_enable(s.h, False)
+        per = {}
+        for r in recs:
+            k = qs.KIND_NAMES[int(r["kind"])]
+            d = per.setdefault(k, {"ms": [], "bytes": int(r["bytes"])})
+            d["ms"].append(float(r["ms"]))
+        out[name] = {k: {"ms": float(np.median(d["ms"])), "bytes": d["bytes"],
+                         "gbs": d["bytes"] / float(np.median(d["ms"])) / 1e6} for k, d in per.items()}
+    full = [v["reduce"]["gbs"] for v in out.values() if "reduce" in v]
+    return {"cases": out, "min_gbs_full_pass": min(full), "frac_min": min(full) / PEAK_HBM_GBS,
+            "note": f"n={n} complex128 state, median of {reps}; kind 'reduce' reads the whole state once, "
+                    "'sample' reads 4096 amplitudes per shot"}
+
+
 def per_target_table(gates, recs, steps):
     """GB/s per target index (median over the timed steps) for each gate of
     the sweep: 1q by target; 2q by first target, adjacent (t, t+1) and far
@@ -371,6 +413,7 @@ def run_sweep(a, qs, torch, W):
     qs.qs_trace_enable(s.h, False)
     norm = s.norm()
     diag = diag_sweep(qs, s, n, S) if a.mode == "pergate" else None
+    reds = reductions(qs, s, n, S) if a.mode == "pergate" else None
     ceiling = ceiling_probe(qs, s)
     s.close()
     kinds = _kinds(qs, recs)
@@ -397,6 +440,7 @@ def run_sweep(a, qs, torch, W):
         "per_target_gbs": per_target,
         "inplace_ceiling": ceiling,
         "diag_sweep": diag,
+        "reductions": reds,
     })
     del psi
     torch.cuda.empty_cache()

@@ -6,7 +6,10 @@
 //   pass 1: the 2^(n-m) "rest" indices of each outcome o are cut into chunks of
 //           CH consecutive rest indices; block (o, chunk) sums its chunk (each
 //           lane a fixed strided subsequence, then a fixed LDS tree) into
-//           part[o * nch + chunk];
+//           part[o * nch + chunk].  Blocks are numbered chunk-major (the 2^m
+//           outcomes of one chunk are consecutive blocks), so blocks that run
+//           together read the same lines when measured qubits lie inside a
+//           line, and HBM sees each line once;
 //   pass 2: one block per outcome sums part[o * nch .. + nch) the same way.
 #include <mutex>
 
@@ -55,8 +58,9 @@ k_prob_chunks(const V* __restrict__ psi, uint64_t rest_per_outcome, uint64_t ch,
               InsertPlan ip, MeasQubits mq, double* __restrict__ part)
 {
     __shared__ double sh[kRT];
-    const uint64_t blk = blockIdx.x;
-    const uint64_t o = blk / nch, chunk = blk % nch;
+    const uint64_t nout = (uint64_t)1 << mq.m;
+    const uint64_t o = blockIdx.x % nout, chunk = blockIdx.x / nout;
+    const uint64_t blk = o * nch + chunk;
     uint64_t obits = 0;
     for (int j = 0; j < mq.m; ++j)
         if ((o >> j) & 1) obits |= 1ull << mq.q[j];
