@@ -555,6 +555,9 @@ qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
  *                                         per CU, capped through unused LDS (0 = built-in rule
  *                                         for gates, no cap for the probe; 8 and more: no cap
  *                                         in effect)
+ *   diag_slots        [QS_DIAG_SLOTS]     diagonal kernel: slots per lane (1, 2, 4 or 8; 0 =
+ *                                         built-in); gate_wg_per_cu and gate_xcd_swizzle apply
+ *                                         to the diagonal kernel too
  *   gate_low_in_regs  [QS_GATE_LOW_HIGH]  per-gate kernel: targets below bit 6 held in a lane's
  *                                         registers instead of exchanged by shuffles (0 none,
  *                                         1 = default: those at or above the 128-byte line,

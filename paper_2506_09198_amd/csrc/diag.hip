@@ -33,6 +33,7 @@ struct DiagArgs {
     uint64_t nblocks;   // counter chunks of 256 * PPL
     uint32_t fm_lo, fv_lo;
     int32_t slog;       // log2 of the slot spread
+    int32_t xcd;        // chunk order: 1 = each XCD a contiguous eighth (as the per-gate kernel)
     int32_t nfree;
     int32_t fpos[kDiagMaxFree];
     double tab[2 << kDiagMaxFree];
@@ -48,7 +49,8 @@ __global__ void __launch_bounds__(256) k_diag(typename CT<R>::V* __restrict__ ps
     __syncthreads();
     const uint64_t S = 1ull << a.slog;
     const uint64_t spb = S >> 8;
-    for (uint64_t b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
+    for (uint64_t bb = blockIdx.x; bb < a.nblocks; bb += gridDim.x) {
+        const uint64_t b = a.xcd ? (bb & 7) * (a.nblocks >> 3) + (bb >> 3) : bb;
         const uint64_t base = (b / spb) * (S * PPL) + (b % spb) * 256 + threadIdx.x;
         V x[PPL];
         uint64_t idx[PPL];
@@ -75,18 +77,48 @@ __global__ void __launch_bounds__(256) k_diag(typename CT<R>::V* __restrict__ ps
 }
 
 template <typename R, int PPL>
-void launch_diag_t(void* psi, DiagArgs& a, hipStream_t st)
+hipError_t launch_diag_t(void* psi, DiagArgs& a, int wg, int xcd, hipStream_t st)
 {
     using V = typename CT<R>::V;
     const int sl = (int)tun(T_DIAG_SLOG);
     a.slog = a.C >= ((1ull << sl) * PPL) ? sl : 8;
     a.nblocks = (a.C + 256 * PPL - 1) / (256 * PPL);
+    a.xcd = (xcd && a.nblocks % 8 == 0) ? 1 : 0;
     const uint64_t cap = (uint64_t)tun(T_GATE_GRID_CAP);
     const unsigned g = (unsigned)(a.nblocks < cap ? a.nblocks : cap);
-    if (a.C >= 64)
-        hipLaunchKernelGGL((k_diag<R, PPL, true>), dim3(g), dim3(256), 0, st, (V*)psi, a);
+    const size_t pad = pad_for_wg_per_cu(wg, sizeof(double) * (2 << kDiagMaxFree));
+    const bool nt = a.C >= 64;
+    hipError_t e = lds_optin(nt ? (const void*)k_diag<R, PPL, true> : (const void*)k_diag<R, PPL, false>, pad);
+    if (e != hipSuccess) return e;
+    if (nt)
+        hipLaunchKernelGGL((k_diag<R, PPL, true>), dim3(g), dim3(256), pad, st, (V*)psi, a);
     else
-        hipLaunchKernelGGL((k_diag<R, PPL, false>), dim3(g), dim3(256), 0, st, (V*)psi, a);
+        hipLaunchKernelGGL((k_diag<R, PPL, false>), dim3(g), dim3(256), pad, st, (V*)psi, a);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_diag_r(void* psi, DiagArgs& a, uint64_t state_bytes, hipStream_t st)
+{
+    // Memory schedule (the per-gate kernel's knobs apply).  Measured on
+    // MI355X at n=30 over CZ on neighbouring pairs and CP with random controls:
+    // each XCD walking its own contiguous eighth of the chunks (+3 % complex64,
+    // +18 % complex128, where pairs 1-64 MiB apart gain the most) and, for
+    // complex128, one slot per lane (the reads skip lines, so the streams are
+    // already many); unlike the dense per-gate kernel, capping occupancy only
+    // loses here.  States that fit the Infinity Cache keep workgroup order.
+    int ppl = (int)tun(T_DIAG_SLOTS), wg = 0, xcd = 1;
+    if (ppl == 0) ppl = sizeof(R) == 8 ? 1 : 4;
+    const int wg_k = (int)tun(T_GATE_WG_PER_CU), xcd_k = (int)tun(T_GATE_XCD);
+    if (state_bytes < (512ull << 20)) xcd = 0;
+    if (wg_k > 0) wg = wg_k;
+    if (xcd_k > 0) xcd = xcd_k - 1;
+    switch (ppl) {
+    case 1: return launch_diag_t<R, 1>(psi, a, wg, xcd, st);
+    case 2: return launch_diag_t<R, 2>(psi, a, wg, xcd, st);
+    case 8: return launch_diag_t<R, 8>(psi, a, wg, xcd, st);
+    default: return launch_diag_t<R, 4>(psi, a, wg, xcd, st);
+    }
 }
 
 } // namespace
@@ -186,11 +218,8 @@ hipError_t launch_diag(void* psi, int dt, const DiagPlan& p, hipStream_t st)
     a.nfree = p.nfree;
     for (int i = 0; i < p.nfree; ++i) a.fpos[i] = p.fpos[i];
     for (int i = 0; i < (2 << p.nfree); ++i) a.tab[i] = p.tab[i];
-    if (dt == QS_C128)
-        launch_diag_t<double, 4>(psi, a, st);
-    else
-        launch_diag_t<float, 4>(psi, a, st);
-    return hipGetLastError();
+    const uint64_t sb = (1ull << p.n) * amp_bytes(dt);
+    return dt == QS_C128 ? launch_diag_r<double>(psi, a, sb, st) : launch_diag_r<float>(psi, a, sb, st);
 }
 
 } // namespace qs

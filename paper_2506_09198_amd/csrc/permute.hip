@@ -76,6 +76,16 @@ __global__ void __launch_bounds__(256) k_bit_involution(V* __restrict__ psi, Inv
     }
 }
 
+template <typename V, int K>
+hipError_t launch_inv(V* psi, const InvArgs& a, unsigned g, int wg, hipStream_t st)
+{
+    const size_t pad = pad_for_wg_per_cu(wg, 2 * sizeof(V) << (2 * K)); // the two tiles in LDS
+    hipError_t e = lds_optin((const void*)k_bit_involution<V, K>, pad);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bit_involution<V, K>), dim3(g), dim3(256), pad, st, psi, a);
+    return hipGetLastError();
+}
+
 } // namespace
 
 uint64_t involution_moved(int n, const int* tau)
@@ -122,20 +132,14 @@ hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipSt
     // up to 2^20 workgroups (fewer with a lower gate_grid_cap); they loop over the tile pairs
     const uint64_t cap = std::min<uint64_t>(1ull << 20, (uint64_t)tun(T_GATE_GRID_CAP));
     const unsigned g = (unsigned)(a.ntiles < cap ? a.ntiles : cap);
-    if (dt == QS_C128) {
-        if (Kr == 4)
-            hipLaunchKernelGGL((k_bit_involution<double2, 4>), dim3(g), dim3(256), 0, st, (double2*)psi, a);
-        else
-            hipLaunchKernelGGL((k_bit_involution<double2, 5>), dim3(g), dim3(256), 0, st, (double2*)psi, a);
-    } else {
-        if (Kr == 4)
-            hipLaunchKernelGGL((k_bit_involution<float2, 4>), dim3(g), dim3(256), 0, st, (float2*)psi, a);
-        else if (Kr == 5)
-            hipLaunchKernelGGL((k_bit_involution<float2, 5>), dim3(g), dim3(256), 0, st, (float2*)psi, a);
-        else
-            hipLaunchKernelGGL((k_bit_involution<float2, 6>), dim3(g), dim3(256), 0, st, (float2*)psi, a);
-    }
-    return hipGetLastError();
+    // workgroups per CU: the per-gate kernel's occupancy knob applies (0 = no cap)
+    const int wg = (int)tun(T_GATE_WG_PER_CU);
+    if (dt == QS_C128)
+        return Kr == 4 ? launch_inv<double2, 4>((double2*)psi, a, g, wg, st)
+                       : launch_inv<double2, 5>((double2*)psi, a, g, wg, st);
+    if (Kr == 4) return launch_inv<float2, 4>((float2*)psi, a, g, wg, st);
+    if (Kr == 5) return launch_inv<float2, 5>((float2*)psi, a, g, wg, st);
+    return launch_inv<float2, 6>((float2*)psi, a, g, wg, st);
 }
 
 } // namespace qs

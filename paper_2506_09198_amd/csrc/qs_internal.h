@@ -110,6 +110,7 @@ enum Tun {
     T_GATE_WG_PER_CU,  // per-gate kernel and probe: workgroups per CU (0 rule; 8 and up: no cap in effect)
     T_GATE_LOW_HIGH,   // per-gate kernel: targets below bit 6 held in registers (1: at or above the
                        //   128-byte line bit, 2: all) instead of exchanged by shuffles
+    T_DIAG_SLOTS,      // diagonal kernel: slots per lane (0 = built-in: 4)
     T_COUNT
 };
 int64_t tun(Tun id);

@@ -3,14 +3,18 @@
 //
 // Order is fixed by construction, so a given (n, m, qubits) always sums the
 // same numbers in the same order, whatever the grid size:
-//   pass 1: the 2^(n-m) "rest" indices of each outcome o are cut into chunks of
-//           CH consecutive rest indices; block (o, chunk) sums its chunk (each
-//           lane a fixed strided subsequence, then a fixed LDS tree) into
-//           part[o * nch + chunk].  Blocks are numbered chunk-major (the 2^m
-//           outcomes of one chunk are consecutive blocks), so blocks that run
-//           together read the same lines when measured qubits lie inside a
-//           line, and HBM sees each line once;
+//   pass 1: measured qubits at bit 6 or above select, per block, one pattern
+//           oh of their bits; the remaining indices (measured low bits
+//           included) are cut into chunks of CH = 4096 x 2^(low measured)
+//           consecutive ones, which the block's lanes read contiguously (each
+//           lane a fixed strided subsequence, so its amplitudes all share the
+//           low six index bits: a lane belongs to one low-bit outcome).  A
+//           fixed LDS tree folds the lanes of each low outcome, and the block
+//           writes part[o * nch + chunk] for the 2^(low) outcomes o of oh.
+//           Blocks are numbered chunk-major (the patterns oh of one chunk are
+//           consecutive blocks);
 //   pass 2: one block per outcome sums part[o * nch .. + nch) the same way.
+#include <cstring>
 #include <mutex>
 
 #include "device_common.h"
@@ -34,9 +38,17 @@ void* g_scratch_dev[kMaxDevices] = {};
 constexpr int kRT = 256;        // threads per reduction block
 constexpr int kChunkLog2 = 12;  // CH = 4096 rest indices per block
 
+// Measured qubits split by position: those at bit 6 or above ("high") are
+// fixed per block (inserted into the counter), those below ("low") are lane
+// bits -- every amplitude a lane reads has the same low bits, so the lanes
+// read contiguous amplitudes and the block folds its lanes per low outcome.
 struct MeasQubits {
-    int32_t m;
-    int32_t q[24];
+    int32_t m, mh, nl;
+    uint32_t lmask;  // lane bits of the low measured qubits
+    int32_t hq[24];  // position of high measured qubit i
+    int32_t hj[24];  // its bit in the outcome index
+    int32_t lq[6];   // position (= lane bit) of low measured qubit i
+    int32_t lj[6];   // its bit in the outcome index
 };
 
 __device__ __forceinline__ double block_tree_sum(double v, double* sh)
@@ -58,15 +70,18 @@ k_prob_chunks(const V* __restrict__ psi, uint64_t rest_per_outcome, uint64_t ch,
               InsertPlan ip, MeasQubits mq, double* __restrict__ part)
 {
     __shared__ double sh[kRT];
-    const uint64_t nout = (uint64_t)1 << mq.m;
-    const uint64_t o = blockIdx.x % nout, chunk = blockIdx.x / nout;
-    const uint64_t blk = o * nch + chunk;
-    uint64_t obits = 0;
-    for (int j = 0; j < mq.m; ++j)
-        if ((o >> j) & 1) obits |= 1ull << mq.q[j];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t noh = (uint64_t)1 << mq.mh;
+    const uint64_t oh = blockIdx.x % noh, chunk = blockIdx.x / noh;
+    uint64_t obits = 0, ohout = 0; // high qubits: their index bits and outcome bits
+    for (int i = 0; i < mq.mh; ++i)
+        if ((oh >> i) & 1) {
+            obits |= 1ull << mq.hq[i];
+            ohout |= 1ull << mq.hj[i];
+        }
     double acc = 0.0;
     const uint64_t r0 = chunk * ch;
-    for (uint64_t r = threadIdx.x; r < ch; r += kRT) {
+    for (uint64_t r = tid; r < ch; r += kRT) {
         const uint64_t rr = r0 + r;
         if (rr < rest_per_outcome) {
             const V a = psi[ins_bits(rr, ip) | obits];
@@ -74,8 +89,23 @@ k_prob_chunks(const V* __restrict__ psi, uint64_t rest_per_outcome, uint64_t ch,
             acc += x * x + y * y;
         }
     }
-    const double s = block_tree_sum(acc, sh);
-    if (threadIdx.x == 0) part[blk] = s;
+    // Fold the other thread bits, highest first, so thread t with those bits
+    // zero holds the sum over the threads sharing its low-qubit lane bits.
+    sh[tid] = acc;
+    uint32_t done = 0;
+    for (int b = 7; b >= 0; --b) {
+        if ((mq.lmask >> b) & 1) continue;
+        __syncthreads();
+        if (!(tid & (done | (1u << b)))) sh[tid] += sh[tid | (1u << b)];
+        done |= 1u << b;
+    }
+    __syncthreads();
+    if (!(tid & done)) {
+        uint64_t o = ohout;
+        for (int i = 0; i < mq.nl; ++i)
+            if ((tid >> mq.lq[i]) & 1) o |= 1ull << mq.lj[i];
+        part[o * nch + chunk] = sh[tid];
+    }
 }
 
 __global__ void __launch_bounds__(kRT)
@@ -90,7 +120,7 @@ k_prob_final(const double* __restrict__ part, uint64_t nch, double* __restrict__
 }
 
 // Pauli-string expectation, pass 1.  Terms (x != 0): pairs (k0, k1 = k0 ^ x)
-// with bit b = lowest bit of x clear in k0, term = conj(psi_k1) psi_k0 s(k0)
+// with bit b = highest bit of x clear in k0, term = conj(psi_k1) psi_k0 s(k0)
 // + conj(psi_k0) psi_k1 s(k1), s(k) = (-1)^{|k & z|}; (x == 0): |psi_k|^2 s(k).
 // Chunks of CH consecutive terms per block, fixed lane order and tree;
 // part[chunk] = real sum, part[nch + chunk] = imaginary sum.
@@ -192,8 +222,10 @@ k_sample_chunk(const V* __restrict__ psi, uint32_t csize, const SampleReq* __res
 hipError_t launch_pauli_expect(const void* psi, int dt, int n, uint64_t x, uint64_t z, double* part,
                                double* dev_out, hipStream_t st)
 {
+    // pairs (k0, k0 ^ x) with the highest bit of x clear in k0: k0 runs over
+    // whole lines and k0 ^ x permutes within lines, so both reads coalesce
     const uint64_t nterms = x == 0 ? (1ull << n) : (1ull << (n - 1));
-    const int b = x == 0 ? 0 : __builtin_ctzll(x);
+    const int b = x == 0 ? 0 : 63 - __builtin_clzll(x);
     const uint64_t ch = 1ull << kChunkLog2;
     const uint64_t nch = (nterms + ch - 1) / ch;
     if (nch > 0x7fffffffull) return hipErrorInvalidValue;
@@ -257,18 +289,28 @@ hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubit
 {
     if (m > 24) return hipErrorInvalidValue;
     MeasQubits mq;
+    std::memset(&mq, 0, sizeof mq);
     mq.m = m;
-    uint64_t mask = 0;
+    uint64_t mask = 0; // high measured qubits, inserted into the counter
     for (int j = 0; j < m; ++j) {
-        mq.q[j] = qubits[j];
-        mask |= 1ull << qubits[j];
+        if (qubits[j] >= 6) {
+            mq.hq[mq.mh] = qubits[j];
+            mq.hj[mq.mh++] = j;
+            mask |= 1ull << qubits[j];
+        } else {
+            mq.lq[mq.nl] = qubits[j];
+            mq.lj[mq.nl++] = j;
+            mq.lmask |= 1u << qubits[j];
+        }
     }
     InsertPlan ip = make_insert_plan(mask);
-    const int rest = n - m;
-    const int chl = rest < kChunkLog2 ? rest : kChunkLog2;
+    // a block reads 4096 x 2^nl rest indices (or all of them) and writes one
+    // partial per low outcome: 2^m x nch partials, as reduce_scratch_doubles
+    const int rest = n - mq.mh;
+    const int chl = rest < kChunkLog2 + mq.nl ? rest : kChunkLog2 + mq.nl;
     const uint64_t ch = 1ull << chl;
     const uint64_t nch = 1ull << (rest - chl);
-    const uint64_t nblk = (1ull << m) * nch;
+    const uint64_t nblk = (1ull << mq.mh) * nch;
     if (nblk > 0x7fffffffull) return hipErrorInvalidValue;
     if (dt == QS_C128)
         hipLaunchKernelGGL(k_prob_chunks<double2>, dim3((unsigned)nblk), dim3(kRT), 0, st, (const double2*)psi,

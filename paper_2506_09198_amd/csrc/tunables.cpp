@@ -41,6 +41,7 @@ const TunDef kTun[T_COUNT] = {
     {"gate_xcd_swizzle", "QS_GATE_XCD", 0, 0, 2},
     {"gate_wg_per_cu", "QS_GATE_WG_PER_CU", 0, 0, 32},
     {"gate_low_in_regs", "QS_GATE_LOW_HIGH", 1, 0, 2},
+    {"diag_slots", "QS_DIAG_SLOTS", 0, 0, 8},
 };
 
 std::atomic<int64_t> g_val[T_COUNT];
