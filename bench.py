@@ -45,6 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector / matrix, published
 
 
 def _args():
@@ -61,7 +62,8 @@ def _args():
                    help="circuits/batch: skip the per-gate complex128 comparison runs")
     p.add_argument("--no-tune", action="store_true", help="batch: skip the autotuner (library defaults)")
     p.add_argument("--only-head", action="store_true",
-                   help="circuits: run only the complex64 tile-pass variant (no comparisons, e.g. under a profiler)")
+                   help="circuits / batch: run only the complex64 tile-pass variant / fused complex64 batch (no "
+                        "comparisons, e.g. under a profiler)")
     p.add_argument("--qps-sweep", action="store_true", help="serve: also run 0.3x, 0.5x and 1.0x of saturation")
     p.add_argument("--big-blocks", type=int, default=256,
                    help="serve: workgroup cap of the large circuit's passes (0 = library default), which "
@@ -70,6 +72,8 @@ def _args():
     p.add_argument("--no-side", action="store_true",
                    help="sweep: skip the compact batch and serving legs that follow the timed sweep")
     p.add_argument("--cpu-n", type=int, default=0, help="qubits of the oracle sample (0 = workload default)")
+    p.add_argument("--oracle-n", type=int, default=28,
+                   help="circuits: qubits of the chain circuit checked against the host oracle on every GPU path")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run 3 torch copies of 4 GiB (reference for HBM byte counters) and exit")
     return p.parse_args()
@@ -605,11 +609,62 @@ def run_circuits(a, qs, torch, W):
         ms = sum(r["ms"] for r in res[name].values())
         res[name]["total_ms"] = ms
         res[name]["time_vs_head"] = ms / ms64
-    out.update({"variants": res, "roofline": _roofline(kinds),
+    rl = _roofline(kinds)
+    fpa = tile_flops_per_amp()
+    if fpa and rl["kernel"] == "tile":
+        # the pass is bound by FP64 arithmetic issue: its executed FP64 flops per
+        # amplitude (rocprofv3 counters of the same circuits) against 78.6 TF
+        D = kinds["tile"]
+        tf = fpa * (1 << n) / (D["avg_ms"] * 1e-3) / 1e12
+        rl = {"bound": "alu", "kernel": "tile", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+              "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
+              "flops_per_amp_per_pass": fpa, "hbm_gbs_algorithmic": rl["achieved"],
+              "hbm_frac": rl["achieved"] / PEAK_HBM_GBS,
+              "note": "FP64 flops executed per amplitude per pass from profiles/tile_circuits_n30_c64_counters.txt "
+                      "(2 x FP64 FMA + FP64 MUL, the same two circuits at n=30)"}
+    out.update({"variants": res, "roofline": rl,
                 "kernels": {k: {"launches": d["launches"], "avg_ms": round(d["avg_ms"], 4), "gbs": round(d["gbs"], 1)}
                             for k, d in kinds.items()}})
+    if not a.only_head:
+        out["oracle_check"] = circuits_vs_oracle(a, qs, W, min(n, a.oracle_n))
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline_circuits(a.cpu_n or 25)
+    return out
+
+
+def tile_flops_per_amp():
+    """FP64 flops per amplitude per tile pass of the chain circuit + QFT, from
+    the committed rocprofv3 counter summary (None when it is missing)."""
+    path = os.path.join(ROOT, "profiles", "tile_circuits_n30_c64_counters.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if "flop per pass" in line:
+            return float(line.split()[0]) / float(1 << 30)
+    return None
+
+
+def circuits_vs_oracle(a, qs, W, n):
+    """The depth-20 chain circuit at n qubits (the largest the host oracle
+    finishes in about a minute) on every GPU path, each against the FP64
+    oracle run on the host: max |psi - psi_oracle| and fidelity
+    |<psi_oracle|psi>|^2 with psi as computed (not renormalised)."""
+    import oracle
+
+    c = W.rqc_chain(n, 20, 5)
+    ops, mats = c.arrays()
+    t0 = time.perf_counter()
+    ref = oracle.run_circuit(c)
+    t_or = time.perf_counter() - t0
+    out = {"n": n, "gates": len(ops), "oracle_s": t_or, "oracle_threads": oracle.num_threads()}
+    for name, dt, mode, fk in (("c64_tiles", qs.QS_C64, 0, 0), ("c64_mfma5", qs.QS_C64, 0, 5),
+                               ("c128_tiles", qs.QS_C128, 0, 0), ("c128_pergate", qs.QS_C128, 1, 0)):
+        with qs.State.create(n, dt) as s:
+            s.run(ops, mats, mode=mode, fuse_k=fk)
+            got = s.download().astype(np.complex128)
+        out[name] = {"fidelity": float(abs(np.vdot(ref, got)) ** 2), "max_abs_err": float(np.max(np.abs(got - ref))),
+                     "norm2_minus_1": float(np.vdot(got, got).real - 1.0)}
+        del got
     return out
 
 
@@ -689,6 +744,11 @@ def run_batch(a, qs, torch, W):
         emax = max(emax, float(np.max(np.abs(got - want))))
     r["closed_form_check"] = {"circuits": len(pick), "min_fidelity": fmin, "max_abs_err": emax}
     qs.qs_batch_release(b64)
+    if a.only_head:  # one fused complex64 batch only (e.g. under a profiler)
+        return _header(a, "batched circuits/s", r["circuits_per_s"], "circuits/s", r["end_to_end_ms"], "f64",
+                       "synthetic (seeded mix of chain circuits, QFTs and Grover searches)",
+                       {"workload": f"{count} circuits, fused complex64 batch only", "circuits": count}) | {
+                           "variants": res}
     # the same batch replayed from its HIP graph: device work only (planned and uploaded once)
     b = qs.qs_batch_submit(arrs, dtype=qs.QS_C64, mode=0, graph=1, **tuned)
     qs.qs_batch_wait(b)
@@ -734,7 +794,9 @@ def run_batch(a, qs, torch, W):
     out.update({"tuning": {"sample": 256, "seconds": tune_s, "chosen": tuned, "candidates": tune_rows},
                 "variants": res, "roofline": {
         "bound": "hbm", "kernel": "all batch launches (aggregate)", "achieved": ach, "peak": PEAK_HBM_GBS,
-        "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
+        "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": measured_traffic("batch", f"batch_{count}_c64", BATCH_SRCS),
+        "traffic_unit": "HBM bytes per batch (rocprofv3 FETCH_SIZE+WRITE_SIZE over every batch kernel, copy-calibrated)",
+        "algorithmic_bytes": alg,
         "note": "states of n<=22 (<=32 MiB) stay in L2/Infinity Cache, so HBM is a loose roof here"}})
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline_mix(circs)
@@ -884,6 +946,8 @@ def run_serve(a, qs, torch, W):
 
 GATE_SRCS = ("paper_2506_09198_amd/csrc/gates.hip", "paper_2506_09198_amd/csrc/device_common.h")
 DIAG_SRCS = ("paper_2506_09198_amd/csrc/diag.hip", "paper_2506_09198_amd/csrc/device_common.h")
+BATCH_SRCS = ("paper_2506_09198_amd/csrc/tile_batch.hip", "paper_2506_09198_amd/csrc/tile_device.h",
+              "paper_2506_09198_amd/csrc/planner.cpp", "paper_2506_09198_amd/csrc/batch.cpp")
 
 
 def measured_traffic(kernel_class: str, tag: str, srcs=GATE_SRCS):
