@@ -111,6 +111,7 @@ enum Tun {
     T_GATE_LOW_HIGH,   // per-gate kernel: targets below bit 6 held in registers (1: at or above the
                        //   128-byte line bit, 2: all) instead of exchanged by shuffles
     T_DIAG_SLOTS,      // diagonal kernel: slots per lane (0 = built-in: 4)
+    T_TILE_W4,         // lean 2^11 tile passes held to 128 VGPRs (4 waves per SIMD)
     T_COUNT
 };
 int64_t tun(Tun id);

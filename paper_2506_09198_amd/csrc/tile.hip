@@ -6,9 +6,9 @@ namespace qs {
 namespace {
 
 template <typename R, int M, bool FULL>
-__global__ void __launch_bounds__(256)
-k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
-       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
+__device__ __forceinline__ void tile_pass(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, const QList& ql,
+                                          const InsertPlan& ipQ, const TileOp* __restrict__ ops, int nops,
+                                          const double* __restrict__ mats, int nt)
 {
     using V = typename CT<R>::V;
     constexpr uint32_t E = 1u << M;
@@ -25,6 +25,25 @@ k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPla
         tile_store<R, M>(psi, base, ql.L, hoff, tile, nt);
         __syncthreads();
     }
+}
+
+template <typename R, int M, bool FULL>
+__global__ void __launch_bounds__(256)
+k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
+       const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
+{
+    tile_pass<R, M, FULL>(psi, ntiles, ql, ipQ, ops, nops, mats, nt);
+}
+
+// The same pass held to 128 VGPRs (4 waves per SIMD instead of 3): for tiles
+// of 2^11 the compiler then keeps a few values in scratch (12 bytes per lane
+// for the lean kernel); larger tiles would spill heavily and keep k_tile.
+template <typename R, int M, bool FULL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_tile_w4(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
+          const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
+{
+    tile_pass<R, M, FULL>(psi, ntiles, ql, ipQ, ops, nops, mats, nt);
 }
 
 template <typename R, int M>
@@ -50,6 +69,8 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
         const size_t lim = lds_max > 163840 ? 163840 : lds_max;
         hipError_t e = lds_optin((const void*)k_tile<R, M, false>, lim);
         if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, true>, lim);
+        if constexpr (M == 11)
+            if (e == hipSuccess) e = lds_optin((const void*)k_tile_w4<R, M, false>, lim);
         if (e != hipSuccess) return e;
     }
     if (lds > 163840) return hipErrorInvalidValue;
@@ -64,12 +85,21 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     const int nt = (tun(T_NT) && pass.L >= line_bits) ? 1 : 0;
     // the full variant only when the pass needs it (k >= 3 ops, fused
     // blocks or ops outside segments would otherwise cost every pass registers)
-    if (ops_need_full(pass.ops.data(), pass.ops.size(), pass.m))
+    const bool full = ops_need_full(pass.ops.data(), pass.ops.size(), pass.m);
+    if (full) {
         hipLaunchKernelGGL((k_tile<R, M, true>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
                            (int)pass.ops.size(), (const double*)dmats, nt);
-    else
-        hipLaunchKernelGGL((k_tile<R, M, false>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                           (int)pass.ops.size(), (const double*)dmats, nt);
+        return hipGetLastError();
+    }
+    if constexpr (M == 11) {
+        if (tun(T_TILE_W4)) {
+            hipLaunchKernelGGL((k_tile_w4<R, M, false>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
+                               (int)pass.ops.size(), (const double*)dmats, nt);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_tile<R, M, false>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
+                       (int)pass.ops.size(), (const double*)dmats, nt);
     return hipGetLastError();
 }
 

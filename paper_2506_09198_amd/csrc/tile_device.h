@@ -148,20 +148,29 @@ struct Seg {
     static constexpr int LI = 1 << (TB - 8);                    // loop steps
 };
 
+// Keep `old` where this thread's controls fail (plain double selects: a
+// select of double2 values is lowered through a per-lane indexed stack copy).
+__device__ __forceinline__ double2 keep_if(bool tok, double2 nw, double2 old)
+{
+    double2 r;
+    r.x = tok ? nw.x : old.x;
+    r.y = tok ? nw.y : old.y;
+    return r;
+}
+
 // Dense 1q op on register bit B.  With CTL the op has controls: rcm/rcv are
 // control bits at register positions (uniform, tested per pair) and tok
-// says whether this thread's own bits pass the others (if not it applies the
-// identity).  Without CTL the loop has no branch at all.
+// says whether this thread's own bits pass the others (if not its values
+// are kept bit for bit).  The matrix stays uniform either way (scalar
+// operands), so controls cost a select per result, not per-lane matrices.
+// Without CTL the loop has no branch at all.
 template <int NR, int B, bool CTL>
 __device__ __forceinline__ void seg_1q(double2 (&reg)[NR], const uint32_t (&roff)[NR], uint32_t rcm, uint32_t rcv,
                                        bool tok, const double* __restrict__ u)
 {
     double m[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const double id = (i == 0 || i == 6) ? 1.0 : 0.0;
-        m[i] = CTL ? (tok ? u[i] : id) : u[i];
-    }
+    for (int i = 0; i < 8; ++i) m[i] = u[i];
     constexpr int S = 1 << B;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
@@ -169,8 +178,10 @@ __device__ __forceinline__ void seg_1q(double2 (&reg)[NR], const uint32_t (&roff
         if constexpr (CTL)
             if ((roff[j] & rcm) != rcv) continue;
         const double2 a = reg[j], b = reg[j + S];
-        reg[j] = cmad2<double2, double>(m[0], m[1], a, m[2], m[3], b);
-        reg[j + S] = cmad2<double2, double>(m[4], m[5], a, m[6], m[7], b);
+        const double2 na = cmad2<double2, double>(m[0], m[1], a, m[2], m[3], b);
+        const double2 nb = cmad2<double2, double>(m[4], m[5], a, m[6], m[7], b);
+        reg[j] = CTL ? keep_if(tok, na, a) : na;
+        reg[j + S] = CTL ? keep_if(tok, nb, b) : nb;
     }
 }
 
@@ -188,21 +199,16 @@ __device__ __forceinline__ void seg_2q(double2 (&reg)[NR], const uint32_t (&roff
         double2 o[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            double m[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const double id = ((i & 1) == 0 && (i >> 1) == r) ? 1.0 : 0.0;
-                m[i] = CTL ? (tok ? u[8 * r + i] : id) : u[8 * r + i];
-            }
+            const double* m = u + 8 * r;
             const double2 s1 = cmad2<double2, double>(m[0], m[1], v0, m[2], m[3], v1);
             const double2 s2 = cmad2<double2, double>(m[4], m[5], v2, m[6], m[7], v3);
             o[r].x = s1.x + s2.x;
             o[r].y = s1.y + s2.y;
         }
-        reg[j] = o[0];
-        reg[j + S0] = o[1];
-        reg[j + S1] = o[2];
-        reg[j + S0 + S1] = o[3];
+        reg[j] = CTL ? keep_if(tok, o[0], v0) : o[0];
+        reg[j + S0] = CTL ? keep_if(tok, o[1], v1) : o[1];
+        reg[j + S1] = CTL ? keep_if(tok, o[2], v2) : o[2];
+        reg[j + S0 + S1] = CTL ? keep_if(tok, o[3], v3) : o[3];
     }
 }
 
@@ -466,23 +472,40 @@ __device__ __forceinline__ void run_segment(typename CT<R>::V* tile, uint64_t ba
             if ((j >> b) & 1) o |= 1u << rp[b];
         roff[j] = o;
     }
-    const uint32_t freem = ((1u << M) - 1) & ~rmask;
-    for (int li = 0; li < S::LI; ++li) {
-        uint32_t src = (uint32_t)tid | ((uint32_t)li << 8), eb = 0;
-        for (int b = 0; b < M; ++b)
-            if ((freem >> b) & 1) {
-                eb |= (src & 1u) << b;
-                src >>= 1;
+    // The swizzle is linear over XOR, and eb and roff[j] share no bits, so
+    // swz(eb | roff[j]) = swz(eb) ^ swz(roff[j]): the register offsets are
+    // swizzled once per segment (uniform), each element address is one XOR.
+    uint32_t sroff[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) sroff[j] = QS_SW(roff[j]);
+    int rs[RR]; // register positions, ascending, for zero insertion
+#pragma unroll
+    for (int b = 0; b < RR; ++b) rs[b] = rp[b];
+#pragma unroll
+    for (int b = 1; b < RR; ++b)
+#pragma unroll
+        for (int c = RR - 1; c >= b; --c)
+            if (rs[c - 1] > rs[c]) {
+                const int t = rs[c - 1];
+                rs[c - 1] = rs[c];
+                rs[c] = t;
             }
+    for (int li = 0; li < S::LI; ++li) {
+        // the thread's element bits: tid | li << 8 with zeros inserted at the
+        // register positions (ascending)
+        uint32_t eb = (uint32_t)tid | ((uint32_t)li << 8);
+#pragma unroll
+        for (int b = 0; b < RR; ++b) eb = ins0_32(eb, rs[b]);
+        const uint32_t seb = QS_SW(eb);
         double2 reg[NR];
 #pragma unroll
-        for (int j = 0; j < NR; ++j) reg[j] = ld2(tile[QS_SW(eb | roff[j])]);
+        for (int j = 0; j < NR; ++j) reg[j] = ld2(tile[seb ^ sroff[j]]);
         for (int o = 1; o <= nmem; ++o) {
             const TileOp& d = hdr[o];
             if ((base & d.gcm) == d.gcv) seg_op<RR, NR>(reg, roff, rmask, eb, d, base, mats);
         }
 #pragma unroll
-        for (int j = 0; j < NR; ++j) tile[QS_SW(eb | roff[j])] = st2<V>(reg[j]);
+        for (int j = 0; j < NR; ++j) tile[seb ^ sroff[j]] = st2<V>(reg[j]);
     }
 }
 
@@ -497,6 +520,8 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
     constexpr uint32_t E = 1u << M;
     constexpr int PER = (E + 255) / 256; // tile elements per lane
     const int tid = threadIdx.x;
+    // element e = tid + 256 s sits at swz(tid) ^ swz(256 s) (the swizzle is linear over XOR)
+    const uint32_t stid = QS_SW((uint32_t)tid);
     for (int o = 0; o < nops; ++o) {
         const TileOp& d = ops[o];
         const int kind = d.kind;
@@ -644,7 +669,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                     const uint32_t e = tid + 256 * s;
                     if (E >= 256 || e < E) {
                         const bool one = (e >> abit) & 1;
-                        tile[QS_SW(e)] = st2<V>(cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, ld2(tile[QS_SW(e)])));
+                        tile[(stid ^ QS_SW(256u * s))] = st2<V>(cmul<double2, double>(one ? a1r : a0r, one ? a1i : a0i, ld2(tile[(stid ^ QS_SW(256u * s))])));
                     }
                 }
                 abit = -1;
@@ -691,7 +716,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                         const uint32_t e = tid + 256 * s;
                         if ((E >= 256 || e < E) && ((e >> cb) & 1) == cv) {
                             const bool one = (e >> tb) & 1;
-                            tile[QS_SW(e)] = st2<V>(cmul<double2, double>(one ? f1r : f0r, one ? f1i : f0i, ld2(tile[QS_SW(e)])));
+                            tile[(stid ^ QS_SW(256u * s))] = st2<V>(cmul<double2, double>(one ? f1r : f0r, one ? f1i : f0i, ld2(tile[(stid ^ QS_SW(256u * s))])));
                         }
                     }
                 } else {
@@ -704,7 +729,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                             uint32_t idx = gidx;
                             for (int j = 0; j < g.k; ++j)
                                 if (g.lp[j] >= 0) idx |= ((e >> g.lp[j]) & 1) << j;
-                            tile[QS_SW(e)] = st2<V>(cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], ld2(tile[QS_SW(e)])));
+                            tile[(stid ^ QS_SW(256u * s))] = st2<V>(cmul<double2, double>(dd[2 * idx], dd[2 * idx + 1], ld2(tile[(stid ^ QS_SW(256u * s))])));
                         }
                     }
                 }
@@ -718,7 +743,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
 #pragma unroll 4
                 for (int s = 0; s < PER; ++s) {
                     const uint32_t e = tid + 256 * s;
-                    if (E >= 256 || e < E) tile[QS_SW(e)] = st2<V>(cmul<double2, double>(cr, ci, ld2(tile[QS_SW(e)])));
+                    if (E >= 256 || e < E) tile[(stid ^ QS_SW(256u * s))] = st2<V>(cmul<double2, double>(cr, ci, ld2(tile[(stid ^ QS_SW(256u * s))])));
                 }
             }
             o = o2 - 1;
@@ -749,6 +774,8 @@ __device__ __forceinline__ void tile_load(const typename CT<R>::V* __restrict__ 
             ry[s] = v.y;
         }
     }
+    // swz(tid + 256 s) = swz(tid) ^ swz(256 s): the swizzle is linear over XOR
+    const uint32_t st = QS_SW((uint32_t)tid);
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
         const uint32_t e = tid + 256 * s;
@@ -756,7 +783,7 @@ __device__ __forceinline__ void tile_load(const typename CT<R>::V* __restrict__ 
             V v;
             v.x = rx[s];
             v.y = ry[s];
-            tile[QS_SW(e)] = v;
+            tile[st ^ QS_SW(256u * s)] = v;
         }
     }
 }
@@ -770,15 +797,17 @@ __device__ __forceinline__ void tile_store(typename CT<R>::V* __restrict__ psi, 
     constexpr int PER = (E + 255) / 256;
     const uint32_t lowm = (1u << L) - 1;
     const int tid = threadIdx.x;
+    const uint32_t st = QS_SW((uint32_t)tid); // as in tile_load
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
         const uint32_t e = tid + 256 * s;
         if (e < E) {
             V* a = psi + (base | (e & lowm) | ((uint64_t)hoff[e >> L] << L));
+            const V v = tile[st ^ QS_SW(256u * s)];
             if (nt)
-                gst<true>(a, tile[QS_SW(e)]);
+                gst<true>(a, v);
             else
-                gst<false>(a, tile[QS_SW(e)]);
+                gst<false>(a, v);
         }
     }
 }
