@@ -546,7 +546,8 @@ def run_circuits(a, qs, torch, W):
     head = "c64_tiles"
     variants = [(head, qs.QS_C64, 0, 0, a.steps, a.warmup)]
     if not a.only_head:
-        variants += [("c64_mfma5", qs.QS_C64, 0, 5, 1, 1), ("c128_tiles", qs.QS_C128, 0, 0, 1, 1)]
+        variants += [("c64_mfma5", qs.QS_C64, 0, 5, 1, 1), ("c128_tiles", qs.QS_C128, 0, 0, 1, 1),
+                     ("c128_mfma5", qs.QS_C128, 0, 5, 1, 1)]
     if not a.no_baselines and not a.only_head:
         variants.append(("c128_pergate", qs.QS_C128, 1, 0, 1, 0))
     res, traces, states = {}, {}, {}
@@ -578,6 +579,13 @@ def run_circuits(a, qs, torch, W):
             _log(f"circuits {name} {k}: {el * 1e3:.1f} ms")
             if name in (head, "c64_mfma5", "c128_tiles") and not a.only_head:
                 states.setdefault(k, {})[name] = psi
+            elif name == "c128_mfma5":  # both complex128 forms against each other
+                ref = states[k].pop("c128_tiles")
+                res[name][k]["max_abs_err_vs_c128_tiles"] = max(
+                    float((psi[i:i + (1 << 26)] - ref[i:i + (1 << 26)]).abs().max().item())
+                    for i in range(0, psi.numel(), 1 << 26))
+                del ref, psi
+                torch.cuda.empty_cache()
             else:
                 del psi
         torch.cuda.synchronize()
@@ -593,7 +601,8 @@ def run_circuits(a, qs, torch, W):
                 want = np.exp(2j * np.pi * ((x * y.astype(object)) % N).astype(np.float64) / N) / math.sqrt(N)
                 got = states["qft"]["c128_tiles"][torch.from_numpy(y).cuda()].cpu().numpy()
                 res["c128_tiles"]["qft"]["max_abs_err_closed_form_sampled"] = float(np.max(np.abs(got - want)))
-            states.clear()
+            for k in work:  # the complex128 tile results stay for the matrix-core form
+                states[k] = {"c128_tiles": states[k]["c128_tiles"]}
             torch.cuda.empty_cache()
     tot = sum(upd.values())
     ms64 = sum(r["ms"] for r in res[head].values())
@@ -658,7 +667,8 @@ def circuits_vs_oracle(a, qs, W, n):
     t_or = time.perf_counter() - t0
     out = {"n": n, "gates": len(ops), "oracle_s": t_or, "oracle_threads": oracle.num_threads()}
     for name, dt, mode, fk in (("c64_tiles", qs.QS_C64, 0, 0), ("c64_mfma5", qs.QS_C64, 0, 5),
-                               ("c128_tiles", qs.QS_C128, 0, 0), ("c128_pergate", qs.QS_C128, 1, 0)):
+                               ("c128_tiles", qs.QS_C128, 0, 0), ("c128_mfma5", qs.QS_C128, 0, 5),
+                               ("c128_pergate", qs.QS_C128, 1, 0)):
         with qs.State.create(n, dt) as s:
             s.run(ops, mats, mode=mode, fuse_k=fk)
             got = s.download().astype(np.complex128)

@@ -167,7 +167,11 @@ qs_status qs_apply_diag(qs_state s, const int* targets, int k, const double* dia
 /* Execution options for qs_run_circuit.  Zero-initialised means defaults. */
 typedef struct {
     int32_t mode;        /* 0 = auto (fused tile passes), 1 = one launch per gate */
-    int32_t fuse_k;      /* max qubits of a fused dense block; 0 = default */
+    int32_t fuse_k;      /* 0 = default (no matrix-core blocks; register blocks only); 4 or 5 =
+                            inside each tile pass, runs of gates on at most that many tile
+                            qubits are multiplied (FP64, host) into one dense block applied
+                            with FP64 matrix cores (both amplitude types; tiles of at least
+                            fuse_k + 4 qubits) */
     int32_t tile_qubits; /* qubits held in LDS per tile; 0 = default */
     int32_t max_blocks;  /* cap on the workgroups of each tile-pass launch (they stride over
                             the tiles); 0 = default (65536).  A lower cap leaves compute units
@@ -407,8 +411,8 @@ typedef struct {
 } qs_tune_entry;
 
 /* Autotune a batch configuration on a sample of circuits.  Stage 1 times
- * every tile size (10..12) and, for complex64, fused matrix-core width (0, 4,
- * 5) with the default class boundaries; stage 2 keeps the fastest of those and
+ * every tile size (10..12) and fused matrix-core width (0, 4, 5) with the
+ * default class boundaries; stage 2 keeps the fastest of those and
  * times the workgroup classes around the defaults (whole-in-LDS limit one
  * lower; persistent limit two lower to two higher).  Each candidate is
  * planned, run, and replayed twice on the device; *opts (dtype and mode as
@@ -562,6 +566,9 @@ qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
  *                                         registers instead of exchanged by shuffles (0 none,
  *                                         1 = default: those at or above the 128-byte line,
  *                                         2 all)
+ *   tile_waves4       [QS_TILE_W4]        tile passes of 2^11 amplitudes without k >= 3 ops:
+ *                                         1 (default) = the kernel held to 4 waves per SIMD,
+ *                                         0 = the kernel the compiler sizes (3 waves)
  * qs_tunable_set stores `value` (value < 0: back to the default / environment
  * value); QS_ERR_ARG for an unknown name or a value outside the knob's range.
  * Knobs are process-wide and may be changed from any thread; a launch being

@@ -49,12 +49,11 @@ struct qs_batch_s {
         size_t persist_l0 = 0, stream_l0 = 0;
         int persist_count = 0, stream_count = 0, persist_m = 0, stream_m = 0;
         std::vector<std::pair<size_t, std::pair<int, uint32_t>>> rounds; // (entry offset, (count, blocks))
-        // which launches need the full tile kernel (a pass with k >= 3 ops,
-        // fused blocks or ops outside segments); the others take the lean one,
-        // which holds fewer registers
-        std::vector<uint8_t> whole_full; // per whole group
-        bool persist_full = false;
-        std::vector<uint8_t> round_full; // per round
+        // the tile-kernel variant each launch needs (ops_variant, largest over
+        // the passes it covers): the lean kernel holds fewer registers
+        std::vector<uint8_t> whole_var; // per whole group
+        int persist_var = 0;
+        std::vector<uint8_t> round_var; // per round
         const BatchCirc* dcirc = nullptr;
         const BatchPass* dpass = nullptr;
         const TileOp* dops = nullptr;
@@ -186,14 +185,14 @@ qs_status enqueue_fused(qs_batch b, bool mark)
     for (size_t gi = 0; gi < S.whole_groups.size(); ++gi) {
         const auto& g = S.whole_groups[gi];
         st = launched(launch_batch_whole(b->dt, g.first, b->arena, S.dcirc, S.dlist + g.second.first, g.second.second,
-                                         S.dpass, S.dops, S.dmats, S.whole_full[gi] != 0, s0),
+                                         S.dpass, S.dops, S.dmats, S.whole_var[gi], s0),
                       "batch whole launch");
         if (st != QS_OK) return st;
     }
     if (!S.whole_groups.empty()) mk(0, s0);
     if (S.persist_count > 0) {
         st = launched(launch_batch_persist(b->dt, S.persist_m, b->arena, S.dcirc, S.dlist + S.persist_l0,
-                                           S.persist_count, S.dpass, S.dops, S.dmats, S.persist_full, s1),
+                                           S.persist_count, S.dpass, S.dops, S.dmats, S.persist_var, s1),
                       "batch persistent launch");
         if (st != QS_OK) return st;
         mk(1, s1);
@@ -201,7 +200,7 @@ qs_status enqueue_fused(qs_batch b, bool mark)
     for (size_t r = 0; r < S.rounds.size(); ++r) {
         st = launched(launch_batch_round(b->dt, S.stream_m, b->arena, S.dcirc, S.dpass, S.dops, S.dmats,
                                          S.dents + S.rounds[r].first, S.rounds[r].second.first,
-                                         S.rounds[r].second.second, S.round_full[r] != 0, sr),
+                                         S.rounds[r].second.second, S.round_var[r], sr),
                       "batch round launch");
         if (st != QS_OK) return st;
     }
@@ -476,8 +475,8 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         release(b);
         return st;
     }
-    std::vector<uint8_t> needs_full(count, 0);             // any pass of circuit i
-    std::vector<uint8_t> pass_full((size_t)pass0[count], 0); // per pass (global index)
+    std::vector<uint8_t> needs_var(count, 0);             // largest over the passes of circuit i
+    std::vector<uint8_t> pass_var((size_t)pass0[count], 0); // per pass (global index)
     parallel_for(count, [&](int i) {
         double* M = (double*)(b->hbuf + o_mats) + mat0[i];
         if (b->mode == 1) {
@@ -509,9 +508,9 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
                 t.moff += (uint64_t)mat0[i];
                 *T++ = t;
             }
-            const bool f = ops_need_full(p.ops.data(), p.ops.size(), p.m);
-            pass_full[(size_t)pass0[i] + j] = f;
-            needs_full[i] |= f;
+            const uint8_t v = (uint8_t)ops_variant(p.ops.data(), p.ops.size(), p.m);
+            pass_var[(size_t)pass0[i] + j] = v;
+            needs_var[i] = std::max(needs_var[i], v);
             op += (int64_t)p.ops.size();
         }
         std::vector<PlanPass>().swap(passes);
@@ -557,16 +556,16 @@ qs_status qs_batch_submit(const qs_circuit* circuits, int count, const qs_batch_
         S.stream_count = stream_count;
         S.stream_m = stream_m;
         S.rounds = rounds;
-        S.whole_full.assign(whole_groups.size(), 0);
+        S.whole_var.assign(whole_groups.size(), 0);
         for (size_t gi = 0; gi < whole_groups.size(); ++gi)
             for (int k = 0; k < whole_groups[gi].second.second; ++k)
-                S.whole_full[gi] |= needs_full[lists[whole_groups[gi].second.first + k]];
-        S.persist_full = false;
-        for (int k = 0; k < persist_count; ++k) S.persist_full |= needs_full[lists[persist_l0 + k]] != 0;
-        S.round_full.assign(rounds.size(), 0);
+                S.whole_var[gi] = std::max(S.whole_var[gi], needs_var[lists[whole_groups[gi].second.first + k]]);
+        S.persist_var = 0;
+        for (int k = 0; k < persist_count; ++k) S.persist_var = std::max(S.persist_var, (int)needs_var[lists[persist_l0 + k]]);
+        S.round_var.assign(rounds.size(), 0);
         for (size_t r = 0; r < rounds.size(); ++r)
             for (int k = 0; k < rounds[r].second.first; ++k)
-                S.round_full[r] |= pass_full[(size_t)rents[rounds[r].first + k].pass];
+                S.round_var[r] = std::max(S.round_var[r], pass_var[(size_t)rents[rounds[r].first + k].pass]);
         S.dcirc = dcirc;
         S.dpass = dpass;
         S.dops = dops;
@@ -848,7 +847,6 @@ qs_status qs_batch_tune(const qs_circuit* sample, int count, qs_batch_opts* opts
     // stage 1: tile size and fused width at the default classes
     for (int m = 10; m <= 12; ++m)
         for (int f : {0, 4, 5}) {
-            if (f != 0 && dt != QS_C64) continue;
             qs_status st = time_one(Cand{m, f, w0, p0});
             if (st != QS_OK) return st;
         }

@@ -774,7 +774,7 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
             P.gates += 1;
             P.updates += 1ull << (n - __builtin_popcountll(o.cmask));
         }
-        if ((po.fuse_k == 4 || po.fuse_k == 5) && po.dt == QS_C64 && m >= po.fuse_k + 4)
+        if ((po.fuse_k == 4 || po.fuse_k == 5) && m >= po.fuse_k + 4)
             fuse_pass(P, pool, po.fuse_k, po.fuse_min);
         const int r = po.segments ? seg_reg_qubits(po.dt, m) : 0;
         if (r > 0) segment_pass(P, pool, r);

@@ -82,20 +82,24 @@ struct TileOp {
 static_assert(sizeof(TileOp) == 88, "TileOp layout");
 enum { DG_UNIFORM = 0, DG_LTARGET = 1, DG_LCONTROL = 2, DG_GENERAL = 3, DG_CT = 4 };
 
-// Whether a pass's op list needs the full tile kernel: any k >= 3 dense op or
-// fused block, or (tiles of >= 2^10 elements) any op outside a segment.  The
-// lean kernel holds only what the rest needs, which keeps its registers low.
-inline bool ops_need_full(const TileOp* ops, size_t n, int m)
+// The tile-kernel variant a pass's op list needs: 2 with a fused matrix-core
+// block, else 1 with any k >= 3 dense op or (tiles of >= 2^10 elements) any
+// op outside a segment, else 0 (the lean kernel).  Each variant holds only
+// what its passes need, which keeps the registers of the smaller ones low; a
+// launch covering several passes takes the largest of their variants.
+inline int ops_variant(const TileOp* ops, size_t n, int m)
 {
+    int v = 0;
     for (size_t i = 0; i < n; ++i) {
         const int k = ops[i].kind;
         if (k == TK_SEG) {
             i += (size_t)ops[i].dj;
             continue;
         }
-        if (k == TK_DENSEK || k == TK_MFMA || m >= 10) return true;
+        if (k == TK_MFMA) return 2;
+        if (k == TK_DENSEK || m >= 10) v = 1;
     }
-    return false;
+    return v;
 }
 
 struct PlanPass {
@@ -112,7 +116,7 @@ struct PlanPass {
 struct PlanOpts {
     int m = 12;       // tile qubits
     int L = 5;        // forced low qubits
-    int fuse_k = 0;   // 0: no dense fusion; 4 or 5: matrix-core blocks (complex64)
+    int fuse_k = 0;   // 0: no dense fusion; 4 or 5: matrix-core blocks
     int fuse_min = 3; // dense gates a block must absorb to be worth a fused block
     int dt = QS_C128;
     bool segments = true; // group ops into register segments (tiles of >= 2^10 elements)
@@ -194,12 +198,12 @@ struct BatchCirc {
 // qubits runs whole in one block's LDS (initial basis state built in LDS; the
 // final state written once).
 hipError_t launch_batch_whole(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
-                              const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
+                              const BatchPass* passes, const TileOp* ops, const double* mats, int var,
                               hipStream_t st);
 // One launch for `count` circuits whose passes all use tile size M: one block
 // per circuit initialises its state and loops over its passes and tiles.
 hipError_t launch_batch_persist(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list,
-                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
+                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, int var,
                                 hipStream_t st);
 
 // One entry of a pass-major round: blocks [first_block, first_block + 2^(n-m))
@@ -214,7 +218,7 @@ struct RoundEntry {
 // One launch covering the same pass index of many circuits (all with tile size M).
 hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
                               const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
-                              uint32_t nblocks, bool full, hipStream_t st);
+                              uint32_t nblocks, int var, hipStream_t st);
 // Zero `bytes` bytes of the arena and set each listed circuit's basis amplitude.
 hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCirc* circs, const int32_t* list,
                              int count, hipStream_t st);
@@ -241,9 +245,9 @@ struct ServeEntry {
 };
 
 hipError_t launch_serve_round(int dt, int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
-                              uint32_t nblocks, bool full, hipStream_t st);
+                              uint32_t nblocks, int var, hipStream_t st);
 hipError_t launch_serve_whole(int dt, int M, char* pool, const char* plan, const ServeEntry* entries, int nentries,
-                              bool full, hipStream_t st);
+                              int var, hipStream_t st);
 
 qs_status validate_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, int64_t n_mats);
 qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int tile_qubits, PlanOpts& po);
@@ -252,6 +256,7 @@ qs_status run_planned(qs_state s, const qs_op* ops, int64_t n_ops, const double*
                       const qs_run_opts& o);
 
 // Tile pass launcher (tile.hip).  `dops` and `dmats` are device copies.
+// The `var` arguments of the launchers here are ops_variant values.
 // max_blocks caps the launch's grid (0: the default cap); the blocks stride
 // over the tiles.
 hipError_t launch_tile_pass(void* psi, int dt, int n, const PlanPass& pass, const TileOp* dops,

@@ -87,8 +87,8 @@ struct Req {
     uint64_t p_off = 0, p_bytes = 0;
     std::vector<char> plan_host; // kept until the request finishes (async upload source)
     int npass = 0, next_pass = 0;
-    std::vector<uint8_t> pass_full; // pass j needs the full tile kernel
-    bool any_full = false;
+    std::vector<uint8_t> pass_var; // tile-kernel variant of pass j (ops_variant)
+    int max_var = 0;               // largest over the passes
     bool whole = false, whole_launched = false;
     int64_t last_round = -1;
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -304,9 +304,9 @@ qs_status admit_one(qs_server s, Req& r)
         d.op0 = (int)to.size();
         d.nops = (int)p.ops.size();
         for (auto& t : p.ops) to.push_back(t);
-        const bool f = ops_need_full(p.ops.data(), p.ops.size(), p.m);
-        r.pass_full.push_back(f);
-        r.any_full |= f;
+        const int v = ops_variant(p.ops.data(), p.ops.size(), p.m);
+        r.pass_var.push_back((uint8_t)v);
+        r.max_var = std::max(r.max_var, v);
         bp.push_back(d);
     }
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
@@ -395,8 +395,8 @@ bool build_round(qs_server s)
     if (!sl) return false;
     std::vector<ServeEntry> whole_e, round_e;
     std::vector<int> whole_n;
-    std::vector<uint8_t> whole_f; // per whole entry: needs the full kernel
-    bool round_f = false;
+    std::vector<uint8_t> whole_v; // per whole entry: tile-kernel variant
+    int round_v = 0;
     std::vector<uint64_t> ids;
     uint32_t blocks = 0;
     for (uint64_t id : s->active) {
@@ -413,7 +413,7 @@ bool build_round(qs_server s)
             en.n = r.n;
             whole_e.push_back(en);
             whole_n.push_back(r.n);
-            whole_f.push_back(r.any_full);
+            whole_v.push_back((uint8_t)r.max_var);
             ids.push_back(id);
         } else if (r.next_pass < r.npass || (r.npass == 0 && r.last_round < 0)) {
             if (r.npass > 0) {
@@ -427,7 +427,7 @@ bool build_round(qs_server s)
                 en.first_block = blocks;
                 blocks += 1u << (r.n - s->m);
                 round_e.push_back(en);
-                round_f |= r.pass_full[(size_t)r.next_pass] != 0;
+                round_v = std::max(round_v, (int)r.pass_var[(size_t)r.next_pass]);
             }
             ids.push_back(id);
         }
@@ -463,13 +463,13 @@ bool build_round(qs_server s)
     if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "round upload: %s", hipGetErrorString(e));
     for (size_t i = 0; i < order.size() && st == QS_OK;) {
         size_t j = i;
-        bool full = false;
-        while (j < order.size() && whole_n[order[j]] == whole_n[order[i]]) full |= whole_f[order[j++]] != 0;
+        int var = 0;
+        while (j < order.size() && whole_n[order[j]] == whole_n[order[i]]) var = std::max(var, (int)whole_v[order[j++]]);
         if (inject_fault_now()) {
             st = set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
             break;
         }
-        e = launch_serve_whole(s->dt, whole_n[order[i]], s->pool, s->plan, sl->dev + i, (int)(j - i), full, s->st);
+        e = launch_serve_whole(s->dt, whole_n[order[i]], s->pool, s->plan, sl->dev + i, (int)(j - i), var, s->st);
         s->stats.launches += 1;
         if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "whole launch: %s", hipGetErrorString(e));
         i = j;
@@ -479,7 +479,7 @@ bool build_round(qs_server s)
             st = set_err(QS_ERR_DEVICE, "injected device fault (QS_FAULT_INJECT)");
         } else {
             e = launch_serve_round(s->dt, s->m, s->pool, s->plan, sl->dev + whole_e.size(), (int)round_e.size(), blocks,
-                                   round_f, s->st);
+                                   round_v, s->st);
             s->stats.launches += 1;
             if (e != hipSuccess) st = set_err(QS_ERR_DEVICE, "round launch: %s", hipGetErrorString(e));
         }

@@ -5,7 +5,7 @@ namespace qs {
 
 namespace {
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 __device__ __forceinline__ void tile_pass(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, const QList& ql,
                                           const InsertPlan& ipQ, const TileOp* __restrict__ ops, int nops,
                                           const double* __restrict__ mats, int nt)
@@ -21,29 +21,29 @@ __device__ __forceinline__ void tile_pass(typename CT<R>::V* __restrict__ psi, u
         const uint64_t base = ins_bits(tau, ipQ);
         tile_load<R, M>(psi, base, ql.L, hoff, tile, nt);
         __syncthreads();
-        tile_ops<R, M, FULL>(tile, base, ops, nops, mats);
+        tile_ops<R, M, VAR>(tile, base, ops, nops, mats);
         tile_store<R, M>(psi, base, ql.L, hoff, tile, nt);
         __syncthreads();
     }
 }
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 __global__ void __launch_bounds__(256)
 k_tile(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
        const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
 {
-    tile_pass<R, M, FULL>(psi, ntiles, ql, ipQ, ops, nops, mats, nt);
+    tile_pass<R, M, VAR>(psi, ntiles, ql, ipQ, ops, nops, mats, nt);
 }
 
 // The same pass held to 128 VGPRs (4 waves per SIMD instead of 3): for tiles
 // of 2^11 the compiler then keeps a few values in scratch (12 bytes per lane
 // for the lean kernel); larger tiles would spill heavily and keep k_tile.
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_tile_w4(typename CT<R>::V* __restrict__ psi, uint64_t ntiles, QList ql, InsertPlan ipQ,
           const TileOp* __restrict__ ops, int nops, const double* __restrict__ mats, int nt)
 {
-    tile_pass<R, M, FULL>(psi, ntiles, ql, ipQ, ops, nops, mats, nt);
+    tile_pass<R, M, VAR>(psi, ntiles, ql, ipQ, ops, nops, mats, nt);
 }
 
 template <typename R, int M>
@@ -67,10 +67,12 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
     {
         const size_t lim = lds_max > 163840 ? 163840 : lds_max;
-        hipError_t e = lds_optin((const void*)k_tile<R, M, false>, lim);
-        if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, true>, lim);
+        hipError_t e = lds_optin((const void*)k_tile<R, M, 0>, lim);
+        if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, 1>, lim);
+        if constexpr (M >= 8)
+            if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, 2>, lim);
         if constexpr (M == 11)
-            if (e == hipSuccess) e = lds_optin((const void*)k_tile_w4<R, M, false>, lim);
+            if (e == hipSuccess) e = lds_optin((const void*)k_tile_w4<R, M, 0>, lim);
         if (e != hipSuccess) return e;
     }
     if (lds > 163840) return hipErrorInvalidValue;
@@ -83,23 +85,31 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     // non-temporal when each contiguous run covers whole 128-byte lines
     const int line_bits = sizeof(R) == 8 ? 3 : 4;
     const int nt = (tun(T_NT) && pass.L >= line_bits) ? 1 : 0;
-    // the full variant only when the pass needs it (k >= 3 ops, fused
-    // blocks or ops outside segments would otherwise cost every pass registers)
-    const bool full = ops_need_full(pass.ops.data(), pass.ops.size(), pass.m);
-    if (full) {
-        hipLaunchKernelGGL((k_tile<R, M, true>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                           (int)pass.ops.size(), (const double*)dmats, nt);
+    // the variant the pass needs (k >= 3 ops, fused blocks or ops outside
+    // segments would otherwise cost every pass registers)
+    const int var = ops_variant(pass.ops.data(), pass.ops.size(), pass.m);
+    const int nops = (int)pass.ops.size();
+    if constexpr (M >= 8) {
+        if (var == 2) {
+            hipLaunchKernelGGL((k_tile<R, M, 2>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops, nops,
+                               (const double*)dmats, nt);
+            return hipGetLastError();
+        }
+    }
+    if (var >= 1) {
+        hipLaunchKernelGGL((k_tile<R, M, 1>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops, nops,
+                           (const double*)dmats, nt);
         return hipGetLastError();
     }
     if constexpr (M == 11) {
         if (tun(T_TILE_W4)) {
-            hipLaunchKernelGGL((k_tile_w4<R, M, false>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                               (int)pass.ops.size(), (const double*)dmats, nt);
+            hipLaunchKernelGGL((k_tile_w4<R, M, 0>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops, nops,
+                               (const double*)dmats, nt);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_tile<R, M, false>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops,
-                       (int)pass.ops.size(), (const double*)dmats, nt);
+    hipLaunchKernelGGL((k_tile<R, M, 0>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops, nops,
+                       (const double*)dmats, nt);
     return hipGetLastError();
 }
 

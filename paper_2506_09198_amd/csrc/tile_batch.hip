@@ -9,7 +9,7 @@ namespace {
 
 // ---------------------------------------------------------------- batches
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 __global__ void __launch_bounds__(256)
 k_batch_whole(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
               const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
@@ -37,12 +37,12 @@ k_batch_whole(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
     __syncthreads();
     for (int p = 0; p < c.npass; ++p) {
         const BatchPass& bp = passes[c.pass0 + p];
-        tile_ops<R, M, FULL>(tile, 0, ops + bp.op0, bp.nops, mats);
+        tile_ops<R, M, VAR>(tile, 0, ops + bp.op0, bp.nops, mats);
     }
     tile_store<R, M>(psi, 0, M, hoff, tile, M >= 4 ? 1 : 0);
 }
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 __global__ void __launch_bounds__(256)
 k_batch_persist(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const int32_t* __restrict__ list,
                 const BatchPass* __restrict__ passes, const TileOp* __restrict__ ops,
@@ -73,14 +73,14 @@ k_batch_persist(char* __restrict__ arena, const BatchCirc* __restrict__ circs, c
             const uint64_t base = ins_bits(tau, bp.ip);
             tile_load<R, M>(psi, base, bp.L, hoff, tile, 0);
             __syncthreads();
-            tile_ops<R, M, FULL>(tile, base, ops + bp.op0, bp.nops, mats);
+            tile_ops<R, M, VAR>(tile, base, ops + bp.op0, bp.nops, mats);
             tile_store<R, M>(psi, base, bp.L, hoff, tile, 0);
             __syncthreads();
         }
     }
 }
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 __global__ void __launch_bounds__(256)
 k_batch_round(char* __restrict__ arena, const BatchCirc* __restrict__ circs, const BatchPass* __restrict__ passes,
               const TileOp* __restrict__ ops, const double* __restrict__ mats,
@@ -112,7 +112,7 @@ k_batch_round(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
         const int nt = bp.L >= (sizeof(R) == 8 ? 3 : 4) ? 1 : 0;
         tile_load<R, M>(psi, base, bp.L, hoff, tile, nt);
         __syncthreads();
-        tile_ops<R, M, FULL>(tile, base, ops + bp.op0, bp.nops, mats);
+        tile_ops<R, M, VAR>(tile, base, ops + bp.op0, bp.nops, mats);
         tile_store<R, M>(psi, base, bp.L, hoff, tile, nt);
         __syncthreads(); // the next tile rewrites hoff and the tile
     }
@@ -152,7 +152,7 @@ k_batch_basis(char* __restrict__ arena, const BatchCirc* __restrict__ circs, con
     }
 }
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const BatchPass* passes, const TileOp* ops,
                                  const double* mats, const RoundEntry* entries, int nentries, uint32_t nblocks,
                                  hipStream_t st)
@@ -160,50 +160,50 @@ static hipError_t launch_round_m(char* arena, const BatchCirc* circs, const Batc
     const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
     const size_t lds = lds_max > 163840 ? 163840 : lds_max;
     {
-        const hipError_t e = lds_optin((const void*)k_batch_round<R, M, FULL>, lds);
+        const hipError_t e = lds_optin((const void*)k_batch_round<R, M, VAR>, lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_batch_round<R, M, FULL>), dim3(round_grid(nblocks)), dim3(256), lds, st, arena, circs, passes,
+    hipLaunchKernelGGL((k_batch_round<R, M, VAR>), dim3(round_grid(nblocks)), dim3(256), lds, st, arena, circs, passes,
                        ops, mats, entries, nentries, nblocks);
     return hipGetLastError();
 }
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 static hipError_t launch_whole_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                  const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
     const size_t lds = sizeof(typename CT<R>::V) * (1ull << M) + 16;
     {
-        const hipError_t e = lds_optin((const void*)k_batch_whole<R, M, FULL>, lds);
+        const hipError_t e = lds_optin((const void*)k_batch_whole<R, M, VAR>, lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_batch_whole<R, M, FULL>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops, mats);
+    hipLaunchKernelGGL((k_batch_whole<R, M, VAR>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops, mats);
     return hipGetLastError();
 }
 
-template <typename R, int M, bool FULL>
+template <typename R, int M, int VAR>
 static hipError_t launch_persist_m(char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                    const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
     const size_t lds_max = tile_lds_bytes(sizeof(R) == 8 ? QS_C128 : QS_C64, M, 0);
     {
-        const hipError_t e = lds_optin((const void*)k_batch_persist<R, M, FULL>, lds_max > 163840 ? 163840 : lds_max);
+        const hipError_t e = lds_optin((const void*)k_batch_persist<R, M, VAR>, lds_max > 163840 ? 163840 : lds_max);
         if (e != hipSuccess) return e;
     }
     // LDS for the smallest L any pass may have
     const size_t lds = lds_max > 163840 ? 163840 : lds_max;
-    hipLaunchKernelGGL((k_batch_persist<R, M, FULL>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops,
+    hipLaunchKernelGGL((k_batch_persist<R, M, VAR>), dim3(count), dim3(256), lds, st, arena, circs, list, passes, ops,
                        mats);
     return hipGetLastError();
 }
 
-template <typename R, bool FULL>
+template <typename R, int VAR>
 static hipError_t batch_whole_r(int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                 const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
     switch (M) {
 #define QS_WCASE(MM) \
-    case MM: return launch_whole_m<R, MM, FULL>(arena, circs, list, count, passes, ops, mats, st);
+    case MM: return launch_whole_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(arena, circs, list, count, passes, ops, mats, st);
         QS_WCASE(1) QS_WCASE(2) QS_WCASE(3) QS_WCASE(4) QS_WCASE(5) QS_WCASE(6) QS_WCASE(7) QS_WCASE(8)
         QS_WCASE(9) QS_WCASE(10) QS_WCASE(11) QS_WCASE(12) QS_WCASE(13)
 #undef QS_WCASE
@@ -211,13 +211,13 @@ static hipError_t batch_whole_r(int M, char* arena, const BatchCirc* circs, cons
     }
 }
 
-template <typename R, bool FULL>
+template <typename R, int VAR>
 static hipError_t batch_persist_r(int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
                                   const BatchPass* passes, const TileOp* ops, const double* mats, hipStream_t st)
 {
     switch (M) {
 #define QS_PCASE(MM) \
-    case MM: return launch_persist_m<R, MM, FULL>(arena, circs, list, count, passes, ops, mats, st);
+    case MM: return launch_persist_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(arena, circs, list, count, passes, ops, mats, st);
         QS_PCASE(9) QS_PCASE(10) QS_PCASE(11) QS_PCASE(12) QS_PCASE(13)
 #undef QS_PCASE
     default: return hipErrorInvalidValue;
@@ -227,37 +227,35 @@ static hipError_t batch_persist_r(int M, char* arena, const BatchCirc* circs, co
 } // namespace
 
 hipError_t launch_batch_whole(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list, int count,
-                              const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
+                              const BatchPass* passes, const TileOp* ops, const double* mats, int var,
                               hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (dt == QS_C128)
-        return full ? batch_whole_r<double, true>(M, arena, circs, list, count, passes, ops, mats, st)
-                  : batch_whole_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
-    return full ? batch_whole_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
-              : batch_whole_r<float, false>(M, arena, circs, list, count, passes, ops, mats, st);
+    return dispatch_var(dt, var, [&](auto r, auto v) {
+        return batch_whole_r<typename decltype(r)::type, decltype(v)::value>(M, arena, circs, list, count, passes, ops,
+                                                                             mats, st);
+    });
 }
 
 hipError_t launch_batch_persist(int dt, int M, char* arena, const BatchCirc* circs, const int32_t* list,
-                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, bool full,
+                                int count, const BatchPass* passes, const TileOp* ops, const double* mats, int var,
                                 hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    if (dt == QS_C128)
-        return full ? batch_persist_r<double, true>(M, arena, circs, list, count, passes, ops, mats, st)
-                  : batch_persist_r<double, false>(M, arena, circs, list, count, passes, ops, mats, st);
-    return full ? batch_persist_r<float, true>(M, arena, circs, list, count, passes, ops, mats, st)
-              : batch_persist_r<float, false>(M, arena, circs, list, count, passes, ops, mats, st);
+    return dispatch_var(dt, var, [&](auto r, auto v) {
+        return batch_persist_r<typename decltype(r)::type, decltype(v)::value>(M, arena, circs, list, count, passes,
+                                                                               ops, mats, st);
+    });
 }
 
-template <typename R, bool FULL>
+template <typename R, int VAR>
 static hipError_t batch_round_r(int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
                                 const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
                                 uint32_t nblocks, hipStream_t st)
 {
     switch (M) {
 #define QS_RCASE(MM) \
-    case MM: return launch_round_m<R, MM, FULL>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+    case MM: return launch_round_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
         QS_RCASE(9) QS_RCASE(10) QS_RCASE(11) QS_RCASE(12) QS_RCASE(13)
 #undef QS_RCASE
     default: return hipErrorInvalidValue;
@@ -266,14 +264,13 @@ static hipError_t batch_round_r(int M, char* arena, const BatchCirc* circs, cons
 
 hipError_t launch_batch_round(int dt, int M, char* arena, const BatchCirc* circs, const BatchPass* passes,
                               const TileOp* ops, const double* mats, const RoundEntry* entries, int nentries,
-                              uint32_t nblocks, bool full, hipStream_t st)
+                              uint32_t nblocks, int var, hipStream_t st)
 {
     if (nentries <= 0 || nblocks == 0) return hipSuccess;
-    if (dt == QS_C128)
-        return full ? batch_round_r<double, true>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st)
-                  : batch_round_r<double, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
-    return full ? batch_round_r<float, true>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st)
-              : batch_round_r<float, false>(M, arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+    return dispatch_var(dt, var, [&](auto r, auto v) {
+        return batch_round_r<typename decltype(r)::type, decltype(v)::value>(M, arena, circs, passes, ops, mats,
+                                                                             entries, nentries, nblocks, st);
+    });
 }
 
 hipError_t launch_batch_init(int dt, char* arena, uint64_t bytes, const BatchCirc* circs, const int32_t* list,

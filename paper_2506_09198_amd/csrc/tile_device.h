@@ -17,6 +17,8 @@
 // Operations (TileOp): dense 1q / 2q / k-qubit gates whose targets are in Q,
 // with controls split into tile-local and per-tile parts; diagonal gates act
 // elementwise from the global index and need not lie in Q.
+#include <type_traits>
+
 #include "device_common.h"
 #include "planner.h"
 
@@ -48,24 +50,26 @@ __device__ __forceinline__ uint32_t swz(uint32_t e)
 #define QS_SW(e) swz<(int)sizeof(V)>(e)
 
 // Fused dense block on K = 4 or 5 tile-local qubits with FP64 matrix cores
-// (complex64 tiles).  The complex 2^K x 2^K matrix acts as its real embedding
-// [[Ur, -Ui], [Ui, Ur]] (interleaved rows/columns, 2^(K+1) square) on the
-// tile's 2^(M-K) groups ("columns"), with v_mfma_f64_16x16x4f64: lane l holds
-// A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16].  The FP32 amplitudes
-// convert to FP64 exactly and the result is rounded once, to nearest, when it
-// is stored; FP32 matrix-core accumulation instead shrinks the norm by a
-// one-signed ~1e-8 per block, which adds up over a deep circuit.  One FP64
-// MFMA costs as much as the two FP32 ones an exact (hi + lo) matrix would
-// need.  The A fragments come pre-arranged by the planner ([q][lane][2]
-// doubles, q*2+j = rb*KS + ks), so a wave loads them with 16-byte coalesced
-// loads.  Each wave owns whole column blocks of 16 groups, so its in-place
-// writes never race another wave.
+// (both amplitude types).  The complex 2^K x 2^K matrix acts as its real
+// embedding [[Ur, -Ui], [Ui, Ur]] (interleaved rows/columns, 2^(K+1) square)
+// on the tile's 2^(M-K) groups ("columns"), with v_mfma_f64_16x16x4f64: lane
+// l holds A[l%16][l/16], B[l/16][l%16] and D[l/16 + 4v][l%16].  Tile values
+// enter exactly (FP32 widens to FP64 without rounding) and each result is
+// rounded once, to nearest, when it is stored.  An FP32 form would need the
+// matrix as hi + lo FP32 parts (a matrix rounded to FP32 repeats its
+// rounding coherently at every application) with the lo products kept out of
+// the hi accumulator, where they fall below its last bit; two FP32 MFMAs
+// cost what one FP64 MFMA costs.  The A fragments come
+// pre-arranged by the planner ([q][lane][2] doubles, q*2+j = rb*KS + ks), so
+// a wave loads them with 16-byte coalesced loads.  Each wave owns whole
+// column blocks of 16 groups, so its in-place writes never race another wave.
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-template <int K, int M>
-__device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const double* mats, int tid)
+template <typename R, int K, int M>
+__device__ __forceinline__ void mfma_block(typename CT<R>::V* tile, const TileOp& d, const double* mats, int tid)
 {
+    using V = typename CT<R>::V;
     constexpr int DR = 2 << K;     // real dimension
     constexpr int RB = DR / 16;    // 16-row blocks
     constexpr int KS = DR / 4;     // k steps of 4
@@ -90,7 +94,7 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
         pos[j] = d.p[j];
         tm |= 1u << pos[j];
     }
-    float* tf = (float*)tile;
+    R* tr = (R*)tile; // component c of element e at 2 * swz(e) + c
     for (int cb = wave; cb < CB; cb += 4) {
         const uint32_t col = cb * 16 + li;
         uint32_t gb = col; // insert zeros at the block qubits (ascending)
@@ -106,7 +110,7 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 if ((mm >> j) & 1) e |= 1u << pos[j];
-            const double bv = (double)tf[2 * swz<8>(e) + (lk & 1)];
+            const double bv = (double)tr[2 * QS_SW(e) + (lk & 1)];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
                 acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb * KS + ks], bv, acc[rb], 0, 0, 0);
@@ -121,7 +125,7 @@ __device__ __forceinline__ void mfma_block(float2* tile, const TileOp& d, const 
 #pragma unroll
                 for (int j = 0; j < K; ++j)
                     if ((mm >> j) & 1) e |= 1u << pos[j];
-                tf[2 * swz<8>(e) + (lk & 1)] = (float)acc[rb][v];
+                tr[2 * QS_SW(e) + (lk & 1)] = (R)acc[rb][v];
             }
         }
     }
@@ -511,8 +515,12 @@ __device__ __forceinline__ void run_segment(typename CT<R>::V* tile, uint64_t ba
 
 // Apply a pass's operation list to the tile held in LDS (all lanes of the
 // block call this; it ends with the tile complete in LDS).  `base` is the
-// global index of tile element 0 (tile bits zero).
-template <typename R, int M, bool FULL>
+// global index of tile element 0 (tile bits zero).  VAR selects what the
+// kernel holds (the host launches the variant a pass needs, ops_variant):
+// 0 = segments only for tiles of >= 2^10 (every op for smaller tiles),
+// 1 = every op but fused matrix-core blocks, 2 = every op (the matrix-core
+// fragments would otherwise cost every variant-1 pass registers).
+template <typename R, int M, int VAR>
 __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base, const TileOp* __restrict__ ops,
                                          int nops, const double* __restrict__ mats)
 {
@@ -533,7 +541,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
         }
         // the lean kernel of a large tile holds segments only (the host
         // launches the full kernel for any other op)
-        if constexpr (!FULL && M >= 10) continue;
+        if constexpr (VAR == 0 && M >= 10) continue;
         if (kind != TK_DIAG && (base & d.gcm) != d.gcv) continue; // tile fails the outside controls
         const double* u = mats + d.moff;
         const uint32_t lcm = (uint32_t)d.lcm, lcv = (uint32_t)d.lcv;
@@ -597,7 +605,7 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                 }
             }
         } else if (kind == TK_DENSEK) {
-            if constexpr (!FULL) continue;
+            if constexpr (VAR == 0) continue;
             // Rounds of 256 slots; a round holds whole groups (D <= 64
             // divides 256), so every lane reads its group, all wait, and
             // all write: no group is overwritten while still being read.
@@ -640,11 +648,11 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                 __syncthreads();
             }
         } else if (kind == TK_MFMA) {
-            if constexpr (FULL && sizeof(R) == 4 && M >= 8) {
+            if constexpr (VAR == 2 && M >= 8) {
                 if (d.k == 5) {
-                    if constexpr (M >= 9) mfma_block<5, M>((float2*)tile, d, mats, tid);
+                    if constexpr (M >= 9) mfma_block<R, 5, M>(tile, d, mats, tid);
                 } else {
-                    mfma_block<4, M>((float2*)tile, d, mats, tid);
+                    mfma_block<R, 4, M>(tile, d, mats, tid);
                 }
             }
         } else if (kind == TK_DIAG) {
@@ -824,6 +832,23 @@ __device__ __forceinline__ void build_hoff(uint32_t* hoff, int M, int L, const i
     }
 }
 
+// Host: call f(RTag<R>, integral_constant<int, VAR>) for the amplitude type
+// dt and the tile-kernel variant var (an ops_variant value).
+template <typename R>
+struct RTag {
+    using type = R;
+};
+
+template <typename F>
+inline hipError_t dispatch_var(int dt, int var, F&& f)
+{
+    auto by_r = [&](auto r) {
+        if (var >= 2) return f(r, std::integral_constant<int, 2>());
+        if (var == 1) return f(r, std::integral_constant<int, 1>());
+        return f(r, std::integral_constant<int, 0>());
+    };
+    return dt == QS_C128 ? by_r(RTag<double>()) : by_r(RTag<float>());
+}
 
 } // namespace
 } // namespace qs

@@ -119,19 +119,20 @@ def test_planner_groups_gates(qs):
     assert nops <= len(ops) and npass <= 20 * 6
 
 
-def test_planner_fuses_blocks_for_c64(qs, monkeypatch):
+@pytest.mark.parametrize("dt", [1, 2])
+def test_planner_fuses_blocks(qs, dt, monkeypatch):
     monkeypatch.setenv("QS_FUSE_MIN", "2")
     monkeypatch.setenv("QS_REG_SEGMENTS", "0")  # compare matrix-core blocks with ops one by one
     r = W.rqc_chain(20, 10, 1)
     ops, mats = r.arrays()
-    plain = qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, tile_qubits=12)
-    fused = qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, tile_qubits=12, fuse_k=5)
+    plain = qs.qs_plan_circuit(20, dt, ops, mats, tile_qubits=12)
+    fused = qs.qs_plan_circuit(20, dt, ops, mats, tile_qubits=12, fuse_k=5)
     assert fused[0] == plain[0] and fused[1] < 0.6 * plain[1]
-    # complex128 states never get FP32 matrix-core blocks
-    assert qs.qs_plan_circuit(20, qs.QS_C128, ops, mats, tile_qubits=12, fuse_k=5) == \
-        qs.qs_plan_circuit(20, qs.QS_C128, ops, mats, tile_qubits=12)
+    # blocks need tiles of at least fuse_k + 4 qubits
+    assert qs.qs_plan_circuit(20, dt, ops, mats, tile_qubits=8, fuse_k=5) == \
+        qs.qs_plan_circuit(20, dt, ops, mats, tile_qubits=8)
     with pytest.raises(qs.QSError):
-        qs.qs_plan_circuit(20, qs.QS_C64, ops, mats, fuse_k=3)
+        qs.qs_plan_circuit(20, dt, ops, mats, fuse_k=3)
 
 
 def test_new_entry_points_reject_null_handles(qs):

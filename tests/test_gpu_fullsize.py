@@ -86,7 +86,7 @@ def test_gate_sweep_n30_c128_sampled_per_gate(qs):
     assert abs(float((psi.abs() ** 2).sum().item()) - 1.0) < 1e-10
 
 
-@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5)])
+@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5), (2, 5)])
 def test_qft_n32_closed_form_sampled(qs, dt, fuse):
     n = 32
     x = int(np.random.default_rng(6).integers(1 << n))
@@ -117,9 +117,9 @@ def test_rqc_n32_c128_pergate_sampled_and_tile_anchors(qs):
     """Config 3A gate by gate (complex128, 64 GiB): each gate's outputs on 256
     sampled indices against the oracle's definition, from the GPU state just
     before that gate.  The per-gate result then anchors the tile-pass runs of
-    the same circuit on 4096 samples: complex128 within 1e-12, complex64
-    (register blocks, and 5-qubit matrix-core blocks) with an estimated
-    infidelity below 1e-6."""
+    the same circuit on 4096 samples: complex128 (register blocks, and 5-qubit
+    matrix-core blocks) within 1e-12, complex64 (both forms) with an
+    estimated infidelity below 1e-6."""
     import torch
 
     n = 32
@@ -147,7 +147,7 @@ def test_rqc_n32_c128_pergate_sampled_and_tile_anchors(qs):
     ys = np.random.default_rng(33).integers(0, 1 << n, size=4096, dtype=np.uint64)
     ref = _gather(psi, ys)
     N = float(1 << n)
-    for dt, fuse in ((2, 0), (1, 0), (1, 5)):
+    for dt, fuse in ((2, 0), (2, 5), (1, 0), (1, 5)):
         with qs.State.create(n, dt) as t:
             t.run(ops, mats, mode=0, fuse_k=fuse)
             got = np.array([t.download(int(v), 1)[0] for v in ys], dtype=np.complex128)
@@ -161,7 +161,7 @@ def test_rqc_n32_c128_pergate_sampled_and_tile_anchors(qs):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5)])
+@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5), (2, 5)])
 def test_rqc_n32_echo(qs, dt, fuse):
     n = 32
     c = W.rqc_chain(n, 20, 5)

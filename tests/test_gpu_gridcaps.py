@@ -219,3 +219,29 @@ def test_pergate_schedules(qs, dt, n):
         outs.append(got)
     for knobs, o in zip(SCHEDULES[1:], outs[1:]):
         assert o.tobytes() == outs[0].tobytes(), f"{knobs} differs bitwise from the default schedule"
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+@pytest.mark.parametrize("name", ["rqc16", "qft17", "u3cnot15"])
+def test_tile_waves4_bitwise(qs, dt, name):
+    """Tile passes of 2^11 amplitudes with the kernel held to 4 waves per SIMD
+    and with the compiler-sized kernel: both against the oracle and bitwise
+    the same (the register limit changes where values live, not the
+    arithmetic)."""
+    c = CIRCS[name]()
+    ops, mats = c.arrays()
+    psi0 = W.random_state(c.n, 32) if name == "rqc16" else None
+    want = oracle.run(c.n, ops, mats, psi0, c.init_basis)
+    outs = []
+    for w4 in (0, 1):
+        with qs.tunables(tile_waves4=w4):
+            with qs.State.create(c.n, dt) as s:
+                if psi0 is not None:
+                    s.upload(psi0 if dt == 2 else psi0.astype(np.complex64))
+                else:
+                    s.init_basis(c.init_basis)
+                s.run(ops, mats, mode=0, tile_qubits=11)
+                got = s.download()
+        _check(got, want, dt, f"{name} tile_waves4={w4}")
+        outs.append(got)
+    assert outs[0].tobytes() == outs[1].tobytes()

@@ -287,19 +287,22 @@ def test_error_leaves_state_untouched(qs):
     assert np.array_equal(s.download(), psi0)
 
 
+@pytest.mark.parametrize("dt", [1, 2])
 @pytest.mark.parametrize("name", list(CIRCS))
 @pytest.mark.parametrize("fk,tq,fmin", [(4, 0, 1), (5, 0, 1), (5, 9, 1), (4, 8, 2), (5, 13, 3)])
-def test_fused_mfma_blocks_c64(qs, name, fk, tq, fmin, monkeypatch):
+def test_fused_mfma_blocks(qs, dt, name, fk, tq, fmin, monkeypatch):
+    """Fused dense blocks on FP64 matrix cores, both amplitude types, against
+    the oracle (complex128 to the FP64 bar)."""
     monkeypatch.setenv("QS_FUSE_MIN", str(fmin))
     c = CIRCS[name]()
     n = c.n
     ops, mats = c.arrays()
-    npass, nops = qs.qs_plan_circuit(n, qs.QS_C64, ops, mats, fuse_k=fk, tile_qubits=tq)
+    npass, nops = qs.qs_plan_circuit(n, dt, ops, mats, fuse_k=fk, tile_qubits=tq)
     psi0 = _rand(n, 11) if name in ("rqc14", "bench16") else None
     want = oracle.run(n, ops, mats, psi0, c.init_basis)
-    s = _state(qs, n, 1, psi0, c.init_basis)
+    s = _state(qs, n, dt, psi0, c.init_basis)
     s.run(ops, mats, mode=0, fuse_k=fk, tile_qubits=tq)
-    _check(s.download(), want, 1, f"{name} fuse_k={fk} tq={tq} ({nops} ops in {npass} passes)")
+    _check(s.download(), want, dt, f"{name} fuse_k={fk} tq={tq} ({nops} ops in {npass} passes)")
 
 
 def _batch_mix(seed):
@@ -414,7 +417,7 @@ def test_batch_tune(qs, dt):
     a batch with the tuned options matches the oracle."""
     sample = [W.rqc_chain(n, 8, 100 + n) for n in (14, 15, 16, 17, 18)] + [W.qft(n, n) for n in (15, 17)]
     best, rows = qs.qs_batch_tune(sample, dtype=dt)
-    expect = (9 if dt == 1 else 3) + 5  # tile x fusion, then five workgroup-class variants
+    expect = 9 + 5  # tile x fusion, then five workgroup-class variants
     assert len(rows) == expect and all(r["device_ms"] > 0 for r in rows)
     keys = ("tile_qubits", "fuse_k", "whole_max", "persist_max")
     fastest = min(rows, key=lambda r: r["device_ms"])
