@@ -260,11 +260,13 @@ qs_status qs_norm(qs_state s, double* out);
  * DEVICE memory for 2^m doubles, caller-owned.  The work is enqueued on the
  * state's stream and the call returns at once (nothing is copied to the host
  * and nothing waits); read dev_out after that stream.  The partial sums live
- * in one fixed scratch array per GPU (2^22 doubles = 32 MiB, held by the
- * library until the process ends), so the call calls no hipMalloc/hipFree or
- * allocating routine: QS_ERR_ARG when the reduction would need more than that
- * (2^(n-12) partial sums for m <= n - 12, else 2^m: every n <= 34 with
- * m <= 22 fits), or for a NULL dev_out or the qubit list errors of
+ * in one fixed scratch array per GPU (2^22 + 2^12 doubles = 32 MiB + 32 KiB,
+ * held by the library until the process ends), so the call calls no
+ * hipMalloc/hipFree or allocating routine: QS_ERR_ARG when the reduction
+ * would need more than that (2^(n-12) partial sums for m <= n - 12, else 2^m,
+ * plus a 4096th of them for the second level of the final sum when an
+ * outcome has more than 4096: every n <= 34 with m <= 22 fits), or for a
+ * NULL dev_out or the qubit list errors of
  * qs_probabilities.  Every call on one GPU shares that array, and each call
  * overwrites all of it that it reads, so calls need no clearing between them;
  * calls that overlap on one GPU (different streams, or different threads)
@@ -276,8 +278,8 @@ qs_status qs_probabilities_noalloc(qs_state s, const int* qubits, int m, double*
  * z_mask, Y = iXZ on qubits in both.  Summed in FP64 in a fixed order as
  * i^w * sum_k conj(psi_{k ^ x}) psi_k (-1)^popcount(k & z); out[0] = real
  * part, out[1] = imaginary part (0 up to rounding, P being Hermitian).  The
- * state is not normalised first.  Blocking (NEXT item: measurement on top of
- * the reductions).  QS_ERR_ARG for mask bits at or above n. */
+ * state is not normalised first.  Blocking.  QS_ERR_ARG for mask bits at or
+ * above n. */
 qs_status qs_expect_pauli(qs_state s, uint64_t x_mask, uint64_t z_mask, double* out);
 
 /* Sample basis-state indices from |psi_i|^2 / sum_j |psi_j|^2 by inverting

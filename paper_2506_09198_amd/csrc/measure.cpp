@@ -89,13 +89,14 @@ extern "C" qs_status qs_sample(qs_state s, const double* u, int64_t shots, uint6
     if (!u || !out) return set_err(QS_ERR_ARG, "null uniforms or output");
     for (int64_t k = 0; k < shots; ++k)
         if (!(u[k] >= 0.0 && u[k] < 1.0)) return set_err(QS_ERR_ARG, "u[%lld] outside [0, 1)", (long long)k);
-    const uint64_t nch = reduce_scratch_doubles(s->n, 0);
-    if ((st = scratch(s, nch + 1)) != QS_OK) return st;
+    const uint64_t nch = reduce_partials(s->n, 0);  // chunk sums
+    const uint64_t red = reduce_scratch_doubles(s->n, 0);
+    if ((st = scratch(s, red + 1)) != QS_OK) return st;
     double* part = s->red_part;
     st = traced_launch(s, read_rec(s, 1ull << s->n),
                        [&](int* kind) {
                            *kind = QS_K_REDUCE;
-                           return launch_probabilities(s->d, s->dt, s->n, nullptr, 0, part, part + nch, s->st);
+                           return launch_probabilities(s->d, s->dt, s->n, nullptr, 0, part, part + red, s->st);
                        },
                        "sampling chunk sums");
     if (st != QS_OK) return st;

@@ -78,6 +78,9 @@ struct SampleReq {
 hipError_t launch_sample_chunks(const void* psi, int dt, int n, const SampleReq* req, int64_t shots, uint64_t* out,
                                 hipStream_t st);
 uint64_t reduce_scratch_doubles(int n, int m);
+// The pass-1 partials of launch_probabilities (2^m outcomes x chunks, at the
+// start of `part`); with m = 0 one per chunk of min(4096, 2^n) amplitudes.
+uint64_t reduce_partials(int n, int m);
 // The fixed per-device reduction scratch of the no-allocation entry points:
 // its address on device `dev` (which must be current; resolved once per
 // device, then cached) and its size in doubles.

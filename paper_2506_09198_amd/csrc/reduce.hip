@@ -13,7 +13,11 @@
 //           writes part[o * nch + chunk] for the 2^(low) outcomes o of oh.
 //           Blocks are numbered chunk-major (the patterns oh of one chunk are
 //           consecutive blocks);
-//   pass 2: one block per outcome sums part[o * nch .. + nch) the same way.
+//   pass 2: one block per outcome sums part[o * nch .. + nch) the same way;
+//           with more than 4096 partials per outcome, blocks first sum
+//           consecutive runs of 4096 of them (a level of 2^m x nch / 4096
+//           partials after the first level), and one block per outcome sums
+//           those.
 #include <cstring>
 #include <mutex>
 
@@ -23,10 +27,11 @@ namespace qs {
 
 // Device scratch for callers that cannot allocate (qs_probabilities_noalloc):
 // the per-chunk partial sums of one reduction go here instead of into a
-// buffer the library allocates.  2^22 doubles (32 MiB) cover every state the
-// library takes (n <= 34) for m <= 22 measured qubits.  Each GPU holds its own
+// buffer the library allocates.  2^22 + 2^12 doubles (32 MiB + 32 KiB: the
+// chunk partials and the second level of the final sum) cover every state
+// the library takes (n <= 34) for m <= 22 measured qubits.  Each GPU holds its own
 // copy until the process ends; calls that overlap on one GPU share it and race.
-constexpr uint64_t kNoAllocScratchDoubles = 1ull << 22;
+constexpr uint64_t kNoAllocScratchDoubles = (1ull << 22) + (1ull << 12);
 static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
 
 namespace {
@@ -37,6 +42,8 @@ void* g_scratch_dev[kMaxDevices] = {};
 
 constexpr int kRT = 256;        // threads per reduction block
 constexpr int kChunkLog2 = 12;  // CH = 4096 rest indices per block
+constexpr int kU = 8;           // loads a lane issues before summing them
+constexpr int kSegLog2 = 12;    // partials one block of the final sum reads at most
 
 // Measured qubits split by position: those at bit 6 or above ("high") are
 // fixed per block (inserted into the counter), those below ("low") are lane
@@ -79,13 +86,25 @@ k_prob_chunks(const V* __restrict__ psi, uint64_t rest_per_outcome, uint64_t ch,
             obits |= 1ull << mq.hq[i];
             ohout |= 1ull << mq.hj[i];
         }
+    // kU loads in flight per lane before they are summed, in the same order
+    // (r = tid, tid + kRT, ...) as one at a time; missing elements add +0
     double acc = 0.0;
     const uint64_t r0 = chunk * ch;
-    for (uint64_t r = tid; r < ch; r += kRT) {
-        const uint64_t rr = r0 + r;
-        if (rr < rest_per_outcome) {
-            const V a = psi[ins_bits(rr, ip) | obits];
-            const double x = (double)a.x, y = (double)a.y;
+    for (uint64_t r = tid; r < ch; r += (uint64_t)kRT * kU) {
+        V a[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t ru = r + (uint64_t)u * kRT;
+            if (ru < ch && r0 + ru < rest_per_outcome) {
+                a[u] = psi[ins_bits(r0 + ru, ip) | obits];
+            } else {
+                a[u].x = 0;
+                a[u].y = 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const double x = (double)a[u].x, y = (double)a[u].y;
             acc += x * x + y * y;
         }
     }
@@ -108,15 +127,51 @@ k_prob_chunks(const V* __restrict__ psi, uint64_t rest_per_outcome, uint64_t ch,
     }
 }
 
+// Block o sums part[o * nch .. + nch): lane t the partials t, t + kRT, ...
+// in order (kU loads in flight), then a fixed tree over the lanes.
 __global__ void __launch_bounds__(kRT)
 k_prob_final(const double* __restrict__ part, uint64_t nch, double* __restrict__ out)
 {
     __shared__ double sh[kRT];
     const uint64_t o = blockIdx.x;
     double acc = 0.0;
-    for (uint64_t c = threadIdx.x; c < nch; c += kRT) acc += part[o * nch + c];
+    for (uint64_t c = threadIdx.x; c < nch; c += (uint64_t)kRT * kU) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const uint64_t cu = c + (uint64_t)u * kRT;
+            v[u] = cu < nch ? part[o * nch + cu] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc += v[u];
+    }
     const double s = block_tree_sum(acc, sh);
     if (threadIdx.x == 0) out[o] = s;
+}
+
+// The final sum of `groups` runs of nch partials each (part[g * nch ..]) into
+// out[g]: one block per run, or, for runs longer than 2^kSegLog2, one block
+// per 2^kSegLog2-partial segment into lvl (groups x nch / 2^kSegLog2
+// doubles), then one block per run over its segments.
+hipError_t final_sums(const double* part, uint64_t groups, uint64_t nch, double* lvl, double* out, hipStream_t st)
+{
+    const uint64_t seg = 1ull << kSegLog2;
+    if (nch <= seg) {
+        hipLaunchKernelGGL(k_prob_final, dim3((unsigned)groups), dim3(kRT), 0, st, part, nch, out);
+        return hipGetLastError();
+    }
+    const uint64_t per = nch / seg; // nch is a power of two
+    hipLaunchKernelGGL(k_prob_final, dim3((unsigned)(groups * per)), dim3(kRT), 0, st, part, seg, lvl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prob_final, dim3((unsigned)groups), dim3(kRT), 0, st, (const double*)lvl, per, out);
+    return hipGetLastError();
+}
+
+// Doubles of the second level for `groups` runs of nch partials.
+uint64_t level_doubles(uint64_t groups, uint64_t nch)
+{
+    return nch > (1ull << kSegLog2) ? groups * (nch >> kSegLog2) : 0;
 }
 
 // Pauli-string expectation, pass 1.  Terms (x != 0): pairs (k0, k1 = k0 ^ x)
@@ -132,23 +187,54 @@ k_pauli_chunks(const V* __restrict__ psi, uint64_t nterms, uint64_t ch, uint64_t
     __shared__ double sh[kRT];
     const uint64_t chunk = blockIdx.x;
     const uint64_t lowm = (1ull << b) - 1;
+    // kU terms' loads in flight per lane, summed in the order r = tid,
+    // tid + kRT, ... as one at a time (missing terms add zeros)
     double ar = 0.0, ai = 0.0;
-    for (uint64_t r = threadIdx.x; r < ch; r += kRT) {
-        const uint64_t t = chunk * ch + r;
-        if (t >= nterms) continue;
+    for (uint64_t r = threadIdx.x; r < ch; r += (uint64_t)kRT * kU) {
         if (x == 0) {
-            const V a = psi[t];
-            const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-            ar += (__popcll(t & z) & 1) ? -p : p;
+            V a[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint64_t t = chunk * ch + r + (uint64_t)u * kRT;
+                if (r + (uint64_t)u * kRT < ch && t < nterms) {
+                    a[u] = psi[t];
+                } else {
+                    a[u].x = 0;
+                    a[u].y = 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint64_t t = chunk * ch + r + (uint64_t)u * kRT;
+                const double p = (double)a[u].x * (double)a[u].x + (double)a[u].y * (double)a[u].y;
+                ar += (__popcll(t & z) & 1) ? -p : p;
+            }
         } else {
-            const uint64_t k0 = ((t >> b) << (b + 1)) | (t & lowm), k1 = k0 ^ x;
-            const V a0 = psi[k0], a1 = psi[k1];
-            const double x0 = a0.x, y0 = a0.y, x1 = a1.x, y1 = a1.y;
-            // conj(a1) a0 and conj(a0) a1 = conj of the first
-            const double pr = x1 * x0 + y1 * y0, pi = x1 * y0 - y1 * x0;
-            const double s0 = (__popcll(k0 & z) & 1) ? -1.0 : 1.0, s1 = (__popcll(k1 & z) & 1) ? -1.0 : 1.0;
-            ar += s0 * pr + s1 * pr;
-            ai += s0 * pi - s1 * pi;
+            V a0[kU], a1[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint64_t t = chunk * ch + r + (uint64_t)u * kRT;
+                if (r + (uint64_t)u * kRT < ch && t < nterms) {
+                    const uint64_t k0 = ((t >> b) << (b + 1)) | (t & lowm);
+                    a0[u] = psi[k0];
+                    a1[u] = psi[k0 ^ x];
+                } else {
+                    a0[u].x = 0;
+                    a0[u].y = 0;
+                    a1[u] = a0[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const uint64_t t = chunk * ch + r + (uint64_t)u * kRT;
+                const uint64_t k0 = ((t >> b) << (b + 1)) | (t & lowm), k1 = k0 ^ x;
+                const double x0 = a0[u].x, y0 = a0[u].y, x1 = a1[u].x, y1 = a1[u].y;
+                // conj(a1) a0 and conj(a0) a1 = conj of the first
+                const double pr = x1 * x0 + y1 * y0, pi = x1 * y0 - y1 * x0;
+                const double s0 = (__popcll(k0 & z) & 1) ? -1.0 : 1.0, s1 = (__popcll(k1 & z) & 1) ? -1.0 : 1.0;
+                ar += s0 * pr + s1 * pr;
+                ai += s0 * pi - s1 * pi;
+            }
         }
     }
     const double sr = block_tree_sum(ar, sh);
@@ -237,11 +323,15 @@ hipError_t launch_pauli_expect(const void* psi, int dt, int n, uint64_t x, uint6
                            nterms, ch, nch, x, z, b, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prob_final, dim3(2), dim3(kRT), 0, st, part, nch, dev_out);
-    return hipGetLastError();
+    // real sums part[0, nch), imaginary part[nch, 2 nch); second level after them
+    return final_sums(part, 2, nch, part + 2 * nch, dev_out, st);
 }
 
-uint64_t pauli_scratch_doubles(int n) { return 2 * (((1ull << n) + 4095) / 4096) + 2; }
+uint64_t pauli_scratch_doubles(int n)
+{
+    const uint64_t nch = ((1ull << n) + 4095) / 4096; // the most any Pauli string needs
+    return 2 * nch + level_doubles(2, nch) + 2;
+}
 
 hipError_t launch_sample_chunks(const void* psi, int dt, int n, const SampleReq* req, int64_t shots, uint64_t* out,
                                 hipStream_t st)
@@ -276,12 +366,20 @@ hipError_t noalloc_scratch(int dev, double** ptr, uint64_t* doubles)
     return hipSuccess;
 }
 
-uint64_t reduce_scratch_doubles(int n, int m)
+// Chunks per outcome of launch_probabilities (its pass-1 partials are 2^m x
+// this many, chunk-major within each outcome).
+static uint64_t chunks_per_outcome(int n, int m)
 {
     const int rest = n - m;
     const int chl = rest < kChunkLog2 ? rest : kChunkLog2;
-    const uint64_t nch = 1ull << (rest - chl);
-    return (1ull << m) * nch;
+    return 1ull << (rest - chl);
+}
+
+uint64_t reduce_partials(int n, int m) { return (1ull << m) * chunks_per_outcome(n, m); }
+
+uint64_t reduce_scratch_doubles(int n, int m)
+{
+    return reduce_partials(n, m) + level_doubles(1ull << m, chunks_per_outcome(n, m));
 }
 
 hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m, double* part,
@@ -320,8 +418,8 @@ hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubit
                            1ull << rest, ch, nch, ip, mq, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_prob_final, dim3(1u << m), dim3(kRT), 0, st, part, nch, dev_out);
-    return hipGetLastError();
+    // second level after the 2^m x nch partials, as reduce_scratch_doubles
+    return final_sums(part, 1ull << m, nch, part + (1ull << m) * nch, dev_out, st);
 }
 
 } // namespace qs
