@@ -571,6 +571,11 @@ qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
  *   tile_waves4       [QS_TILE_W4]        tile passes of 2^11 amplitudes without k >= 3 ops:
  *                                         1 (default) = the kernel held to 4 waves per SIMD,
  *                                         0 = the kernel the compiler sizes (3 waves)
+ *   reduce_xcd_order  [QS_RED_XCD]        chunk order of the norm, marginal and Pauli reductions:
+ *                                         0 = built-in rule (XCD-contiguous for the norm, sampling
+ *                                         and Pauli strings on states of 512 MiB and more, workgroup
+ *                                         order for marginals), 1 = workgroup order, 2 = each of
+ *                                         the 8 XCDs reads a contiguous eighth of the chunks
  * qs_tunable_set stores `value` (value < 0: back to the default / environment
  * value); QS_ERR_ARG for an unknown name or a value outside the knob's range.
  * Knobs are process-wide and may be changed from any thread; a launch being

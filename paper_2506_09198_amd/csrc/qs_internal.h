@@ -115,6 +115,7 @@ enum Tun {
                        //   128-byte line bit, 2: all) instead of exchanged by shuffles
     T_DIAG_SLOTS,      // diagonal kernel: slots per lane (0 = built-in: 4)
     T_TILE_W4,         // lean 2^11 tile passes held to 128 VGPRs (4 waves per SIMD)
+    T_RED_XCD,         // reduction chunk order: 0 rule, 1 block order, 2 XCD-contiguous
     T_COUNT
 };
 int64_t tun(Tun id);

@@ -43,6 +43,7 @@ const TunDef kTun[T_COUNT] = {
     {"gate_low_in_regs", "QS_GATE_LOW_HIGH", 1, 0, 2},
     {"diag_slots", "QS_DIAG_SLOTS", 0, 0, 8},
     {"tile_waves4", "QS_TILE_W4", 1, 0, 1},
+    {"reduce_xcd_order", "QS_RED_XCD", 0, 0, 2},
 };
 
 std::atomic<int64_t> g_val[T_COUNT];

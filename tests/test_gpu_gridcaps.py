@@ -245,3 +245,29 @@ def test_tile_waves4_bitwise(qs, dt, name):
         _check(got, want, dt, f"{name} tile_waves4={w4}")
         outs.append(got)
     assert outs[0].tobytes() == outs[1].tobytes()
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_reduction_block_order_bitwise(qs, dt):
+    """The reductions with their chunks in workgroup order and in XCD-
+    contiguous order: the same partial sums in the same places, so bitwise
+    the same marginals, norm and Pauli expectations, and both within the FP64
+    bar of the oracle."""
+    n = 17
+    psi0 = W.random_state(n, 71)
+    sets = [[], [0, 1, 2], [n - 3, n - 2, n - 1], [0, 5, 9, 14], list(range(8))]
+    paulis = [(0, (1 << n) - 1), (0x5555 & ((1 << n) - 1), 0x2AAA & ((1 << n) - 1))]
+    outs = []
+    for order in (1, 2):
+        with qs.tunables(reduce_xcd_order=order):
+            with qs.State.create(n, dt) as s:
+                s.upload(psi0 if dt == 2 else psi0.astype(np.complex64))
+                host = s.download().astype(np.complex128)
+                res = [s.probabilities(q) for q in sets if q] + [np.array([s.norm()])]
+                res += [np.array([qs.qs_expect_pauli(s.h, x, z)]) for x, z in paulis]
+        for q, r in zip([q for q in sets if q], res):
+            want = oracle.probabilities(n, host, q)
+            assert float(np.max(np.abs(r - want))) <= 1e-13, (order, q)
+        outs.append(res)
+    for a, b in zip(outs[0], outs[1]):
+        assert a.tobytes() == b.tobytes()
