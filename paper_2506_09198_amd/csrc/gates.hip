@@ -92,6 +92,7 @@ struct GateArgs {
     uint32_t lowmask;    // lane bits of the low targets
     int32_t slog;        // log2 of the slot spread S
     int32_t xcd;         // chunk order: 0 = block order, 1 = each XCD a contiguous eighth
+    int32_t skip_fail;   // lanes whose in-line controls fail skip their stores (64-byte pieces)
     uint64_t roff[4];    // register r -> index offset (high-target bits of r)
     int32_t srcl[4];     // member m -> lane bits of its low targets
     int32_t hreg[4];     // member m -> register holding it
@@ -131,6 +132,14 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
     const uint64_t b = ga.xcd ? (bb & 7) * (ga.nblocks >> 3) + (bb >> 3) : bb;
     const uint64_t base = (b / spb) * (S * PPL) + (b % spb) * 256 + threadIdx.x;
 
+    // Controls inside a 128-byte line are tested per lane.  A lane whose
+    // control bits fail stores its amplitudes back unchanged, bit for bit, so
+    // every store instruction still writes whole lines, unless the changed
+    // amplitudes come in aligned 64-byte halves of lines (skip_fail): measured
+    // on MI355X, lines written in 16- or 32-byte pieces cost 10-18 % more than
+    // whole lines, 64-byte halves about 3 % less.
+    const uint32_t myctl = lane & ga.cm_lo;
+    const bool cok = myctl == ga.cv_lo;
     double2 x[PPL][NR];
     uint64_t idx[PPL];
     bool live[PPL];
@@ -159,7 +168,6 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
         }
         rr[r] = v;
     }
-    const uint32_t myctl = lane & ga.cm_lo;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         double2 mem[D];
@@ -175,7 +183,7 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
                 mem[m].y = __shfl(v.y, src, 64);
             }
         }
-        if (live[p] && myctl == ga.cv_lo) {
+        if (live[p]) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 double sr = 0.0, si = 0.0;
@@ -185,7 +193,10 @@ __global__ void __launch_bounds__(256) k_gate(typename CT<R>::V* __restrict__ ps
                     sr += ur * mem[m].x - ui * mem[m].y;
                     si += ur * mem[m].y + ui * mem[m].x;
                 }
-                gst<NT>(psi + (idx[p] | ga.roff[r]), st2<V>(make_double2(sr, si)));
+                // plain double selects (a select of double2 values is lowered
+                // through a per-lane indexed stack copy)
+                const double ox = cok ? sr : x[p][r].x, oy = cok ? si : x[p][r].y;
+                if (cok || !ga.skip_fail) gst<NT>(psi + (idx[p] | ga.roff[r]), st2<V>(make_double2(ox, oy)));
             }
         }
     }
@@ -375,10 +386,18 @@ static hipError_t apply_gate_t(void* psi, int n, int K, const int* t, const doub
     ga.ip = make_insert_plan(himask | cm_ins);
     const int nins = nh + __builtin_popcountll(cm_ins);
     ga.C = 1ull << (n - nins);
+    // Lanes whose in-line controls fail skip their stores only when every
+    // such control leaves aligned runs of at least 64 bytes (the lowest
+    // in-line control at or above bit log2(64 / sizeof amplitude)); otherwise
+    // they store their values back and every line is written whole.
+    {
+        const uint64_t cm_line = cm & linemask;
+        const int min_run_bit = sizeof(R) == 8 ? 2 : 3; // 64-byte runs
+        ga.skip_fail = (cm_line != 0 && __builtin_ctzll(cm_line) >= min_run_bit) ? 1 : 0;
+    }
     // Non-temporal stores only when each store instruction writes whole lines:
-    // no lane skips its store (no per-amplitude controls), no register target
-    // inside a line, and full waves.
-    const bool nt = tun(T_NT) && ga.cm_lo == 0 && (reg_low & linemask) == 0 && ga.C >= 64;
+    // no register target inside a line, no skipped stores, and full waves.
+    const bool nt = tun(T_NT) && (reg_low & linemask) == 0 && !ga.skip_fail && ga.C >= 64;
     const uint64_t sb = (1ull << n) * sizeof(R) * 2;
     if (K == 1)
         return nh == 0 ? launch_gate_k<R, 1, 0>(psi, ga, nt, sb, st) : launch_gate_k<R, 1, 1>(psi, ga, nt, sb, st);

@@ -231,6 +231,37 @@ def test_controls_leave_other_amplitudes_bitwise(qs):
 
 
 @pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("ctl", [(0,), (1,), (2,), (3,), (1, 2), (2, 3), (0, 11)])
+def test_inline_controls_bitwise(qs, dt, ctl):
+    """Controls on bits inside a 128-byte line (tested per lane; the lanes
+    that fail write their amplitudes back or skip the store, by run size):
+    amplitudes whose controls fail stay bitwise equal, the others match the
+    oracle, for 1q and 2q gates with high and low targets."""
+    n = 14
+    rng = np.random.default_rng(90 + sum(ctl))
+    psi0 = _rand(n, 5)
+    start = psi0 if dt == 2 else psi0.astype(np.complex64).astype(np.complex128)
+    cm = sum(1 << c for c in ctl)
+    cv = cm & ~(1 << ctl[0]) if len(ctl) > 1 else cm  # first control on |0>, the rest on |1>
+    free = [q for q in range(n) if q not in ctl]
+    for tg in ([free[0]], [free[-1]], [free[0], free[1]], [free[1], free[-1]], [free[-2], free[-1]]):
+        u = W.haar_unitary(1 << len(tg), rng)
+        s = _state(qs, n, dt, psi0)
+        if len(tg) == 1:
+            qs.qs_apply_1q(s.h, tg[0], u, cm, cv)
+        else:
+            qs.qs_apply_2q(s.h, tg[0], tg[1], u, cm, cv)
+        got = s.download()
+        s.close()
+        want = start.copy()
+        oracle.apply_op(n, want, tuple(tg), u, cm, cv)
+        keep = (np.arange(1 << n) & cm) != cv
+        base = psi0 if dt == 2 else psi0.astype(np.complex64)
+        assert np.array_equal(got[keep], base[keep]), (tg, ctl)
+        _check(got, want, dt, f"targets {tg} controls {ctl}")
+
+
+@pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("n", [1, 5, 13, 18])
 def test_probabilities(qs, dt, n):
     psi0 = _rand(n, 21)
