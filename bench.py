@@ -69,6 +69,8 @@ def _args():
                    help="serve: workgroup cap of the large circuit's passes (0 = library default), which "
                         "leaves compute units to the request stream")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--tune-gates", action="store_true",
+                   help="sweep: autotune the per-gate schedules on the state (qs_tune_gates) before the warm-up")
     p.add_argument("--no-side", action="store_true",
                    help="sweep: skip the compact batch and serving legs that follow the timed sweep")
     p.add_argument("--cpu-n", type=int, default=0, help="qubits of the oracle sample (0 = workload default)")
@@ -400,6 +402,11 @@ def run_sweep(a, qs, torch, W):
     psi = _random_state_torch(torch, n, tdt, 2)
     torch.cuda.synchronize()
     s = qs.State.from_torch(psi)
+    tuned = None
+    if a.tune_gates and a.mode == "pergate":
+        t0 = time.perf_counter()
+        tuned = {"schedules": qs.qs_tune_gates(s.h), "seconds": time.perf_counter() - t0}
+        _log(f"sweep: gate schedules tuned in {tuned['seconds']:.1f} s: {tuned['schedules']}")
 
     def step():
         if a.mode == "planned":
@@ -450,6 +457,7 @@ def run_sweep(a, qs, torch, W):
                     for k, d in kinds.items()},
         "event_coverage": sum(d["ms"] for d in kinds.values()) / (elapsed * 1e3),
         "step_device_ms": _step_stats(recs, len(gates), a.steps),
+        "gate_schedules_tuned": tuned,
         "norm_minus_1": norm - 1.0,
         "per_target_gbs": per_target,
         "inplace_ceiling": ceiling,

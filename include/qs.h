@@ -534,6 +534,48 @@ qs_status qs_trace_read(qs_state s, qs_trace_rec* out, int max, int* count);
  * QS_ERR_ARG for other values. */
 qs_status qs_probe_inplace(qs_state s, int slots, int spread_log2);
 
+/* ------------------------------------------------------------------ schedule autotuner */
+
+/* Gate classes of the per-gate kernel's memory schedule: 0 = every target
+ * inside a 128-byte line (members exchanged by shuffles), 1 = one-qubit gate
+ * on a target at bit 6 or above, 2 = two-qubit gate with one such target, 3 =
+ * two-qubit gate with both. */
+#define QS_GATE_CLASSES 4
+
+/* A tuned schedule: slots per lane (1, 2, 4 or 8), workgroups per CU (0 = as
+ * many as fit), chunk order (1 = each of the 8 XCDs walks a contiguous
+ * eighth), and the rate the timing measured (GB/s of bytes read and written
+ * by the class's representative gates). */
+typedef struct {
+    int32_t cls;
+    int32_t slots;
+    int32_t wg_per_cu;
+    int32_t xcd;
+    double gbs;
+    int32_t from_cache; /* 1 = read from the cache file, 0 = timed by this call */
+} qs_gate_sched;
+
+/* Autotune the per-gate kernel's memory schedule for the state's amplitude
+ * type and qubit count (the survey's autotune cache; the paper's counterpart
+ * is choosing its kernel variants per machine, Section II).  For each class,
+ * every candidate (slots 1/2/4, and 8 for class 0; 0, 2, 3, 4, 6 or 8
+ * workgroups per CU; either chunk order) is timed on `s` with Pauli X gates on
+ * representative targets, each applied twice, so every amplitude ends as it
+ * started (only the sign of an exactly zero amplitude may change).  The
+ * fastest becomes the process-wide schedule for gates of that class on states
+ * of this type and size; explicit launch knobs (qs_tunable_set) still take
+ * precedence.  With `cache_path` (host path, may be NULL): classes found
+ * there under this device's key (architecture, CU count, type, n) are loaded
+ * instead of timed, and newly timed ones are written back, one JSON object
+ * per line, the file replaced atomically.  out[0..max_out) receives the
+ * schedules by class (NULL allowed), *n_out their number.  Blocking; takes a
+ * few seconds per class at 30 qubits.  QS_ERR_ARG for n < 12 or an
+ * unwritable cache file.  Schedules never change results (bitwise). */
+qs_status qs_tune_gates(qs_state s, const char* cache_path, qs_gate_sched* out, int max_out, int* n_out);
+
+/* Drop every tuned schedule: gates use the built-in table again. */
+qs_status qs_tune_gates_reset(void);
+
 /* ------------------------------------------------------------------ launch knobs */
 
 /* Launch knobs that change how work is spread over the GPU, never what is

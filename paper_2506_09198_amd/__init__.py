@@ -58,6 +58,14 @@ class _TuneEntry(ctypes.Structure):
                 ("persist_max", ctypes.c_int32), ("device_ms", ctypes.c_double)]
 
 
+class _GateSched(ctypes.Structure):
+    _fields_ = [("cls", ctypes.c_int32), ("slots", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("xcd", ctypes.c_int32), ("gbs", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+
+
+QS_GATE_CLASSES = 4
+
+
 class _BatchStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("passes", ctypes.c_uint64), ("device_ms", ctypes.c_double),
                 ("class_ms", ctypes.c_double * 3), ("class_circuits", ctypes.c_uint32 * 3), ("rsv", ctypes.c_uint32),
@@ -154,6 +162,8 @@ def _load():
         "qs_trace_enable": ([vp, i32], i32),
         "qs_trace_read": ([vp, vp, i32, ctypes.POINTER(i32)], i32),
         "qs_probe_inplace": ([vp, i32, i32], i32),
+        "qs_tune_gates": ([vp, ctypes.c_char_p, ctypes.POINTER(_GateSched), i32, ctypes.POINTER(i32)], i32),
+        "qs_tune_gates_reset": ([], i32),
         "qs_tunable_set": ([ctypes.c_char_p, ctypes.c_int64], i32),
         "qs_tunable_get": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)], i32),
     }
@@ -615,6 +625,21 @@ def qs_probe_inplace(s: int, slots: int = 4, spread_log2: int = 11):
     """Enqueue the in-place read-modify-write ceiling probe over the state's
     buffer (leaves it unchanged; timed through the trace as kind "probe")."""
     _check(lib.qs_probe_inplace(ctypes.c_void_p(s), int(slots), int(spread_log2)))
+
+
+def qs_tune_gates(s: int, cache_path: str | None = None) -> list:
+    """Autotune the per-gate kernel's schedule for this state's type and size
+    (see include/qs.h); returns one dict per gate class."""
+    out = (_GateSched * QS_GATE_CLASSES)()
+    n = ctypes.c_int(0)
+    path = cache_path.encode() if cache_path else None
+    _check(lib.qs_tune_gates(ctypes.c_void_p(s), path, out, QS_GATE_CLASSES, ctypes.byref(n)))
+    return [{"cls": int(r.cls), "slots": int(r.slots), "wg_per_cu": int(r.wg_per_cu), "xcd": int(r.xcd),
+             "gbs": float(r.gbs), "from_cache": bool(r.from_cache)} for r in out[:n.value]]
+
+
+def qs_tune_gates_reset() -> None:
+    _check(lib.qs_tune_gates_reset())
 
 
 # ------------------------------------------------------------------ convenience

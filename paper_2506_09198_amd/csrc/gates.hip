@@ -277,6 +277,15 @@ static GateSched gate_sched(uint64_t state_bytes)
         g.wg = 0;
         g.xcd = 0;
     }
+    // a schedule tuned for this type, size and class (qs_tune_gates)
+    constexpr int cls = NH == 0 ? 0 : (NH == 1 ? (K == 1 ? 1 : 2) : 3);
+    GateSchedOverride o;
+    const int n = 63 - __builtin_clzll(state_bytes / (2 * sizeof(R)));
+    if (gate_sched_override(C128 ? QS_C128 : QS_C64, n, cls, &o)) {
+        g.ppl = o.ppl;
+        g.wg = o.wg;
+        g.xcd = o.xcd;
+    }
     const int ppl_k = (int)tun(NH == 0 ? T_PPL_H0 : (NH == 1 ? T_PPL_H1 : T_PPL_H2));
     if (ppl_k > 0) g.ppl = ppl_k;
     const int wg_k = (int)tun(T_GATE_WG_PER_CU);

@@ -88,6 +88,13 @@ hipError_t noalloc_scratch(int dev, double** ptr, uint64_t* doubles);
 hipError_t launch_probabilities(const void* psi, int dt, int n, const int* qubits, int m,
                                 double* part, double* dev_out, hipStream_t st);
 
+// Tuned per-gate schedules (gate_tune.cpp): an override of the built-in
+// table for (amplitude type, qubit count, gate class), if one is installed.
+struct GateSchedOverride {
+    int ppl, wg, xcd;
+};
+bool gate_sched_override(int dt, int n, int cls, GateSchedOverride* o);
+
 // In-place read-modify-write of `bytes` (16-byte words, each XORed with
 // `mask`): the memory ceiling probe.  slots 1/2/4/8, slog 8..30.
 hipError_t launch_probe_inplace(void* dev, uint64_t bytes, int slots, int slog, uint64_t mask, hipStream_t st);

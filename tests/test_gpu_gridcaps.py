@@ -271,3 +271,60 @@ def test_reduction_block_order_bitwise(qs, dt):
         outs.append(res)
     for a, b in zip(outs[0], outs[1]):
         assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_gate_schedule_tuner_and_cache(qs, dt, tmp_path):
+    """qs_tune_gates times every schedule candidate per gate class on the
+    caller's state and leaves the state bitwise as it was; the chosen
+    schedules are installed (gates still match the oracle and equal the
+    built-in schedule's results bit for bit), written to the cache file and
+    read back from it by the next call without timing."""
+    import json
+
+    n = 16
+    cache = str(tmp_path / "gate_sched.jsonl")
+    psi0 = W.random_state(n, 81)
+    base = psi0 if dt == 2 else psi0.astype(np.complex64)
+    rng = np.random.default_rng(82)
+    gates = _pergate_list(n, rng)
+    want = psi0.copy() if dt == 2 else psi0.astype(np.complex64).astype(np.complex128)
+    for tg, u, cm, cv in gates:
+        oracle.apply_op(n, want, tg, u, cm, cv)
+
+    def run_gates(s):
+        for tg, u, cm, cv in gates:
+            if len(tg) == 1:
+                qs.qs_apply_1q(s.h, tg[0], u, cm, cv)
+            else:
+                qs.qs_apply_2q(s.h, tg[0], tg[1], u, cm, cv)
+        return s.download()
+
+    qs.qs_tune_gates_reset()
+    try:
+        with qs.State.create(n, dt) as s:
+            s.upload(base)
+            ref = run_gates(s)  # built-in schedules
+        with qs.State.create(n, dt) as s:
+            s.upload(base)
+            rows = qs.qs_tune_gates(s.h, cache)
+            assert s.download().tobytes() == base.tobytes()  # tuning left the state as it was
+            assert [r["cls"] for r in rows] == [0, 1, 2, 3]
+            assert all(r["slots"] in (1, 2, 4, 8) and r["gbs"] > 0 and not r["from_cache"] for r in rows)
+            assert all(r["slots"] != 8 for r in rows[1:])
+            got = run_gates(s)
+        _check(got, want, dt, "tuned schedules")
+        assert got.tobytes() == ref.tobytes()
+        lines = [json.loads(l) for l in open(cache)]
+        assert len(lines) == 4 and len({l["key"] for l in lines}) == 1 and f"n{n}" in lines[0]["key"]
+        qs.qs_tune_gates_reset()
+        with qs.State.create(n, dt) as s:
+            again = qs.qs_tune_gates(s.h, cache)
+        assert all(r["from_cache"] for r in again)
+        assert [(r["slots"], r["wg_per_cu"], r["xcd"]) for r in again] == \
+            [(r["slots"], r["wg_per_cu"], r["xcd"]) for r in rows]
+        with pytest.raises(qs.QSError):
+            with qs.State.create(8, dt) as s:
+                qs.qs_tune_gates(s.h, None)
+    finally:
+        qs.qs_tune_gates_reset()
