@@ -328,3 +328,25 @@ def test_gate_schedule_tuner_and_cache(qs, dt, tmp_path):
                 qs.qs_tune_gates(s.h, None)
     finally:
         qs.qs_tune_gates_reset()
+
+
+@pytest.mark.parametrize("dt", [2, 1])
+def test_restore_pass_run_lengths(qs, dt):
+    """The qubit-order restore pass with runs of 2^4, 2^5 and (complex64)
+    2^6 amplitudes: each against the oracle and bitwise the same (a pure
+    permutation moves every amplitude unchanged)."""
+    n = 17
+    c = W.qft(n, 31337)
+    ops, mats = c.arrays()
+    assert len(qs.qs_plan_restore(n, dt, ops, mats)) >= 1
+    want = oracle.run_circuit(c)
+    outs = []
+    for run in ((4, 5) if dt == 2 else (4, 5, 6)):
+        with qs.tunables(perm_run_log2=run):
+            with qs.State.create(n, dt) as s:
+                s.init_basis(c.init_basis)
+                s.run(ops, mats, mode=0)
+                got = s.download()
+        _check(got, want, dt, f"qft17 restore runs 2^{run}")
+        outs.append(got)
+    assert all(o.tobytes() == outs[0].tobytes() for o in outs[1:])
