@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqs.so")
+# QS_LIB selects another build of the same library (e.g. the host-AddressSanitizer
+# build, libqs_asan.so); there is no fallback when it is missing.
+LIB_PATH = os.environ.get("QS_LIB") or os.path.join(_HERE, "libqs.so")
 
 QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_DEVICE, QS_ERR_BUSY, QS_ERR_UNSUPPORTED, QS_ERR_CANCELLED, \
     QS_ERR_TIMEOUT = range(8)

@@ -3,6 +3,15 @@
 Each source compiles to an object under ``_build/`` (in parallel), then one
 link produces ``paper_2506_09198_amd/libqs.so``.  Packed FP32 VALU forms are
 disabled in device code (``-packed-fp32-ops``).
+
+``python -m paper_2506_09198_amd._build --asan`` builds a second library,
+``libqs_asan.so`` (objects under ``_build_asan/``), whose host code is
+compiled with AddressSanitizer (device code unchanged).  The CPU tests run
+against it with
+
+    QS_LIB=paper_2506_09198_amd/libqs_asan.so ASAN_OPTIONS=detect_leaks=0 \
+    LD_PRELOAD=$(/opt/rocm/llvm/bin/clang -print-file-name=libclang_rt.asan-x86_64.so) \
+    python -m pytest tests -m "not gpu"
 """
 from __future__ import annotations
 
@@ -38,13 +47,22 @@ _NOSINK = ["-mllvm", "-simplifycfg-sink-common=false", "-mllvm", "-simplifycfg-h
 EXTRA = {"tile.hip": _NOSINK, "tile_batch.hip": _NOSINK, "tile_serve.hip": _NOSINK}
 
 
-def _compile(src: str) -> str:
+# AddressSanitizer for host code only: each -fsanitize= goes to the host pass.
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+ASAN_LINK = ["-fno-gpu-sanitize", "-fsanitize=address"]
+BUILD_ASAN = os.path.join(ROOT, "_build_asan")
+LIB_ASAN = os.path.join(PKG, "libqs_asan.so")
+
+
+def _compile(src: str, asan: bool = False) -> str:
     base = os.path.splitext(os.path.basename(src))[0]
-    obj = os.path.join(BUILD, base + ".o")
+    obj = os.path.join(BUILD_ASAN if asan else BUILD, base + ".o")
+    extra = ASAN_HOST if asan else []
     if src.endswith(".hip"):
-        cmd = [hipcc(), *COMMON, *DEVICE, *EXTRA.get(os.path.basename(src), []), "-x", "hip", "-c", src, "-o", obj]
+        cmd = [hipcc(), *COMMON, *DEVICE, *EXTRA.get(os.path.basename(src), []), *extra, "-x", "hip", "-c", src,
+               "-o", obj]
     else:
-        cmd = [hipcc(), *COMMON, "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", "-x", "c++", "-c", src,
+        cmd = [hipcc(), *COMMON, *extra, "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__", "-x", "c++", "-c", src,
                "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -58,22 +76,23 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(jobs: int | None = None, asan: bool = False) -> str:
+    os.makedirs(BUILD_ASAN if asan else BUILD, exist_ok=True)
     srcs = sorted(
         os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip") or f.endswith(".cpp")
     )
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+        objs = list(ex.map(lambda s: _compile(s, asan), srcs))
+    out = LIB_ASAN if asan else LIB
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *(ASAN_LINK if asan else []), *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(asan="--asan" in sys.argv[1:]))
