@@ -361,7 +361,7 @@ def reductions(qs, s, n, S, reps=3, seed=17):
 
 def _step_stats(recs, per_step, steps):
     """Device time of each timed step (sum of its launches' HIP-event times):
-    min and median over the steps, as the survey's timing rule asks."""
+    min and median over the steps."""
     if len(recs) < per_step * steps or steps < 1:
         return None
     ms = np.array([float(r) for r in recs["ms"][:per_step * steps]]).reshape(steps, per_step).sum(axis=1)
@@ -1012,7 +1012,7 @@ def main():
     a = _args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(the library runs on one GPU; sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -54,7 +54,7 @@ typedef enum {
     QS_ERR_OOM = 2,         /* device memory (or the configured budget) exhausted */
     QS_ERR_DEVICE = 3,      /* a HIP call failed; the handle is now failed */
     QS_ERR_BUSY = 4,        /* resource in use (e.g. batch not finished) */
-    QS_ERR_UNSUPPORTED = 5, /* valid request this build does not handle */
+    QS_ERR_UNSUPPORTED = 5, /* valid request the library does not handle */
     QS_ERR_CANCELLED = 6,
     QS_ERR_TIMEOUT = 7
 } qs_status;
@@ -556,8 +556,8 @@ typedef struct {
 } qs_gate_sched;
 
 /* Autotune the per-gate kernel's memory schedule for the state's amplitude
- * type and qubit count (the survey's autotune cache; the paper's counterpart
- * is choosing its kernel variants per machine, Section II).  For each class,
+ * type and qubit count (the paper's counterpart is choosing its kernel
+ * variants per machine, Section II).  For each class,
  * every candidate (slots 1/2/4, and 8 for class 0; 0, 2, 3, 4, 6 or 8
  * workgroups per CU; either chunk order) is timed on `s` with Pauli X gates on
  * representative targets, each applied twice, so every amplitude ends as it
