@@ -564,12 +564,14 @@ def run_circuits(a, qs, torch, W):
     head = "c64_tiles"
     variants = [(head, qs.QS_C64, 0, 0, a.steps, a.warmup)]
     if not a.only_head:
-        variants += [("c64_mfma5", qs.QS_C64, 0, 5, 1, 1), ("c128_tiles", qs.QS_C128, 0, 0, 1, 1),
-                     ("c128_mfma5", qs.QS_C128, 0, 5, 1, 1)]
+        variants += [("c64_mfma5", qs.QS_C64, 0, 5, 1, 1), ("c64_mfma5_fp32", qs.QS_C64, 0, 5, 1, 1),
+                     ("c128_tiles", qs.QS_C128, 0, 0, 1, 1), ("c128_mfma5", qs.QS_C128, 0, 5, 1, 1)]
     if not a.no_baselines and not a.only_head:
         variants.append(("c128_pergate", qs.QS_C128, 1, 0, 1, 0))
     res, traces, states = {}, {}, {}
     for name, dt, mode, fk, steps, warm in variants:
+        # FP32 matrix-core blocks (hi + bfloat16 lo) are a planner option
+        os.environ["QS_FUSE_FP32"] = "1" if name.endswith("_fp32") else "0"
         tdt = torch.complex128 if dt == qs.QS_C128 else torch.complex64
         for k, c in work.items():
             ops, mats = arrs[k]
@@ -607,6 +609,7 @@ def run_circuits(a, qs, torch, W):
             else:
                 del psi
         torch.cuda.synchronize()
+        os.environ["QS_FUSE_FP32"] = "0"
         if name == "c128_tiles":  # both precisions of each circuit are resident: compare them
             for k in work:
                 for v in (head, "c64_mfma5"):
@@ -687,11 +690,13 @@ def circuits_vs_oracle(a, qs, W, n):
     t_or = time.perf_counter() - t0
     out = {"n": n, "gates": len(ops), "oracle_s": t_or, "oracle_threads": oracle.num_threads()}
     for name, dt, mode, fk in (("c64_tiles", qs.QS_C64, 0, 0), ("c64_mfma5", qs.QS_C64, 0, 5),
-                               ("c128_tiles", qs.QS_C128, 0, 0), ("c128_mfma5", qs.QS_C128, 0, 5),
-                               ("c128_pergate", qs.QS_C128, 1, 0)):
+                               ("c64_mfma5_fp32", qs.QS_C64, 0, 5), ("c128_tiles", qs.QS_C128, 0, 0),
+                               ("c128_mfma5", qs.QS_C128, 0, 5), ("c128_pergate", qs.QS_C128, 1, 0)):
+        os.environ["QS_FUSE_FP32"] = "1" if name.endswith("_fp32") else "0"
         with qs.State.create(n, dt) as s:
             s.run(ops, mats, mode=mode, fuse_k=fk)
             got = s.download()
+        os.environ["QS_FUSE_FP32"] = "0"
         ov, nrm, err = 0j, 0.0, 0.0
         for i in range(0, got.size, 1 << 24):
             g = got[i:i + (1 << 24)].astype(np.complex128)

@@ -171,7 +171,10 @@ typedef struct {
                             inside each tile pass, runs of gates on at most that many tile
                             qubits are multiplied (FP64, host) into one dense block applied
                             with FP64 matrix cores (both amplitude types; tiles of at least
-                            fuse_k + 4 qubits) */
+                            fuse_k + 4 qubits).  With the environment variable
+                            QS_FUSE_FP32=1 at planning time, complex64 blocks use FP32
+                            matrix cores instead: the FP64 product split into an FP32 part
+                            and a bfloat16 remainder, each with its own accumulator */
     int32_t tile_qubits; /* qubits held in LDS per tile; 0 = default */
     int32_t max_blocks;  /* cap on the workgroups of each tile-pass launch (they stride over
                             the tiles); 0 = default (65536).  A lower cap leaves compute units

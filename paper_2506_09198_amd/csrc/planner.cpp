@@ -108,7 +108,17 @@ static void embed_op(const TileOp& t, const std::vector<double>& pool, const int
     }
 }
 
-static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_dense)
+// Round to the nearest bfloat16 (ties to even): the upper half of the FP32
+// bit pattern after rounding the lower half away.
+static uint16_t bf16_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_dense, bool fp32)
 {
     std::vector<TileOp> out;
     std::vector<int64_t> osrc;
@@ -132,25 +142,55 @@ static void fuse_pass(PlanPass& P, std::vector<double>& pool, int K, int min_den
             std::vector<cd> G((size_t)D * D, cd(0, 0));
             for (int i = 0; i < D; ++i) G[(size_t)i * D + i] = 1.0;
             for (size_t i : blk) embed_op(P.ops[i], pool, bq, K, G);
-            const int DR = 2 * D, RB = DR / 16, KS = DR / 4, NF = RB * KS;
-            std::vector<double> fr((size_t)NF * 64); // [q][lane][2], fragment f = 2q + j
-            for (int lane = 0; lane < 64; ++lane)
-                for (int rb = 0; rb < RB; ++rb)
-                    for (int ks = 0; ks < KS; ++ks) {
-                        const int row = 16 * rb + (lane % 16), col = 4 * ks + lane / 16;
-                        const cd u = G[(size_t)(row / 2) * D + col / 2];
-                        double v;
-                        if ((row & 1) == 0)
-                            v = (col & 1) == 0 ? u.real() : -u.imag();
-                        else
-                            v = (col & 1) == 0 ? u.imag() : u.real();
-                        const int f = rb * KS + ks;
-                        fr[((size_t)(f / 2) * 64 + lane) * 2 + (f % 2)] = v;
+            const int DR = 2 * D, RB = DR / 16, KS = DR / 4, NF = RB * KS, KB = KS / 4;
+            // the real embedding [[Ur, -Ui], [Ui, Ur]], interleaved rows and columns
+            auto areal = [&](int row, int col) {
+                const cd u = G[(size_t)(row / 2) * D + col / 2];
+                if ((row & 1) == 0) return (col & 1) == 0 ? u.real() : -u.imag();
+                return (col & 1) == 0 ? u.imag() : u.real();
+            };
+            std::vector<double> fr;
+            if (!fp32) {
+                fr.assign((size_t)NF * 64, 0.0); // [q][lane][2], fragment f = 2q + j
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int rb = 0; rb < RB; ++rb)
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const int f = rb * KS + ks;
+                            fr[((size_t)(f / 2) * 64 + lane) * 2 + (f % 2)] =
+                                areal(16 * rb + (lane % 16), 4 * ks + lane / 16);
+                        }
+            } else {
+                // FP32 form: hi = the FP32 rounding of each entry, as
+                // v_mfma_f32_16x16x4f32 A fragments ([f][lane] floats,
+                // fragment f = rb * KS + ks, lane l: row 16rb + l%16, column
+                // 4ks + l/16); lo = the remainder rounded to bfloat16,
+                // as v_mfma_f32_16x16x16bf16 A fragments ([rb * KB + kb][lane]
+                // x 4, lane l: row 16rb + l%16, columns 16kb + 4(l/16) + j).
+                std::vector<float> hi((size_t)NF * 64);
+                std::vector<uint16_t> lo((size_t)RB * KB * 64 * 4);
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const int row = 16 * rb + (lane % 16);
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const int f = rb * KS + ks;
+                            hi[(size_t)f * 64 + lane] = (float)areal(row, 4 * ks + lane / 16);
+                        }
+                        for (int kb = 0; kb < KB; ++kb)
+                            for (int j = 0; j < 4; ++j) {
+                                const double a = areal(row, 16 * kb + 4 * (lane / 16) + j);
+                                const float h = (float)a;
+                                lo[(((size_t)(rb * KB + kb) * 64 + lane) * 4) + j] = bf16_rne((float)(a - (double)h));
+                            }
                     }
+                fr.assign((hi.size() * 4 + lo.size() * 2 + 7) / 8, 0.0);
+                std::memcpy(fr.data(), hi.data(), hi.size() * 4);
+                std::memcpy((char*)fr.data() + hi.size() * 4, lo.data(), lo.size() * 2);
+            }
             TileOp t;
             std::memset(&t, 0, sizeof t);
             t.kind = TK_MFMA;
             t.k = K;
+            t.dclass = fp32 ? 1 : 0; // 1: FP32 hi + bfloat16 lo fragments
             for (int j = 0; j < K; ++j) t.p[j] = bq[j];
             size_t off = pool.size();
             pool.resize(off + fr.size() + 2);
@@ -775,7 +815,7 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
             P.updates += 1ull << (n - __builtin_popcountll(o.cmask));
         }
         if ((po.fuse_k == 4 || po.fuse_k == 5) && m >= po.fuse_k + 4)
-            fuse_pass(P, pool, po.fuse_k, po.fuse_min);
+            fuse_pass(P, pool, po.fuse_k, po.fuse_min, po.fuse_fp32 && po.dt == QS_C64);
         const int r = po.segments ? seg_reg_qubits(po.dt, m) : 0;
         if (r > 0) segment_pass(P, pool, r);
         passes.push_back(std::move(P));
@@ -998,6 +1038,7 @@ qs_status plan_opts_for(int dt, const qs_op* ops, int64_t n_ops, int fuse_k, int
     po.fuse_min = env_int("QS_FUSE_MIN", 3);
     po.dt = dt;
     po.segments = env_int("QS_REG_SEGMENTS", 1) != 0;
+    po.fuse_fp32 = env_int("QS_FUSE_FP32", 0) != 0;
     if (po.fuse_k != 0 && po.fuse_k != 4 && po.fuse_k != 5)
         return set_err(QS_ERR_ARG, "fuse_k=%d: fused blocks have 4 or 5 qubits", po.fuse_k);
     return QS_OK;

@@ -82,11 +82,12 @@ struct TileOp {
 static_assert(sizeof(TileOp) == 88, "TileOp layout");
 enum { DG_UNIFORM = 0, DG_LTARGET = 1, DG_LCONTROL = 2, DG_GENERAL = 3, DG_CT = 4 };
 
-// The tile-kernel variant a pass's op list needs: 2 with a fused matrix-core
-// block, else 1 with any k >= 3 dense op or (tiles of >= 2^10 elements) any
-// op outside a segment, else 0 (the lean kernel).  Each variant holds only
-// what its passes need, which keeps the registers of the smaller ones low; a
-// launch covering several passes takes the largest of their variants.
+// The tile-kernel variant a pass's op list needs: 3 with a fused block in
+// the FP32 matrix-core form (complex64), 2 with one in the FP64 form, else 1
+// with any k >= 3 dense op or (tiles of >= 2^10 elements) any op outside a
+// segment, else 0 (the lean kernel).  Each variant holds only what its passes
+// need, which keeps the registers of the smaller ones low; a launch covering
+// several passes takes the largest of their variants (a plan uses one form).
 inline int ops_variant(const TileOp* ops, size_t n, int m)
 {
     int v = 0;
@@ -96,7 +97,7 @@ inline int ops_variant(const TileOp* ops, size_t n, int m)
             i += (size_t)ops[i].dj;
             continue;
         }
-        if (k == TK_MFMA) return 2;
+        if (k == TK_MFMA) return ops[i].dclass == 1 ? 3 : 2;
         if (k == TK_DENSEK || m >= 10) v = 1;
     }
     return v;
@@ -118,6 +119,7 @@ struct PlanOpts {
     int L = 5;        // forced low qubits
     int fuse_k = 0;   // 0: no dense fusion; 4 or 5: matrix-core blocks
     int fuse_min = 3; // dense gates a block must absorb to be worth a fused block
+    bool fuse_fp32 = false; // complex64: FP32 matrix-core blocks (hi FP32 + lo bfloat16 parts)
     int dt = QS_C128;
     bool segments = true; // group ops into register segments (tiles of >= 2^10 elements)
 };

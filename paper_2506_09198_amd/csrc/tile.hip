@@ -71,6 +71,8 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
         if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, 1>, lim);
         if constexpr (M >= 8)
             if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, 2>, lim);
+        if constexpr (M >= 8 && sizeof(R) == 4)
+            if (e == hipSuccess) e = lds_optin((const void*)k_tile<R, M, 3>, lim);
         if constexpr (M == 11)
             if (e == hipSuccess) e = lds_optin((const void*)k_tile_w4<R, M, 0>, lim);
         if (e != hipSuccess) return e;
@@ -89,8 +91,15 @@ hipError_t launch_m(void* psi, int n, const PlanPass& pass, const TileOp* dops, 
     // segments would otherwise cost every pass registers)
     const int var = ops_variant(pass.ops.data(), pass.ops.size(), pass.m);
     const int nops = (int)pass.ops.size();
+    if constexpr (M >= 8 && sizeof(R) == 4) {
+        if (var == 3) { // FP32 matrix-core blocks
+            hipLaunchKernelGGL((k_tile<R, M, 3>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops, nops,
+                               (const double*)dmats, nt);
+            return hipGetLastError();
+        }
+    }
     if constexpr (M >= 8) {
-        if (var == 2) {
+        if (var >= 2) {
             hipLaunchKernelGGL((k_tile<R, M, 2>), dim3(g), dim3(256), lds, st, (V*)psi, ntiles, ql, ip, dops, nops,
                                (const double*)dmats, nt);
             return hipGetLastError();

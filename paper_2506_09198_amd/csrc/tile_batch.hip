@@ -203,7 +203,7 @@ static hipError_t batch_whole_r(int M, char* arena, const BatchCirc* circs, cons
 {
     switch (M) {
 #define QS_WCASE(MM) \
-    case MM: return launch_whole_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(arena, circs, list, count, passes, ops, mats, st);
+    case MM: return launch_whole_m<R, MM, (VAR >= 2 && MM < 8 ? 1 : VAR)>(arena, circs, list, count, passes, ops, mats, st);
         QS_WCASE(1) QS_WCASE(2) QS_WCASE(3) QS_WCASE(4) QS_WCASE(5) QS_WCASE(6) QS_WCASE(7) QS_WCASE(8)
         QS_WCASE(9) QS_WCASE(10) QS_WCASE(11) QS_WCASE(12) QS_WCASE(13)
 #undef QS_WCASE
@@ -217,7 +217,7 @@ static hipError_t batch_persist_r(int M, char* arena, const BatchCirc* circs, co
 {
     switch (M) {
 #define QS_PCASE(MM) \
-    case MM: return launch_persist_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(arena, circs, list, count, passes, ops, mats, st);
+    case MM: return launch_persist_m<R, MM, (VAR >= 2 && MM < 8 ? 1 : VAR)>(arena, circs, list, count, passes, ops, mats, st);
         QS_PCASE(9) QS_PCASE(10) QS_PCASE(11) QS_PCASE(12) QS_PCASE(13)
 #undef QS_PCASE
     default: return hipErrorInvalidValue;
@@ -255,7 +255,7 @@ static hipError_t batch_round_r(int M, char* arena, const BatchCirc* circs, cons
 {
     switch (M) {
 #define QS_RCASE(MM) \
-    case MM: return launch_round_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
+    case MM: return launch_round_m<R, MM, (VAR >= 2 && MM < 8 ? 1 : VAR)>(arena, circs, passes, ops, mats, entries, nentries, nblocks, st);
         QS_RCASE(9) QS_RCASE(10) QS_RCASE(11) QS_RCASE(12) QS_RCASE(13)
 #undef QS_RCASE
     default: return hipErrorInvalidValue;

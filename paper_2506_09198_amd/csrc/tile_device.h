@@ -131,6 +131,110 @@ __device__ __forceinline__ void mfma_block(typename CT<R>::V* tile, const TileOp
     }
 }
 
+// The same block on FP32 matrix cores (complex64 tiles, planner option
+// QS_FUSE_FP32).  The FP64 product A is split into hi = fl32(A) and lo =
+// bf16(A - hi): hi enters v_mfma_f32_16x16x4f32 (lane l: A[l%16][l/16],
+// B[l/16][l%16]) and lo, whose products are about 2^-24 of hi's, a separate
+// accumulator through v_mfma_f32_16x16x16bf16 (lane l: A[l%16][4(l/16)+j],
+// B[4(l/16)+j][l%16], j < 4) with the amplitudes rounded to bfloat16; both
+// accumulate rows D[4(l/16)+v][l%16] and are added once at the end.  Keeping
+// lo out of the hi accumulator matters: added there, each lo product falls
+// below the accumulator's last bit and the block acts as the FP32-rounded
+// matrix, whose rounding repeats at every application.  The bfloat16 part
+// costs about 1/16 of the FP32 part, so a block takes about half the time of
+// the FP64 form.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_rne_dev(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+template <int K, int M>
+__device__ __forceinline__ void mfma_block32(float2* tile, const TileOp& d, const double* mats, int tid)
+{
+    constexpr int DR = 2 << K;  // real dimension
+    constexpr int RB = DR / 16; // 16-row blocks
+    constexpr int KS = DR / 4;  // FP32 k steps of 4
+    constexpr int KB = KS / 4;  // bfloat16 k steps of 16
+    constexpr int NF = RB * KS;
+    constexpr int NG = 4;       // hi accumulators (over quarters of the k steps)
+    constexpr int C = 1 << (M - K);
+    constexpr int CB = C / 16;
+    static_assert(CB >= 1, "tile too small for a fused block");
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    // fragments stay in memory (read once per row block, coalesced): holding
+    // them all in registers left one wave per SIMD
+    const float* fh = (const float*)(mats + d.moff);                          // [rb * KS + ks][lane]
+    const s4_t* fl = (const s4_t*)((const char*)(mats + d.moff) + sizeof(float) * NF * 64); // [rb * KB + kb][lane]
+    uint32_t tm = 0;
+    int pos[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        pos[j] = d.p[j];
+        tm |= 1u << pos[j];
+    }
+    float* tf = (float*)tile; // component c of element e at 2 * swz(e) + c
+    for (int cb = wave; cb < CB; cb += 4) {
+        const uint32_t col = cb * 16 + li;
+        uint32_t gb = col; // insert zeros at the block qubits (ascending)
+        for (int b = 0; b < M; ++b)
+            if ((tm >> b) & 1) gb = ins0_32(gb, b);
+        auto elem = [&](int mm) {
+            uint32_t e = gb;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((mm >> j) & 1) e |= 1u << pos[j];
+            return e;
+        };
+        // NG accumulators over consecutive quarters of the k steps, summed in
+        // FP64 at the end: each sees 16 (K = 5) sequentially rounded products
+        // instead of 64, which keeps the rounding of structured inputs (a
+        // Grover state's equal amplitudes add up the same rounding error at
+        // every step) from accumulating.  Row blocks run one after another;
+        // their results are held until every row block has read the column.
+        float out[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            f4_t acc[NG], accl = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int g = 0; g < NG; ++g) acc[g] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                // real row 4ks + lk = component (lk & 1) of member 2ks + lk/2
+                const float bv = tf[2 * swz<8>(elem(2 * ks + (lk >> 1))) + (lk & 1)];
+                constexpr int per = KS / NG;
+                acc[ks / per] = __builtin_amdgcn_mfma_f32_16x16x4f32(fh[(rb * KS + ks) * 64 + lane], bv,
+                                                                     acc[ks / per], 0, 0, 0);
+            }
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                // real rows 16kb + 4lk + j: members 8kb + 2lk (j = 0, 1) and + 1 (j = 2, 3)
+                const float2 x0 = tile[swz<8>(elem(8 * kb + 2 * lk))];
+                const float2 x1 = tile[swz<8>(elem(8 * kb + 2 * lk + 1))];
+                const s4_t bl = {bf16_rne_dev(x0.x), bf16_rne_dev(x0.y), bf16_rne_dev(x1.x), bf16_rne_dev(x1.y)};
+                accl = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fl[(rb * KB + kb) * 64 + lane], bl, accl, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double s = (double)accl[v];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) s += (double)acc[g][v];
+                out[rb][v] = (float)s;
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) // real rows 16rb + 4lk + 2h (+1) = (re, im) of member 8rb + 2lk + h
+                tile[swz<8>(elem(8 * rb + 2 * lk + h))] = make_float2(out[rb][2 * h], out[rb][2 * h + 1]);
+    }
+}
+
 // ------------------------------------------------------------ segments
 //
 // A segment (TK_SEG header + dj member ops) acts on r register positions of
@@ -518,8 +622,9 @@ __device__ __forceinline__ void run_segment(typename CT<R>::V* tile, uint64_t ba
 // global index of tile element 0 (tile bits zero).  VAR selects what the
 // kernel holds (the host launches the variant a pass needs, ops_variant):
 // 0 = segments only for tiles of >= 2^10 (every op for smaller tiles),
-// 1 = every op but fused matrix-core blocks, 2 = every op (the matrix-core
-// fragments would otherwise cost every variant-1 pass registers).
+// 1 = every op but fused matrix-core blocks, 2 = every op with blocks in the
+// FP64 form, 3 = every op with blocks in the FP32 form (complex64; the
+// fragments of either form would otherwise cost every other pass registers).
 template <typename R, int M, int VAR>
 __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base, const TileOp* __restrict__ ops,
                                          int nops, const double* __restrict__ mats)
@@ -648,7 +753,13 @@ __device__ __forceinline__ void tile_ops(typename CT<R>::V* tile, uint64_t base,
                 __syncthreads();
             }
         } else if (kind == TK_MFMA) {
-            if constexpr (VAR == 2 && M >= 8) {
+            if constexpr (VAR == 3 && sizeof(R) == 4 && M >= 8) { // FP32 form (complex64)
+                if (d.k == 5) {
+                    if constexpr (M >= 9) mfma_block32<5, M>((float2*)tile, d, mats, tid);
+                } else {
+                    mfma_block32<4, M>((float2*)tile, d, mats, tid);
+                }
+            } else if constexpr (VAR >= 2 && M >= 8) {
                 if (d.k == 5) {
                     if constexpr (M >= 9) mfma_block<R, 5, M>(tile, d, mats, tid);
                 } else {
@@ -843,6 +954,8 @@ template <typename F>
 inline hipError_t dispatch_var(int dt, int var, F&& f)
 {
     auto by_r = [&](auto r) {
+        if constexpr (std::is_same<typename decltype(r)::type, float>::value)
+            if (var >= 3) return f(r, std::integral_constant<int, 3>());
         if (var >= 2) return f(r, std::integral_constant<int, 2>());
         if (var == 1) return f(r, std::integral_constant<int, 1>());
         return f(r, std::integral_constant<int, 0>());

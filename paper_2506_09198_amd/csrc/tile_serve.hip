@@ -114,7 +114,7 @@ static hipError_t serve_round_r(int M, char* pool, const char* plan, const Serve
 {
     switch (M) {
 #define QS_SRCASE(MM) \
-    case MM: return launch_serve_round_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(pool, plan, entries, nentries, nblocks, st);
+    case MM: return launch_serve_round_m<R, MM, (VAR >= 2 && MM < 8 ? 1 : VAR)>(pool, plan, entries, nentries, nblocks, st);
         QS_SRCASE(9) QS_SRCASE(10) QS_SRCASE(11) QS_SRCASE(12) QS_SRCASE(13)
 #undef QS_SRCASE
     default: return hipErrorInvalidValue;
@@ -127,7 +127,7 @@ static hipError_t serve_whole_r(int M, char* pool, const char* plan, const Serve
 {
     switch (M) {
 #define QS_SWCASE(MM) \
-    case MM: return launch_serve_whole_m<R, MM, (VAR == 2 && MM < 8 ? 1 : VAR)>(pool, plan, entries, nentries, st);
+    case MM: return launch_serve_whole_m<R, MM, (VAR >= 2 && MM < 8 ? 1 : VAR)>(pool, plan, entries, nentries, st);
         QS_SWCASE(1) QS_SWCASE(2) QS_SWCASE(3) QS_SWCASE(4) QS_SWCASE(5) QS_SWCASE(6) QS_SWCASE(7)
         QS_SWCASE(8) QS_SWCASE(9) QS_SWCASE(10) QS_SWCASE(11) QS_SWCASE(12) QS_SWCASE(13)
 #undef QS_SWCASE

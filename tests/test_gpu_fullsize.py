@@ -86,8 +86,11 @@ def test_gate_sweep_n30_c128_sampled_per_gate(qs):
     assert abs(float((psi.abs() ** 2).sum().item()) - 1.0) < 1e-10
 
 
-@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5), (2, 5)])
-def test_qft_n32_closed_form_sampled(qs, dt, fuse):
+@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5), (2, 5), (1, -5)])
+def test_qft_n32_closed_form_sampled(qs, dt, fuse, monkeypatch):
+    """fuse -5: 5-qubit blocks on FP32 matrix cores (complex64)."""
+    monkeypatch.setenv("QS_FUSE_FP32", "1" if fuse < 0 else "0")
+    fuse = abs(fuse)
     n = 32
     x = int(np.random.default_rng(6).integers(1 << n))
     c = W.qft(n, x)
@@ -161,8 +164,11 @@ def test_rqc_n32_c128_pergate_sampled_and_tile_anchors(qs):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5), (2, 5)])
-def test_rqc_n32_echo(qs, dt, fuse):
+@pytest.mark.parametrize("dt,fuse", [(2, 0), (1, 0), (1, 5), (2, 5), (1, -5)])
+def test_rqc_n32_echo(qs, dt, fuse, monkeypatch):
+    """fuse -5: 5-qubit blocks on FP32 matrix cores (complex64)."""
+    monkeypatch.setenv("QS_FUSE_FP32", "1" if fuse < 0 else "0")
+    fuse = abs(fuse)
     n = 32
     c = W.rqc_chain(n, 20, 5)
     ops, mats = c.arrays()

@@ -318,13 +318,15 @@ def test_error_leaves_state_untouched(qs):
     assert np.array_equal(s.download(), psi0)
 
 
-@pytest.mark.parametrize("dt", [1, 2])
+@pytest.mark.parametrize("dt,fp32", [(1, 0), (2, 0), (1, 1)])
 @pytest.mark.parametrize("name", list(CIRCS))
 @pytest.mark.parametrize("fk,tq,fmin", [(4, 0, 1), (5, 0, 1), (5, 9, 1), (4, 8, 2), (5, 13, 3)])
-def test_fused_mfma_blocks(qs, dt, name, fk, tq, fmin, monkeypatch):
-    """Fused dense blocks on FP64 matrix cores, both amplitude types, against
+def test_fused_mfma_blocks(qs, dt, fp32, name, fk, tq, fmin, monkeypatch):
+    """Fused dense blocks on FP64 matrix cores, both amplitude types, and
+    (complex64) on FP32 matrix cores with the hi + bfloat16 lo split, against
     the oracle (complex128 to the FP64 bar)."""
     monkeypatch.setenv("QS_FUSE_MIN", str(fmin))
+    monkeypatch.setenv("QS_FUSE_FP32", str(fp32))
     c = CIRCS[name]()
     n = c.n
     ops, mats = c.arrays()

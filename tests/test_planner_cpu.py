@@ -187,3 +187,52 @@ def test_swap_relabeling_pays_for_qft(qs):
         assert qs.qs_plan_restore(32, dt, ops, mats, remap=1) == []
     with pytest.raises(qs.QSError):
         qs.qs_plan_circuit(32, 1, ops, mats, remap=2)
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("dt", [1, 2])
+@pytest.mark.parametrize("fk,tq", [(4, 10), (5, 11), (5, 12)])
+def test_fused_blocks_encoded_match_oracle(qs, monkeypatch, fk, tq, dt, fp32):
+    """Passes with fused matrix-core blocks, their fragments decoded back into
+    matrices by the host model: the oracle's state, to FP64 rounding for the
+    FP64 fragments and to the bfloat16 remainder (about 2^-33 of each entry)
+    for the FP32 hi + lo fragments (complex64 only; complex128 keeps FP64)."""
+    from tests.tile_model import run_plan
+
+    monkeypatch.setenv("QS_FUSE_MIN", "1")
+    monkeypatch.setenv("QS_FUSE_FP32", str(fp32))
+    for c in (W.rqc_chain(14, 8, 41), W.qft(13, 77), W.grover(12, 123)):
+        ops, mats = c.arrays()
+        passes, tops, pool = qs.qs_plan_export(c.n, dt, ops, mats, tile_qubits=tq, fuse_k=fk)
+        assert any(int(t["kind"]) == 4 for t in tops), c.name
+        assert all(int(t["dclass"]) == (fp32 if dt == 1 else 0) for t in tops if int(t["kind"]) == 4)
+        restore = qs.qs_plan_restore(c.n, dt, ops, mats, tile_qubits=tq, fuse_k=fk)
+        got = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis), restore)
+        err = float(np.max(np.abs(got - oracle.run_circuit(c))))
+        assert err <= (1e-8 if (fp32 and dt == 1) else 1e-12), (c.name, err)
+
+
+def test_fp32_fragments_split_the_fp64_matrix(qs, monkeypatch):
+    """The FP32 form's hi + lo parts reproduce the FP64 form's matrix to the
+    bfloat16 remainder, and hi alone is each entry rounded to FP32."""
+    from tests.tile_model import mfma_matrix
+
+    monkeypatch.setenv("QS_FUSE_MIN", "1")
+    c = W.rqc_chain(14, 6, 5)
+    ops, mats = c.arrays()
+    monkeypatch.setenv("QS_FUSE_FP32", "0")
+    _, t64, p64 = qs.qs_plan_export(c.n, 1, ops, mats, tile_qubits=11, fuse_k=5)
+    monkeypatch.setenv("QS_FUSE_FP32", "1")
+    _, t32, p32 = qs.qs_plan_export(c.n, 1, ops, mats, tile_qubits=11, fuse_k=5)
+    m64 = [mfma_matrix(t, p64) for t in t64 if int(t["kind"]) == 4]
+    m32 = [mfma_matrix(t, p32) for t in t32 if int(t["kind"]) == 4]
+    assert len(m64) == len(m32) > 0
+    diffs = []
+    for a, b in zip(m64, m32):
+        d = float(np.max(np.abs(a - b)))
+        assert d <= 2.0 ** -32 * float(np.max(np.abs(a))), d
+        assert np.allclose(a @ a.conj().T, np.eye(a.shape[0]), atol=1e-12)
+        diffs.append(d)
+    # blocks of sqrt(X)/sqrt(Y) gates only are exact in FP32; those with
+    # sqrt(W) (entries with 1/sqrt(2)) need the lo part
+    assert max(diffs) > 0.0

@@ -5,8 +5,10 @@ complex128 state with numpy, so a CPU test can compare the result with the
 FP64 oracle and catch an encoding mistake without a GPU.  After SWAP
 relabeling the passes act on physical qubit positions, and the restoring
 involutions (one in-place exchange of bit pairs each) follow them.  It follows the
-field meanings the kernels use; it does not model rounding, thread layout
-or the matrix-core blocks.
+field meanings the kernels use; it does not model rounding or thread layout.
+Fused matrix-core blocks are decoded from their fragment layouts (FP64
+fragments, or FP32 hi + bfloat16 lo fragments) back into the dense matrix
+they carry.
 """
 import numpy as np
 
@@ -115,6 +117,43 @@ def _member(T, base, R, op, pool):
     _diag(T, tsel, f)
 
 
+def mfma_matrix(op, pool):
+    """The complex 2^k x 2^k matrix a fused matrix-core block carries, read
+    back from its fragments: the real embedding A (rows and columns
+    interleaved re/im) has A[2r][2c] = Re U[r][c] and A[2r+1][2c] = Im U[r][c].
+    FP64 form: doubles [q][lane][2], fragment f = 2q + j = rb * KS + ks holds
+    A[16rb + lane%16][4ks + lane/16].  FP32 form (dclass 1): FP32 hi
+    fragments [f][lane], then bfloat16 lo fragments
+    [rb * KB + kb][lane][4] holding A[16rb + lane%16][16kb + 4(lane/16) + j]."""
+    k = int(op["k"])
+    D = 1 << k
+    DR, RB, KS = 2 * D, (2 * D) // 16, (2 * D) // 4
+    KB, NF = KS // 4, RB * KS
+    A = np.zeros((DR, DR))
+    moff = int(op["moff"])
+    lanes = np.arange(64)
+    if int(op["dclass"]) == 0:
+        fr = pool[moff:moff + NF * 64]
+        for rb in range(RB):
+            for ks in range(KS):
+                f = rb * KS + ks
+                A[16 * rb + lanes % 16, 4 * ks + lanes // 16] = fr[((f // 2) * 64 + lanes) * 2 + f % 2]
+    else:
+        raw = np.ascontiguousarray(pool[moff:]).view(np.uint8)
+        hi = raw[:NF * 64 * 4].view(np.float32)
+        lo16 = raw[NF * 64 * 4:NF * 64 * 4 + RB * KB * 64 * 8].view(np.uint16)
+        lo = (lo16.astype(np.uint32) << 16).view(np.float32)
+        for rb in range(RB):
+            for ks in range(KS):
+                f = rb * KS + ks
+                A[16 * rb + lanes % 16, 4 * ks + lanes // 16] = hi[f * 64 + lanes]
+            for kb in range(KB):
+                for j in range(4):
+                    A[16 * rb + lanes % 16, 16 * kb + 4 * (lanes // 16) + j] += \
+                        lo[((rb * KB + kb) * 64 + lanes) * 4 + j].astype(np.float64)
+    return A[0::2, 0::2] + 1j * A[1::2, 0::2]
+
+
 def _top(T, base, op, pool):
     """An operation outside a segment, in the planner's original form."""
     E = T.shape[1]
@@ -130,6 +169,11 @@ def _top(T, base, op, pool):
             b = _bit(e, q)[None, :] if q >= 0 else _bit(base, int(op["p"][j]))[:, None]
             idx |= b << j
         _diag(T, tsel, np.where(((e & lcm) == lcv)[None, :], tab[idx], 1.0))
+        return
+    if kind == TK_MFMA:  # fused blocks carry no controls
+        tsel = np.ones(T.shape[0], dtype=bool)
+        _dense(T, tsel, lambda g: np.ones(g.shape, dtype=bool), [int(x) for x in op["p"][:k]],
+               mfma_matrix(op, pool))
         return
     if kind in (TK_DENSE1, TK_DENSE2, TK_DENSEK):
         tsel = (base & int(op["gcm"])) == int(op["gcv"])
