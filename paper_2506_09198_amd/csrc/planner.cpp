@@ -531,10 +531,12 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
             return (nd[x] & (nd[y] | dq[y])) == 0 && (nd[y] & (nd[x] | dq[x])) == 0;
         };
         // Consecutive diagonal ops (they commute) as one factor table: index
-        // bits = all r register bits (rank order), then the thread positions
-        // they use, then the positions outside the tile (targets or
-        // controls); at most 10 bits.  Each thread reads its 2^r factors
-        // as one contiguous slice.
+        // bits = the register bits the product depends on (mask rdep, rank
+        // order, compressed), then the thread positions they use, then the
+        // positions outside the tile (targets or controls); at most 10 bits
+        // before compression.  Each thread reads its 2^|rdep| factors as one
+        // contiguous slice (uniform loads when no thread position is used);
+        // dj = kt | kg << 8 | rdep << 16.
         auto diag_masks = [&](const int* gs, size_t cnt, uint32_t& tpm, uint64_t& gpm) {
             tpm = 0;
             gpm = 0;
@@ -624,14 +626,38 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 pool[off + 2 * x] = fr;
                 pool[off + 2 * x + 1] = fi;
             }
+            // Register bits the factors do not depend on (bitwise equal
+            // entries) are dropped from the index: a thread then loads one
+            // factor per combination of the others instead of one per register.
+            uint32_t rdep = 0;
+            for (int b = 0; b < r; ++b)
+                for (int x = 0; x < D; ++x)
+                    if (!((x >> b) & 1) &&
+                        (std::memcmp(&pool[off + 2 * (size_t)x], &pool[off + 2 * (size_t)(x | 1 << b)],
+                                     2 * sizeof(double)) != 0)) {
+                        rdep |= 1u << b;
+                        break;
+                    }
+            const int kr = __builtin_popcount(rdep);
+            if (kr < r) {
+                const int Kc = kr + kt + kg;
+                for (int y = 0; y < (1 << Kc); ++y) { // y <= x: compacting in place keeps unread entries
+                    int x = (y >> kr) << r;
+                    for (int b = 0, i = 0; b < r; ++b)
+                        if ((rdep >> b) & 1) x |= ((y >> i++) & 1) << b;
+                    pool[off + 2 * (size_t)y] = pool[off + 2 * (size_t)x];
+                    pool[off + 2 * (size_t)y + 1] = pool[off + 2 * (size_t)x + 1];
+                }
+                pool.resize(off + 2 * ((size_t)1 << Kc));
+            }
             TileOp t;
             std::memset(&t, 0, sizeof t);
             t.kind = TK_DIAG;
-            t.k = K;
+            t.k = kr + kt + kg;
             t.lcm = tpm; // thread positions of the index
             t.lcv = gpm; // positions outside the tile
             t.moff = off;
-            t.dj = kt | (kg << 8);
+            t.dj = kt | (kg << 8) | (int32_t)(rdep << 16);
             t.rsv = SO_DGROUP << 16;
             out.push_back(t);
             osrc.push_back(-1);

@@ -453,6 +453,31 @@ __device__ __forceinline__ void seg_block(double2 (&reg)[NR], const double* __re
     for (int r = 0; r < NR; ++r) reg[r] = o[r];
 }
 
+// A diagonal group's factors for one thread: f holds one factor per
+// combination of the register bits in RD (compressed, ascending), so the
+// thread loads 2^|RD| factors instead of one per register.
+constexpr int pext_c(int j, int m)
+{
+    int r = 0, b = 0;
+    for (int q = 0; q < 4; ++q)
+        if ((m >> q) & 1) r |= ((j >> q) & 1) << b++;
+    return r;
+}
+
+template <int NR, int RD>
+__device__ __forceinline__ void dgroup_mul(double2 (&reg)[NR], const double2* __restrict__ f)
+{
+    constexpr int C = 1 << __builtin_popcount(RD);
+    double2 F[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) F[c] = f[c];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int c = pext_c(j, RD);
+        reg[j] = cmul<double2, double>(F[c].x, F[c].y, reg[j]);
+    }
+}
+
 // One segment member, dispatched by its opcode in a single switch so the
 // register array has one join per op.
 template <int RR, int NR>
@@ -497,21 +522,34 @@ __device__ __forceinline__ void seg_op(double2 (&reg)[NR], const uint32_t (&roff
         return;
     }
     if (opc == SO_DGROUP) {
-        // factor table index: register bits, then the thread positions in
-        // lcm, then the positions outside the tile in lcv
+        // factor table index: the register bits the factors depend on (mask
+        // RD, compressed), then the thread positions in lcm, then the
+        // positions outside the tile in lcv
         const uint32_t tpm = (uint32_t)d.lcm;
         const uint64_t gpm = d.lcv;
         uint32_t ti = 0, gi = 0;
         int b = 0;
-        for (uint32_t m = tpm; m; m &= m - 1) ti |= ((eb >> __builtin_ctz(m)) & 1) << b++;
-        b = 0;
         for (uint64_t m = gpm; m; m &= m - 1) gi |= (uint32_t)((base >> __builtin_ctzll(m)) & 1) << b++;
-        const int kt = d.dj & 255;
-        const double2* f = (const double2*)u + ((((uint64_t)gi << kt) | ti) << RR);
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const double2 fj = f[j];
-            reg[j] = cmul<double2, double>(fj.x, fj.y, reg[j]);
+        const int kt = d.dj & 255, rd = (d.dj >> 16) & 15;
+        const double2* f;
+        if (kt == 0) {
+            // no thread positions: every thread of the tile multiplies by the
+            // same factors, read with uniform (scalar) loads
+            f = (const double2*)u + ((uint64_t)gi << __builtin_popcount(rd));
+        } else {
+            b = 0;
+            for (uint32_t m = tpm; m; m &= m - 1) ti |= ((eb >> __builtin_ctz(m)) & 1) << b++;
+            f = (const double2*)u + ((((uint64_t)gi << kt) | ti) << __builtin_popcount(rd));
+        }
+        switch (rd) {
+#define QS_G(RD_)                                                                                    \
+    case RD_:                                                                                        \
+        if constexpr (RD_ < NR) dgroup_mul<NR, RD_>(reg, f);                                         \
+        break;
+            QS_G(0) QS_G(1) QS_G(2) QS_G(3) QS_G(4) QS_G(5) QS_G(6) QS_G(7)
+            QS_G(8) QS_G(9) QS_G(10) QS_G(11) QS_G(12) QS_G(13) QS_G(14) QS_G(15)
+#undef QS_G
+        default: break;
         }
         return;
     }

@@ -189,6 +189,36 @@ def test_swap_relabeling_pays_for_qft(qs):
         qs.qs_plan_circuit(32, 1, ops, mats, remap=2)
 
 
+@pytest.mark.parametrize("tq", [10, 11, 12])
+def test_diag_groups_drop_unused_register_bits(qs, tq):
+    """A diagonal group's factor table leaves out the register bits its
+    product does not depend on (the QFT's phase groups mostly touch one or
+    two of them), and some groups use no thread position at all; the
+    compacted plans still give the oracle's state (host model)."""
+    from tests.tile_model import SO_DGROUP, run_plan
+
+    r = min(4, tq - 8)
+    big = W.qft(24, 4321)
+    ops, mats = big.arrays()
+    tops = qs.qs_plan_export(big.n, 2, ops, mats, tile_qubits=tq)[1]
+    groups = [t for t in tops if (int(t["rsv"]) >> 16) == SO_DGROUP]
+    assert groups
+    dep = [(int(t["dj"]) >> 16) & 15 for t in groups]
+    kt = [int(t["dj"]) & 255 for t in groups]
+    kg = [(int(t["dj"]) >> 8) & 255 for t in groups]
+    assert all(d < (1 << r) for d in dep)
+    assert any(bin(d).count("1") < r for d in dep), dep
+    assert any(k == 0 for k in kt), kt
+    for t, d, a, b in zip(groups, dep, kt, kg):
+        assert int(t["k"]) == bin(d).count("1") + a + b
+    c = W.qft(14, 4321)
+    ops, mats = c.arrays()
+    passes, tops, pool = qs.qs_plan_export(c.n, 2, ops, mats, tile_qubits=tq)
+    got = run_plan(c.n, passes, tops, pool, oracle.basis(c.n, c.init_basis),
+                   qs.qs_plan_restore(c.n, 2, ops, mats, tile_qubits=tq))
+    assert float(np.max(np.abs(got - oracle.run_circuit(c)))) <= 1e-12
+
+
 @pytest.mark.parametrize("fp32", [0, 1])
 @pytest.mark.parametrize("dt", [1, 2])
 @pytest.mark.parametrize("fk,tq", [(4, 10), (5, 11), (5, 12)])

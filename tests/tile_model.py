@@ -76,13 +76,15 @@ def _member(T, base, R, op, pool):
     if opc == SO_DGROUP:
         tp = [q for q in range(32) if (int(op["lcm"]) >> q) & 1]
         gp = [q for q in range(64) if (int(op["lcv"]) >> q) & 1]
+        rdep = (int(op["dj"]) >> 16) & 15  # register bits the factors depend on
+        rq = [q for b, q in enumerate(R) if (rdep >> b) & 1]
         idx = np.zeros((T.shape[0], E), dtype=np.int64)
-        for b, q in enumerate(R):
+        for b, q in enumerate(rq):
             idx |= _bit(e, q)[None, :] << b
         for b, q in enumerate(tp):
-            idx |= _bit(e, q)[None, :] << (len(R) + b)
+            idx |= _bit(e, q)[None, :] << (len(rq) + b)
         for b, q in enumerate(gp):
-            idx |= _bit(base, q)[:, None] << (len(R) + len(tp) + b)
+            idx |= _bit(base, q)[:, None] << (len(rq) + len(tp) + b)
         _diag(T, tsel, tab[idx])
         return
     if opc == SO_DG:
