@@ -531,13 +531,17 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
             return (nd[x] & (nd[y] | dq[y])) == 0 && (nd[y] & (nd[x] | dq[x])) == 0;
         };
         // Consecutive diagonal ops (they commute) as one factor table: index
-        // bits = the register bits the product depends on (mask rdep, rank
-        // order, compressed), then the thread positions they use, then the
-        // positions outside the tile (targets or controls); at most 10 bits
-        // before compression.  Each thread reads its 2^|rdep| factors as one
-        // contiguous slice (uniform loads when no thread position is used);
-        // dj = kt | kg << 8 | rdep << 16.
-        auto diag_masks = [&](const int* gs, size_t cnt, uint32_t& tpm, uint64_t& gpm) {
+        // bits = the register bits the product depends on (rank mask rdep,
+        // ascending, compressed), then the thread positions they use, then
+        // the positions outside the tile (targets or controls); at most
+        // kGroupBits bits, counting the register ranks the ops touch.  Each
+        // thread reads its 2^|rdep| factors as one contiguous slice (uniform
+        // loads when no thread position is used); dj = kt | kg << 8 | rdep << 16.
+        // 12 bits gave the 32-qubit QFT 15 % fewer groups but tripled its
+        // planning time (the tables are built entry by entry on the host).
+        constexpr int kGroupBits = 10;
+        auto diag_masks = [&](const int* gs, size_t cnt, uint32_t& rrm, uint32_t& tpm, uint64_t& gpm) {
+            rrm = 0;
             tpm = 0;
             gpm = 0;
             for (size_t i = 0; i < cnt; ++i) {
@@ -545,37 +549,28 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 for (int j = 0; j < t.k; ++j) {
                     if (t.lp[j] >= 0) {
                         if (!((R >> t.lp[j]) & 1)) tpm |= 1u << t.lp[j];
+                        else rrm |= 1u << rank[t.lp[j]];
                     } else {
                         gpm |= 1ull << t.p[j];
                     }
                 }
+                for (uint32_t m = (uint32_t)t.lcm & R; m; m &= m - 1) rrm |= 1u << rank[__builtin_ctz(m)];
                 tpm |= (uint32_t)t.lcm & ~R;
                 gpm |= t.gcm;
             }
         };
         auto diag_group = [&](const int* gs, size_t cnt) -> bool {
-            uint32_t tpm = 0;
-            uint64_t gpm = 0;
-            for (size_t i = 0; i < cnt; ++i) {
-                const TileOp& t = P.ops[gs[i]];
-                for (int j = 0; j < t.k; ++j) {
-                    if (t.lp[j] >= 0) {
-                        if (!((R >> t.lp[j]) & 1)) tpm |= 1u << t.lp[j];
-                    } else {
-                        gpm |= 1ull << t.p[j];
-                    }
-                }
-                tpm |= (uint32_t)t.lcm & ~R;
-                gpm |= t.gcm;
-            }
-            const int kt = __builtin_popcount(tpm), kg = __builtin_popcountll(gpm);
-            if (r + kt + kg > 10) return false;
+            uint32_t rrm, tpm;
+            uint64_t gpm;
+            diag_masks(gs, cnt, rrm, tpm, gpm);
+            const int kr0 = __builtin_popcount(rrm), kt = __builtin_popcount(tpm), kg = __builtin_popcountll(gpm);
+            if (kr0 + kt + kg > kGroupBits) return false;
             int tpos[32], gpos[64];
             for (int i = 0, q = 0; q < 32; ++q)
                 if ((tpm >> q) & 1) tpos[i++] = q;
             for (int i = 0, q = 0; q < 64; ++q)
                 if ((gpm >> q) & 1) gpos[i++] = q;
-            const int K = r + kt + kg, D = 1 << K;
+            const int K = kr0 + kt + kg, D = 1 << K;
             size_t off = pool.size();
             if (off & 1) pool.push_back(0.0), ++off; // 16-byte aligned factors
             pool.resize(off + 2 * (size_t)D);
@@ -590,9 +585,10 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
             int xbit_local[32], xbit_glob[64];
             for (int q = 0; q < 32; ++q) xbit_local[q] = -1;
             for (int q = 0; q < 64; ++q) xbit_glob[q] = -1;
-            for (int b = 0; b < r; ++b) xbit_local[h.p[b]] = b;
-            for (int b = 0; b < kt; ++b) xbit_local[tpos[b]] = r + b;
-            for (int b = 0; b < kg; ++b) xbit_glob[gpos[b]] = r + kt + b;
+            for (int b = 0, i = 0; b < r; ++b)
+                if ((rrm >> b) & 1) xbit_local[h.p[b]] = i++;
+            for (int b = 0; b < kt; ++b) xbit_local[tpos[b]] = kr0 + b;
+            for (int b = 0; b < kg; ++b) xbit_glob[gpos[b]] = kr0 + kt + b;
             for (size_t i = 0; i < cnt; ++i) {
                 const TileOp& t = P.ops[gs[i]];
                 Xop& x = xo[i];
@@ -627,29 +623,32 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 pool[off + 2 * x + 1] = fi;
             }
             // Register bits the factors do not depend on (bitwise equal
-            // entries) are dropped from the index: a thread then loads one
-            // factor per combination of the others instead of one per register.
-            uint32_t rdep = 0;
-            for (int b = 0; b < r; ++b)
+            // entries; a CZ pair can cancel) are dropped from the index as well.
+            uint32_t dep = 0; // over the kr0 compressed register bits
+            for (int b = 0; b < kr0; ++b)
                 for (int x = 0; x < D; ++x)
                     if (!((x >> b) & 1) &&
                         (std::memcmp(&pool[off + 2 * (size_t)x], &pool[off + 2 * (size_t)(x | 1 << b)],
                                      2 * sizeof(double)) != 0)) {
-                        rdep |= 1u << b;
+                        dep |= 1u << b;
                         break;
                     }
-            const int kr = __builtin_popcount(rdep);
-            if (kr < r) {
+            const int kr = __builtin_popcount(dep);
+            if (kr < kr0) {
                 const int Kc = kr + kt + kg;
                 for (int y = 0; y < (1 << Kc); ++y) { // y <= x: compacting in place keeps unread entries
-                    int x = (y >> kr) << r;
-                    for (int b = 0, i = 0; b < r; ++b)
-                        if ((rdep >> b) & 1) x |= ((y >> i++) & 1) << b;
+                    int x = (y >> kr) << kr0;
+                    for (int b = 0, i = 0; b < kr0; ++b)
+                        if ((dep >> b) & 1) x |= ((y >> i++) & 1) << b;
                     pool[off + 2 * (size_t)y] = pool[off + 2 * (size_t)x];
                     pool[off + 2 * (size_t)y + 1] = pool[off + 2 * (size_t)x + 1];
                 }
                 pool.resize(off + 2 * ((size_t)1 << Kc));
             }
+            uint32_t rdep = 0; // rank mask
+            for (int b = 0, i = 0; b < r; ++b)
+                if ((rrm >> b) & 1)
+                    if ((dep >> i++) & 1) rdep |= 1u << b;
             TileOp t;
             std::memset(&t, 0, sizeof t);
             t.kind = TK_DIAG;
@@ -701,13 +700,16 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 // the longest run of diagonal ops from i whose factor table
                 // fits (at most 10 index bits)
                 size_t j = i;
-                uint32_t tpm = 0;
+                uint32_t rrm = 0, tpm = 0;
                 uint64_t gpm = 0;
                 while (j < pend.size() && P.ops[pend[j]].kind == TK_DIAG) {
-                    uint32_t t2;
+                    uint32_t r2, t2;
                     uint64_t g2;
-                    diag_masks(pend.data() + j, 1, t2, g2);
-                    if (r + __builtin_popcount(tpm | t2) + __builtin_popcountll(gpm | g2) > 10) break;
+                    diag_masks(pend.data() + j, 1, r2, t2, g2);
+                    if (__builtin_popcount(rrm | r2) + __builtin_popcount(tpm | t2) + __builtin_popcountll(gpm | g2) >
+                        kGroupBits)
+                        break;
+                    rrm |= r2;
                     tpm |= t2;
                     gpm |= g2;
                     ++j;
