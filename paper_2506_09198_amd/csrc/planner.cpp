@@ -537,9 +537,7 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
         // kGroupBits bits, counting the register ranks the ops touch.  Each
         // thread reads its 2^|rdep| factors as one contiguous slice (uniform
         // loads when no thread position is used); dj = kt | kg << 8 | rdep << 16.
-        // 12 bits gave the 32-qubit QFT 15 % fewer groups but tripled its
-        // planning time (the tables are built entry by entry on the host).
-        constexpr int kGroupBits = 10;
+        constexpr int kGroupBits = 12; // 64 KiB tables; a tile reads 2^(|rdep| + kt) entries
         auto diag_masks = [&](const int* gs, size_t cnt, uint32_t& rrm, uint32_t& tpm, uint64_t& gpm) {
             rrm = 0;
             tpm = 0;
@@ -579,7 +577,6 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                 int tb[6];
                 int k;
                 uint32_t cm, cv;
-                const double* T;
             };
             std::vector<Xop> xo(cnt);
             int xbit_local[32], xbit_glob[64];
@@ -605,22 +602,36 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
                         x.cm |= 1u << xbit_glob[q];
                         if ((t.gcv >> q) & 1) x.cv |= 1u << xbit_glob[q];
                     }
-                x.T = nullptr;
             }
+            // The product over the ops, in their order, entry by entry; an op
+            // visits only the entries where its factor is not exactly 1 (its
+            // controls pass and its targets spell a factor other than 1):
+            // a controlled phase touches a quarter of the table.
+            double* F = pool.data() + off;
             for (int x = 0; x < D; ++x) {
-                double fr = 1.0, fi = 0.0;
-                for (size_t i = 0; i < cnt; ++i) {
-                    const Xop& o = xo[i];
-                    if (((uint32_t)x & o.cm) != o.cv) continue;
-                    int idx = 0;
-                    for (int j = 0; j < o.k; ++j) idx |= ((x >> o.tb[j]) & 1) << j;
-                    const double* T = pool.data() + P.ops[gs[i]].moff + 2 * idx;
-                    const double nr = fr * T[0] - fi * T[1], ni = fr * T[1] + fi * T[0];
-                    fr = nr;
-                    fi = ni;
+                F[2 * x] = 1.0;
+                F[2 * x + 1] = 0.0;
+            }
+            for (size_t i = 0; i < cnt; ++i) {
+                const Xop& o = xo[i];
+                for (int v = 0; v < (1 << o.k); ++v) {
+                    const double* T = pool.data() + P.ops[gs[i]].moff + 2 * v;
+                    if (T[0] == 1.0 && T[1] == 0.0) continue;
+                    uint32_t fix = o.cm, val = o.cv;
+                    for (int j = 0; j < o.k; ++j) {
+                        fix |= 1u << o.tb[j];
+                        if ((v >> j) & 1) val |= 1u << o.tb[j];
+                    }
+                    const uint32_t fr_bits = (uint32_t)(D - 1) & ~fix; // free index bits
+                    uint32_t y = 0;
+                    do {
+                        double* e = F + 2 * (size_t)(y | val);
+                        const double nr = e[0] * T[0] - e[1] * T[1], ni = e[0] * T[1] + e[1] * T[0];
+                        e[0] = nr;
+                        e[1] = ni;
+                        y = (y - fr_bits) & fr_bits;
+                    } while (y != 0);
                 }
-                pool[off + 2 * x] = fr;
-                pool[off + 2 * x + 1] = fi;
             }
             // Register bits the factors do not depend on (bitwise equal
             // entries; a CZ pair can cancel) are dropped from the index as well.
@@ -753,7 +764,7 @@ static bool is_diagonal(const double* U, int nt)
 }
 
 void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po,
-                  std::vector<PlanPass>& passes, std::vector<double>& pool)
+                  std::vector<PlanPass>& passes, std::vector<double>& pool, bool encode)
 {
     const int m = std::min(std::max(po.m, 1), n);
     const int Lf = std::min(std::max(po.L, 0), m);
@@ -842,10 +853,10 @@ void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, co
             P.gates += 1;
             P.updates += 1ull << (n - __builtin_popcountll(o.cmask));
         }
-        if ((po.fuse_k == 4 || po.fuse_k == 5) && m >= po.fuse_k + 4)
+        if (encode && (po.fuse_k == 4 || po.fuse_k == 5) && m >= po.fuse_k + 4)
             fuse_pass(P, pool, po.fuse_k, po.fuse_min, po.fuse_fp32 && po.dt == QS_C64);
         const int r = po.segments ? seg_reg_qubits(po.dt, m) : 0;
-        if (r > 0) segment_pass(P, pool, r);
+        if (encode && r > 0) segment_pass(P, pool, r);
         passes.push_back(std::move(P));
         items.clear();
         qmask = 0;
@@ -1010,23 +1021,35 @@ void plan_circuit_remap(int n, const qs_op* ops, int64_t n_ops, const double* ma
                         std::vector<PlanPass>& passes, std::vector<double>& pool, Remap& r)
 {
     r.nrestore = 0;
-    plan_circuit(n, ops, n_ops, mats, po, passes, pool);
     // QS_REMAP_ALWAYS=1 relabels whenever there is a SWAP gate (for tests)
     const bool always = env_int("QS_REMAP_ALWAYS", 0) != 0;
     Remap rr;
-    if (remap != 0 || (passes.size() <= 1 && !always) || !remap_swaps(n, ops, n_ops, mats, rr)) return;
-    std::vector<PlanPass> p2;
-    std::vector<double> pool2;
-    if (!rr.ops.empty()) plan_circuit(n, rr.ops.data(), (int64_t)rr.ops.size(), mats, po, p2, pool2);
-    if (!always && (double)p2.size() + 0.5 * rr.nrestore >= (double)passes.size()) return;
-    for (PlanPass& P : p2) {
+    if (remap != 0 || !remap_swaps(n, ops, n_ops, mats, rr)) {
+        plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+        return;
+    }
+    // Compare the pass counts of both plans before encoding either: the
+    // encoding (fused blocks, segments, diagonal factor tables) is most of
+    // the planning time and only the chosen plan needs it.
+    if (!always) {
+        std::vector<PlanPass> p1, p2;
+        std::vector<double> pool1, pool2;
+        plan_circuit(n, ops, n_ops, mats, po, p1, pool1, false);
+        if (!rr.ops.empty()) plan_circuit(n, rr.ops.data(), (int64_t)rr.ops.size(), mats, po, p2, pool2, false);
+        if (p1.size() <= 1 || (double)p2.size() + 0.5 * rr.nrestore >= (double)p1.size()) {
+            plan_circuit(n, ops, n_ops, mats, po, passes, pool);
+            return;
+        }
+    }
+    passes.clear();
+    pool.clear();
+    if (!rr.ops.empty()) plan_circuit(n, rr.ops.data(), (int64_t)rr.ops.size(), mats, po, passes, pool);
+    for (PlanPass& P : passes) {
         for (int64_t& g : P.src)
             if (g >= 0) g = rr.src[(size_t)g];
         for (int64_t& g : P.order)
             if (g >= 0) g = rr.src[(size_t)g];
     }
-    passes.swap(p2);
-    pool.swap(pool2);
     r = std::move(rr);
 }
 

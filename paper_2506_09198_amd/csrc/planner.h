@@ -126,8 +126,11 @@ struct PlanOpts {
 
 // Plan in FP64.  `mats_out` receives the pool the passes' moff index (FP64,
 // interleaved complex); the executor converts it to the state's real type.
+// With encode = false the passes are partitioned but not encoded (no fused
+// blocks or register segments): the pass count is the same, for comparing
+// plans cheaply.
 void plan_circuit(int n, const qs_op* ops, int64_t n_ops, const double* mats, const PlanOpts& po,
-                  std::vector<PlanPass>& passes, std::vector<double>& mats_out);
+                  std::vector<PlanPass>& passes, std::vector<double>& mats_out, bool encode = true);
 
 // Qubit relabeling.  An uncontrolled SWAP gate exchanges two qubits' values;
 // instead of moving amplitudes, the planner can record that the two logical
