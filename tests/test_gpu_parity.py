@@ -178,6 +178,73 @@ def test_circuits(qs, dt, name, mode, tq):
     _check(s.download(), want, dt, f"{name} mode={mode} tq={tq}")
 
 
+def _phase_circuit(n, count, seed):
+    """Random controlled phases, CZ and one-qubit diagonals (some with a
+    further control): every form a diagonal factor group can take."""
+    rng = np.random.default_rng(seed)
+    c = W.Circuit(n, f"phases{n}")
+    for q in range(n):
+        c.g1(q, W.H)
+    for _ in range(count):
+        a, b, e = (int(x) for x in rng.choice(n, 3, replace=False))
+        kind = int(rng.integers(4))
+        if kind == 0:
+            c.g1(a, W.phase(float(rng.uniform(0, 2 * np.pi))), controls=(b,))
+        elif kind == 1:
+            c.g1(a, W.Z, controls=(b,))
+        elif kind == 2:
+            c.g1(a, np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, 2))))
+        else:
+            c.g1(a, W.phase(float(rng.uniform(0, 2 * np.pi))), controls=(b, e))
+    return c
+
+
+def _groups(qs, c, dt, tq):
+    """(thread positions, register bits kept) of every diagonal factor group
+    in the plan."""
+    from tests.tile_model import SO_DGROUP
+
+    ops, mats = c.arrays()
+    tops = qs.qs_plan_export(c.n, dt, ops, mats, tile_qubits=tq)[1]
+    return [(int(t["dj"]) & 255, bin((int(t["dj"]) >> 16) & 15).count("1")) for t in tops
+            if (int(t["rsv"]) >> 16) == SO_DGROUP]
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("tq", [10, 11, 12])
+def test_diag_groups_against_oracle(qs, dt, tq):
+    """Diagonal factor groups gathered per thread, with factors that skip
+    register bits, against the oracle (random phases, CZ and controlled
+    phases on 17 qubits)."""
+    c = _phase_circuit(17, 400, 6)
+    g = _groups(qs, c, dt, tq)
+    assert any(k > 0 for k, _ in g) and any(d < min(4, tq - 8) for _, d in g), g
+    ops, mats = c.arrays()
+    psi0 = _rand(c.n, 21)
+    want = oracle.run(c.n, ops, mats, psi0)
+    s = _state(qs, c.n, dt, psi0)
+    s.run(ops, mats, mode=0, tile_qubits=tq)
+    _check(s.download(), want, dt, f"phases tq={tq}")
+
+
+@pytest.mark.parametrize("dt", DTS)
+@pytest.mark.parametrize("tq", [10, 11, 12])
+def test_diag_groups_uniform_qft24(qs, dt, tq):
+    """At 24 qubits the QFT's plan has groups with no thread position (read
+    with uniform loads) beside per-thread ones: closed form."""
+    n, x = 24, 9876543
+    c = W.qft(n, x)
+    g = _groups(qs, c, dt, tq)
+    assert any(k == 0 for k, _ in g) and any(k > 0 for k, _ in g), g
+    ops, mats = c.arrays()
+    s = _state(qs, n, dt, basis=x)
+    s.run(ops, mats, mode=0, tile_qubits=tq)
+    N = 1 << n
+    y = np.arange(N, dtype=np.int64)
+    want = np.exp(2j * np.pi * ((x * y) % N) / N) / math.sqrt(N)
+    _check(s.download(), want, dt, f"qft24 tq={tq}")
+
+
 def test_config1_parity_and_determinism(qs):
     c = W.random_u3_cnot(12, 200, seed=1)
     ops, mats = c.arrays()
