@@ -43,6 +43,7 @@ template <typename V, int K>
 __global__ void __launch_bounds__(256) k_bit_involution(V* __restrict__ psi, InvArgs a)
 {
     __shared__ V la[1 << (2 * K)], lb[1 << (2 * K)];
+    constexpr int PT = ((1 << (2 * K)) + 255) / 256; // elements per thread at most (|T| <= 2K)
     const int E = 1 << a.nt;
     auto deposit = [&](int u) {
         uint64_t off = (uint64_t)(u & ((1 << K) - 1)) & (((uint64_t)1 << a.nt) - 1);
@@ -60,17 +61,33 @@ __global__ void __launch_bounds__(256) k_bit_involution(V* __restrict__ psi, Inv
         for (int i = 0; i < a.np; ++i)
             if (((t >> a.pa[i]) ^ (t >> a.pb[i])) & 1) t2 ^= (1ull << a.pa[i]) | (1ull << a.pb[i]);
         if (t2 < t) continue; // the block of tile t2 does this pair (same decision for the whole block)
-        for (int u = threadIdx.x; u < E; u += 256) {
-            const uint64_t off = deposit(u);
-            la[u] = psi[t | off];
-            if (t2 != t) lb[u] = psi[t2 | off];
+        // every load of the pair is issued before the first LDS store, so a
+        // thread keeps all its reads in flight at once; each amplitude is
+        // read and written once, so loads and stores bypass the caches
+        V ra[PT], rb[PT];
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int u = threadIdx.x + 256 * i;
+            if (u < E) {
+                const uint64_t off = deposit(u);
+                ra[i] = gld<true>(psi + (t | off));
+                if (t2 != t) rb[i] = gld<true>(psi + (t2 | off));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int u = threadIdx.x + 256 * i;
+            if (u < E) {
+                la[u] = ra[i];
+                if (t2 != t) lb[u] = rb[i];
+            }
         }
         __syncthreads();
         for (int u = threadIdx.x; u < E; u += 256) {
             const uint64_t off = deposit(u);
             const int su = sigma_in(u);
-            psi[t2 | off] = la[su];
-            if (t2 != t) psi[t | off] = lb[su];
+            gst<true>(psi + (t2 | off), la[su]);
+            if (t2 != t) gst<true>(psi + (t | off), lb[su]);
         }
         __syncthreads();
     }
@@ -106,11 +123,13 @@ hipError_t launch_bit_involution(void* psi, int dt, int n, const int* tau, hipSt
     InvArgs a;
     std::memset(&a, 0, sizeof a);
     // Runs of 2^Kr amplitudes; both tiles of a pair sit in LDS.  Measured at
-    // 30 qubits (QFT restore): 256-byte runs are best -- Kr = 5 for complex64
-    // (2.7 TB/s; Kr = 6 needs 64 KiB of LDS per block and drops to 1.1),
-    // Kr = 4 for complex128 (3.3 TB/s against 3.0 at Kr = 5).
+    // 30 qubits (QFT restore), with the batched non-temporal loads and stores:
+    // Kr = 5 for both types -- complex64 3.2 TB/s (256-byte runs; Kr = 6 needs
+    // 64 KiB of LDS per block and drops to 1.7), complex128 4.0 TB/s (512-byte
+    // runs; 3.4 at Kr = 4; with cached accesses Kr = 5 fell to 1.9).  Issuing
+    // the stores in one burst as well (LDS reads first) lost 10 %.
     const int kenv = (int)tun(T_PERM_RUN);
-    const int Kr = (kenv >= 4 && kenv <= (dt == QS_C128 ? 5 : 6)) ? kenv : (dt == QS_C128 ? 4 : 5);
+    const int Kr = (kenv >= 4 && kenv <= (dt == QS_C128 ? 5 : 6)) ? kenv : 5;
     const int K = n < Kr ? n : Kr;
     uint64_t T = 0;
     for (int p = 0; p < K; ++p) T |= (1ull << p) | (1ull << tau[p]);
