@@ -709,7 +709,7 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
             }
             for (size_t i = 0; i < pend.size();) {
                 // the longest run of diagonal ops from i whose factor table
-                // fits (at most 10 index bits)
+                // fits (at most kGroupBits index bits)
                 size_t j = i;
                 uint32_t rrm = 0, tpm = 0;
                 uint64_t gpm = 0;
