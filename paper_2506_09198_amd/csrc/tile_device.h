@@ -478,6 +478,21 @@ __device__ __forceinline__ void dgroup_mul(double2 (&reg)[NR], const double2* __
     }
 }
 
+template <int NR>
+__device__ __forceinline__ void dgroup_apply(double2 (&reg)[NR], const double2* __restrict__ f, int rd)
+{
+    switch (rd) {
+#define QS_G(RD_)                                                                                    \
+    case RD_:                                                                                        \
+        if constexpr (RD_ < NR) dgroup_mul<NR, RD_>(reg, f);                                         \
+        break;
+        QS_G(0) QS_G(1) QS_G(2) QS_G(3) QS_G(4) QS_G(5) QS_G(6) QS_G(7)
+        QS_G(8) QS_G(9) QS_G(10) QS_G(11) QS_G(12) QS_G(13) QS_G(14) QS_G(15)
+#undef QS_G
+    default: break;
+    }
+}
+
 // One segment member, dispatched by its opcode in a single switch so the
 // register array has one join per op.
 template <int RR, int NR>
@@ -531,26 +546,16 @@ __device__ __forceinline__ void seg_op(double2 (&reg)[NR], const uint32_t (&roff
         int b = 0;
         for (uint64_t m = gpm; m; m &= m - 1) gi |= (uint32_t)((base >> __builtin_ctzll(m)) & 1) << b++;
         const int kt = d.dj & 255, rd = (d.dj >> 16) & 15;
-        const double2* f;
         if (kt == 0) {
             // no thread positions: every thread of the tile multiplies by the
-            // same factors, read with uniform (scalar) loads
-            f = (const double2*)u + ((uint64_t)gi << __builtin_popcount(rd));
-        } else {
-            b = 0;
-            for (uint32_t m = tpm; m; m &= m - 1) ti |= ((eb >> __builtin_ctz(m)) & 1) << b++;
-            f = (const double2*)u + ((((uint64_t)gi << kt) | ti) << __builtin_popcount(rd));
+            // same factors, read with uniform (scalar) loads -- a call site of
+            // its own, so the pointer stays uniform
+            dgroup_apply<NR>(reg, (const double2*)u + ((uint64_t)gi << __builtin_popcount(rd)), rd);
+            return;
         }
-        switch (rd) {
-#define QS_G(RD_)                                                                                    \
-    case RD_:                                                                                        \
-        if constexpr (RD_ < NR) dgroup_mul<NR, RD_>(reg, f);                                         \
-        break;
-            QS_G(0) QS_G(1) QS_G(2) QS_G(3) QS_G(4) QS_G(5) QS_G(6) QS_G(7)
-            QS_G(8) QS_G(9) QS_G(10) QS_G(11) QS_G(12) QS_G(13) QS_G(14) QS_G(15)
-#undef QS_G
-        default: break;
-        }
+        b = 0;
+        for (uint32_t m = tpm; m; m &= m - 1) ti |= ((eb >> __builtin_ctz(m)) & 1) << b++;
+        dgroup_apply<NR>(reg, (const double2*)u + ((((uint64_t)gi << kt) | ti) << __builtin_popcount(rd)), rd);
         return;
     }
     double2 F[4];
