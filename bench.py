@@ -647,7 +647,9 @@ def run_circuits(a, qs, torch, W):
         D = kinds["tile"]
         tf = fpa * (1 << n) / (D["avg_ms"] * 1e-3) / 1e12
         rl = {"bound": "alu", "kernel": "tile", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-              "frac": tf / PEAK_FP64_TFLOPS, "traffic": None,
+              "frac": tf / PEAK_FP64_TFLOPS,
+              "traffic": measured_traffic("tile", f"tile_circuits_n{n}_c64", TILE_SRCS),
+              "traffic_unit": "HBM bytes per tile pass (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
               "flops_per_amp_per_pass": fpa, "hbm_gbs_algorithmic": rl["achieved"],
               "hbm_frac": rl["achieved"] / PEAK_HBM_GBS,
               "note": "FP64 flops executed per amplitude per pass from profiles/tile_circuits_n30_c64_counters.txt "
@@ -987,6 +989,8 @@ def run_serve(a, qs, torch, W):
 
 GATE_SRCS = ("paper_2506_09198_amd/csrc/gates.hip", "paper_2506_09198_amd/csrc/device_common.h")
 DIAG_SRCS = ("paper_2506_09198_amd/csrc/diag.hip", "paper_2506_09198_amd/csrc/device_common.h")
+TILE_SRCS = ("paper_2506_09198_amd/csrc/tile.hip", "paper_2506_09198_amd/csrc/tile_device.h",
+             "paper_2506_09198_amd/csrc/planner.cpp")
 BATCH_SRCS = ("paper_2506_09198_amd/csrc/tile_batch.hip", "paper_2506_09198_amd/csrc/tile_device.h",
               "paper_2506_09198_amd/csrc/planner.cpp", "paper_2506_09198_amd/csrc/batch.cpp")
 
