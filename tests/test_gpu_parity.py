@@ -216,7 +216,7 @@ def test_diag_groups_against_oracle(qs, dt, tq):
     """Diagonal factor groups gathered per thread, with factors that skip
     register bits, against the oracle (random phases, CZ and controlled
     phases on 17 qubits)."""
-    c = _phase_circuit(17, 400, 6)
+    c = _phase_circuit(17, 400, 7)
     g = _groups(qs, c, dt, tq)
     assert any(k > 0 for k, _ in g) and any(d < min(4, tq - 8) for _, d in g), g
     ops, mats = c.arrays()
@@ -229,10 +229,10 @@ def test_diag_groups_against_oracle(qs, dt, tq):
 
 @pytest.mark.parametrize("dt", DTS)
 @pytest.mark.parametrize("tq", [10, 11, 12])
-def test_diag_groups_uniform_qft24(qs, dt, tq):
-    """At 24 qubits the QFT's plan has groups with no thread position (read
+def test_diag_groups_uniform_qft25(qs, dt, tq):
+    """At 25 qubits the QFT's plan has groups with no thread position (read
     with uniform loads) beside per-thread ones: closed form."""
-    n, x = 24, 9876543
+    n, x = 25, 9876543
     c = W.qft(n, x)
     g = _groups(qs, c, dt, tq)
     assert any(k == 0 for k, _ in g) and any(k > 0 for k, _ in g), g
@@ -242,7 +242,7 @@ def test_diag_groups_uniform_qft24(qs, dt, tq):
     N = 1 << n
     y = np.arange(N, dtype=np.int64)
     want = np.exp(2j * np.pi * ((x * y) % N) / N) / math.sqrt(N)
-    _check(s.download(), want, dt, f"qft24 tq={tq}")
+    _check(s.download(), want, dt, f"qft25 tq={tq}")
 
 
 def test_config1_parity_and_determinism(qs):

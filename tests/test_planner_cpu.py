@@ -198,7 +198,7 @@ def test_diag_groups_drop_unused_register_bits(qs, tq):
     from tests.tile_model import SO_DGROUP, run_plan
 
     r = min(4, tq - 8)
-    big = W.qft(24, 4321)
+    big = W.qft(25, 4321)
     ops, mats = big.arrays()
     tops = qs.qs_plan_export(big.n, 2, ops, mats, tile_qubits=tq)[1]
     groups = [t for t in tops if (int(t["rsv"]) >> 16) == SO_DGROUP]
