@@ -537,7 +537,7 @@ static void segment_pass(PlanPass& P, std::vector<double>& pool, int r)
         // kGroupBits bits, counting the register ranks the ops touch.  Each
         // thread reads its 2^|rdep| factors as one contiguous slice (uniform
         // loads when no thread position is used); dj = kt | kg << 8 | rdep << 16.
-        constexpr int kGroupBits = 14; // 256 KiB tables; a tile reads 2^(|rdep| + kt) entries
+        constexpr int kGroupBits = 12; // 64 KiB tables; a tile reads 2^(|rdep| + kt) entries
         auto diag_masks = [&](const int* gs, size_t cnt, uint32_t& rrm, uint32_t& tpm, uint64_t& gpm) {
             rrm = 0;
             tpm = 0;
